@@ -1,0 +1,195 @@
+"""CPU oracle for the trapezoidal transcription NLP -- test infrastructure only.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  It shares no code with the GPU library: the C source in this
+folder is compiled with gcc (never hipcc) into ``liboracle.so`` and loaded
+here with ctypes.  ``defn.py`` holds an independent, dtype-generic definition
+of the objective and constraints used to pin the C oracle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ocp_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+          "-fPIC", "-shared", "-Wall", "-Wextra"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc; returns the path of the shared library."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Oracle:
+    """One loaded copy of the oracle library (the default one, or a variant
+    compiled from an edited source in a mutation test)."""
+
+    def __init__(self, path: str = LIB):
+        self.path = path
+        self._L = None
+
+    @property
+    def L(self):
+        if self._L is None:
+            if self.path == LIB and not os.path.exists(LIB):
+                build(force=False)
+            L = ctypes.CDLL(self.path)
+            i64, i32, dbl, ptr = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+            L.orc_sizes.argtypes = [i64, i32, i32, ptr]
+            L.orc_obj.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr]
+            L.orc_grad.argtypes = [i64, i32, i32, ptr, ptr, ptr, i64, i64, ptr, ptr]
+            L.orc_cons.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, i64, i64, ptr, ptr]
+            L.orc_jac.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, i64, i64, ptr, ptr]
+            L.orc_hess.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, dbl,
+                                   i64, i64, ptr, ptr]
+            L.orc_pattern.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr]
+            L.orc_kkt.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, ptr, ptr]
+            L.orc_assemble.argtypes = [i64, i64, ptr, i64, ptr, ptr, i64, ptr, ptr, ptr, ptr]
+            L.orc_set_threads.argtypes = [i32]
+            L.orc_set_threads.restype = None
+            L.orc_get_threads.restype = i32
+            self._L = L
+        return self._L
+
+    def set_threads(self, t: int) -> None:
+        self.L.orc_set_threads(int(t))
+
+    def get_threads(self) -> int:
+        return int(self.L.orc_get_threads())
+
+    def sizes(self, N, n, m) -> dict:
+        out = np.zeros(8, np.int64)
+        _check(self.L.orc_sizes(N, n, m, _p(out)), "sizes")
+        keys = ["nvar", "ncon", "nnzj", "nnzh", "dim", "npair", "T", "S"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def obj(self, inst):
+        """(f, mu_f)."""
+        out = np.zeros(2)
+        _check(self.L.orc_obj(inst.N, inst.n, inst.m, _p(_d(inst.q)), _p(_d(inst.r)),
+                              _p(_d(inst.z)), _p(out)), "obj")
+        return float(out[0]), float(out[1])
+
+    def grad(self, inst, k0=0, k1=None):
+        k1 = inst.N + 1 if k1 is None else k1
+        K = k1 - k0
+        g = np.empty((inst.n + inst.m) * K)
+        mu = np.empty_like(g)
+        _check(self.L.orc_grad(inst.N, inst.n, inst.m, _p(_d(inst.q)), _p(_d(inst.r)),
+                               _p(_d(inst.z)), k0, k1, _p(g), _p(mu)), "grad")
+        return g, mu
+
+    def cons(self, inst, k0=0, k1=None):
+        k1 = inst.N if k1 is None else k1
+        K = k1 - k0
+        c = np.empty(inst.n * K)
+        mu = np.empty_like(c)
+        _check(self.L.orc_cons(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.B)),
+                               _p(_d(inst.gamma)), _p(_d(inst.z)), k0, k1, _p(c), _p(mu)), "cons")
+        return c, mu
+
+    def jac(self, inst, k0=0, k1=None):
+        k1 = inst.N if k1 is None else k1
+        K = k1 - k0
+        T = 2 * inst.n + 2 * inst.m
+        v = np.empty(inst.n * T * K)
+        mu = np.empty_like(v)
+        _check(self.L.orc_jac(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.B)),
+                              _p(_d(inst.gamma)), _p(_d(inst.z)), k0, k1, _p(v), _p(mu)), "jac")
+        return v, mu
+
+    def hess(self, inst, k0=0, k1=None, sigma=None, y=None):
+        k1 = inst.N + 1 if k1 is None else k1
+        K = k1 - k0
+        S = self.sizes(inst.N, inst.n, inst.m)["S"]
+        v = np.empty(S * K)
+        mu = np.empty_like(v)
+        sigma = inst.sigma if sigma is None else sigma
+        y = inst.y if y is None else y
+        _check(self.L.orc_hess(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.B)),
+                               _p(_d(inst.gamma)), _p(_d(inst.q)), _p(_d(inst.r)), _p(_d(inst.z)),
+                               _p(_d(y)), float(sigma), k0, k1, _p(v), _p(mu)), "hess")
+        return v, mu
+
+    def pattern(self, N, n, m):
+        """(jrow, jcol, hrow, hcol) int32 COO patterns."""
+        s = self.sizes(N, n, m)
+        jrow = np.empty(s["nnzj"], np.int32)
+        jcol = np.empty(s["nnzj"], np.int32)
+        hrow = np.empty(s["nnzh"], np.int32)
+        hcol = np.empty(s["nnzh"], np.int32)
+        _check(self.L.orc_pattern(N, n, m, _p(jrow), _p(jcol), _p(hrow), _p(hcol)), "pattern")
+        return jrow, jcol, hrow, hcol
+
+    def kkt(self, N, n, m, pat=None):
+        """Generic sort-based KKT build: (rowptr, colind, perm_j, perm_h)."""
+        s = self.sizes(N, n, m)
+        jrow, jcol, hrow, hcol = self.pattern(N, n, m) if pat is None else pat
+        rowptr = np.empty(s["dim"] + 1, np.int32)
+        colind = np.empty(s["nnzh"] + s["nnzj"] + s["dim"], np.int32)
+        perm_j = np.empty(s["nnzj"], np.int32)
+        perm_h = np.empty(s["nnzh"], np.int32)
+        nnzk = np.zeros(1, np.int64)
+        _check(self.L.orc_kkt(N, n, m, _p(jrow), _p(jcol), _p(hrow), _p(hcol), _p(rowptr),
+                              _p(colind), _p(perm_j), _p(perm_h), _p(nnzk)), "kkt")
+        return rowptr, colind[: int(nnzk[0])].copy(), perm_j, perm_h
+
+    def assemble(self, rowptr, perm_j, jvals, perm_h, hvals, reg=None):
+        nnzk = int(rowptr[-1])
+        dim = len(rowptr) - 1
+        out = np.empty(nnzk)
+        regp = None if reg is None else _d(reg)
+        _check(self.L.orc_assemble(nnzk, dim, _p(np.ascontiguousarray(rowptr, np.int32)),
+                                   len(perm_j), _p(np.ascontiguousarray(perm_j, np.int32)),
+                                   _p(_d(jvals)), len(perm_h),
+                                   _p(np.ascontiguousarray(perm_h, np.int32)), _p(_d(hvals)),
+                                   _p(regp), _p(out)), "assemble")
+        return out
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments")
+
+
+DEFAULT = Oracle(LIB)
+
+set_threads = DEFAULT.set_threads
+get_threads = DEFAULT.get_threads
+sizes = DEFAULT.sizes
+obj = DEFAULT.obj
+grad = DEFAULT.grad
+cons = DEFAULT.cons
+jac = DEFAULT.jac
+hess = DEFAULT.hess
+pattern = DEFAULT.pattern
+kkt = DEFAULT.kkt
+assemble = DEFAULT.assemble
+
+
+def build_variant(src_text: str, out_path: str) -> "Oracle":
+    """Compile an edited copy of the oracle source (mutation tests) and load it."""
+    c_path = out_path[:-3] + ".c" if out_path.endswith(".so") else out_path + ".c"
+    with open(c_path, "w") as fh:
+        fh.write(src_text)
+    subprocess.check_call(["gcc", *CFLAGS, c_path, "-o", out_path, "-lm"])
+    return Oracle(out_path)

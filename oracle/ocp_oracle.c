@@ -1,0 +1,513 @@
+/*
+ * ocp_oracle.c -- CPU oracle for the trapezoidal direct-transcription NLP.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header
+ * or generated table with the GPU library, and the GPU library never calls it.
+ *
+ * Everything here is the plain definition, evaluated with plain loops in
+ * IEEE double precision (built with -ffp-contract=off, no fast-math):
+ *
+ *   Transcription (paper, Sec. 3 and the trapezoidal generated code of Sec. 5):
+ *     grid t_k = k h, h = 1/N, k = 0..N; hh = h/2; state X_{jk}, control U_{lk}
+ *     on every node k = 0..N; one constraint generator per state component,
+ *       c_{ik} = (X_{i,k+1} - X_{ik}) - hh (F_i(k) + F_i(k+1)),  k = 0..N-1
+ *     and the Lagrange cost summed with the trapezoidal rule (two objective
+ *     generators: end nodes weighted dt/2, interior nodes dt).
+ *   Dynamics of the workload family:
+ *     F_i(k) = sum_j A_ij sin X_jk + sum_l B_il U_lk + gamma_i X_ik X_{p(i)k},
+ *     p(i) = (i+1) mod n.
+ *   Cost: f = sum_k w_k (sum_j q_j X_jk^2 + sum_l r_l U_lk^2).
+ *   Derivatives (the evaluations an interior-point iteration requests, Sec. 6):
+ *     gradient of f, Jacobian of c, Hessian of L = sigma f + y^T c,
+ *     and the KKT matrix [[H, J^T], [J, 0]] in lower-triangular CSR.
+ *
+ * Index conventions (component-major unknowns):
+ *   vx(j,k) = j (N+1) + k,   vu(l,k) = n (N+1) + l (N+1) + k,
+ *   constraint row r(i,k) = i N + k,  y indexed like c.
+ *   Jacobian COO position of slot t in row r(i,k):  (i T + t) N + k,  T = 2n + 2m.
+ *   Hessian COO position of slot s at node k:       s (N+1) + k.
+ *
+ * Node-range functions take [k0, k1) and write a compact block whose slot
+ * stride is K = k1 - k0; the full range reproduces the full-size layout.
+ * Each value function also writes a magnitude mu: the sum of the absolute
+ * values of the terms the value is made of (the scale for a rounding bound).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_BAD 1
+
+static int npair_of(int n) { return n >= 3 ? n : (n == 2 ? 1 : 0); }
+
+static int bad_sizes(int64_t N, int n, int m)
+{
+    return N < 1 || n < 1 || m < 0;
+}
+
+/* Cost weight of node k: trapezoidal rule on a uniform grid. */
+static double weight(int64_t N, int64_t k)
+{
+    double h = 1.0 / (double)N;
+    double hh = 0.5 * h;
+    return (k == 0 || k == N) ? hh : h;
+}
+
+/* out = {nvar, ncon, nnzj, nnzh, dim, npair, T, S} */
+int orc_sizes(int64_t N, int n, int m, int64_t *out)
+{
+    if (bad_sizes(N, n, m) || !out) return ORC_BAD;
+    int64_t npair = npair_of(n);
+    int64_t T = 2 * (int64_t)n + 2 * (int64_t)m;
+    int64_t S = (int64_t)n + npair + (int64_t)m;
+    out[0] = ((int64_t)n + m) * (N + 1);
+    out[1] = (int64_t)n * N;
+    out[2] = (int64_t)n * N * T;
+    out[3] = S * (N + 1);
+    out[4] = out[0] + out[1];
+    out[5] = npair;
+    out[6] = T;
+    out[7] = S;
+    return ORC_OK;
+}
+
+void orc_set_threads(int t) { if (t > 0) omp_set_num_threads(t); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
+
+/* ---- dynamics at one node ------------------------------------------------ */
+
+/* F_i(k) and |F|_i(k) (sum of |terms|), summed j ascending, l ascending, then
+ * the bilinear term. */
+static void dynamics(int64_t N, int n, int m, const double *A, const double *B,
+                     const double *gam, const double *z, int64_t k,
+                     double *F, double *Fabs)
+{
+    const double *X = z;
+    const double *U = z + (int64_t)n * (N + 1);
+    for (int i = 0; i < n; i++) {
+        double s = 0.0, sa = 0.0, t;
+        for (int j = 0; j < n; j++) {
+            t = A[i * n + j] * sin(X[(int64_t)j * (N + 1) + k]);
+            s += t; sa += fabs(t);
+        }
+        for (int l = 0; l < m; l++) {
+            t = B[i * m + l] * U[(int64_t)l * (N + 1) + k];
+            s += t; sa += fabs(t);
+        }
+        int p = (i + 1) % n;
+        t = gam[i] * X[(int64_t)i * (N + 1) + k] * X[(int64_t)p * (N + 1) + k];
+        s += t; sa += fabs(t);
+        F[i] = s;
+        if (Fabs) Fabs[i] = sa;
+    }
+}
+
+/* ---- objective (o1) ------------------------------------------------------ */
+
+/* Neumaier-compensated accumulator. */
+typedef struct { double s, c; } acc_t;
+static void acc_add(acc_t *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+#define OBJ_CHUNK 4096
+
+/* out[0] = f, out[1] = mu(f).  Per-node terms are summed with Neumaier
+ * compensation inside fixed chunks of OBJ_CHUNK nodes, then the chunk results
+ * are summed with Neumaier in chunk order: the result does not depend on the
+ * number of threads. */
+int orc_obj(int64_t N, int n, int m, const double *q, const double *r,
+            const double *z, double *out)
+{
+    if (bad_sizes(N, n, m) || !q || (m && !r) || !z || !out) return ORC_BAD;
+    const double *X = z;
+    const double *U = z + (int64_t)n * (N + 1);
+    int64_t nodes = N + 1;
+    int64_t nch = (nodes + OBJ_CHUNK - 1) / OBJ_CHUNK;
+    double *cs = (double *)malloc(sizeof(double) * 2 * nch);
+    double *ca = (double *)malloc(sizeof(double) * nch);
+    if (!cs || !ca) { free(cs); free(ca); return ORC_BAD; }
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nch; c++) {
+        acc_t a = {0.0, 0.0};
+        double mu = 0.0;
+        int64_t kend = (c + 1) * OBJ_CHUNK < nodes ? (c + 1) * OBJ_CHUNK : nodes;
+        for (int64_t k = c * OBJ_CHUNK; k < kend; k++) {
+            double s = 0.0, sa = 0.0;
+            for (int j = 0; j < n; j++) {
+                double x = X[(int64_t)j * (N + 1) + k];
+                double t = q[j] * x * x;
+                s += t; sa += fabs(t);
+            }
+            for (int l = 0; l < m; l++) {
+                double u = U[(int64_t)l * (N + 1) + k];
+                double t = r[l] * u * u;
+                s += t; sa += fabs(t);
+            }
+            double w = weight(N, k);
+            acc_add(&a, w * s);
+            mu += w * sa;
+        }
+        cs[2 * c] = a.s;
+        cs[2 * c + 1] = a.c;
+        ca[c] = mu;
+    }
+    acc_t tot = {0.0, 0.0};
+    double mu = 0.0;
+    for (int64_t c = 0; c < nch; c++) {
+        acc_add(&tot, cs[2 * c]);
+        acc_add(&tot, cs[2 * c + 1]);
+        mu += ca[c];
+    }
+    out[0] = tot.s + tot.c;
+    out[1] = mu;
+    free(cs);
+    free(ca);
+    return ORC_OK;
+}
+
+/* ---- gradient (o2) ------------------------------------------------------- */
+
+/* Nodes k in [k0, k1) of [0, N]; g[j K + k-k0] for states, g[(n+l) K + k-k0]
+ * for controls. */
+int orc_grad(int64_t N, int n, int m, const double *q, const double *r,
+             const double *z, int64_t k0, int64_t k1, double *g, double *mu)
+{
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N + 1 || k0 > k1 || !z || !g) return ORC_BAD;
+    const double *X = z;
+    const double *U = z + (int64_t)n * (N + 1);
+    int64_t K = k1 - k0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = k0; k < k1; k++) {
+        double w = weight(N, k);
+        for (int j = 0; j < n; j++) {
+            double v = 2.0 * w * q[j] * X[(int64_t)j * (N + 1) + k];
+            g[(int64_t)j * K + (k - k0)] = v;
+            if (mu) mu[(int64_t)j * K + (k - k0)] = fabs(v);
+        }
+        for (int l = 0; l < m; l++) {
+            double v = 2.0 * w * r[l] * U[(int64_t)l * (N + 1) + k];
+            g[(int64_t)(n + l) * K + (k - k0)] = v;
+            if (mu) mu[(int64_t)(n + l) * K + (k - k0)] = fabs(v);
+        }
+    }
+    return ORC_OK;
+}
+
+/* ---- constraints (o3) ---------------------------------------------------- */
+
+/* Intervals k in [k0, k1) of [0, N); c[i K + k-k0]. */
+int orc_cons(int64_t N, int n, int m, const double *A, const double *B,
+             const double *gam, const double *z, int64_t k0, int64_t k1,
+             double *c, double *mu)
+{
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N || k0 > k1 || !z || !c) return ORC_BAD;
+    const double *X = z;
+    double hh = 0.5 * (1.0 / (double)N);
+    int64_t K = k1 - k0;
+    #pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * 4 * n);
+        double *F0 = buf, *F1 = buf + n, *A0 = buf + 2 * n, *A1 = buf + 3 * n;
+        #pragma omp for schedule(static)
+        for (int64_t k = k0; k < k1; k++) {
+            dynamics(N, n, m, A, B, gam, z, k, F0, A0);
+            dynamics(N, n, m, A, B, gam, z, k + 1, F1, A1);
+            for (int i = 0; i < n; i++) {
+                double x0 = X[(int64_t)i * (N + 1) + k];
+                double x1 = X[(int64_t)i * (N + 1) + k + 1];
+                c[(int64_t)i * K + (k - k0)] = (x1 - x0) - hh * (F0[i] + F1[i]);
+                if (mu) mu[(int64_t)i * K + (k - k0)] = fabs(x1) + fabs(x0) + hh * (A0[i] + A1[i]);
+            }
+        }
+        free(buf);
+    }
+    return ORC_OK;
+}
+
+/* ---- Jacobian values (o4) ------------------------------------------------ */
+
+/* dF_i/dX_j at node k, and its magnitude. */
+static void dF_dx(int64_t N, int n, const double *A, const double *gam,
+                  const double *X, int i, int j, int64_t k, double *v, double *va)
+{
+    int p = (i + 1) % n;
+    double a = A[i * n + j] * cos(X[(int64_t)j * (N + 1) + k]);
+    double g = 0.0, ga = 0.0;
+    if (j == i) { g += gam[i] * X[(int64_t)p * (N + 1) + k]; ga += fabs(gam[i] * X[(int64_t)p * (N + 1) + k]); }
+    if (j == p) { g += gam[i] * X[(int64_t)i * (N + 1) + k]; ga += fabs(gam[i] * X[(int64_t)i * (N + 1) + k]); }
+    *v = a + g;
+    *va = fabs(a) + ga;
+}
+
+/* Intervals k in [k0, k1); value of slot t of row (i, k) at (i T + t) K + k-k0.
+ * Slots in ascending column order: X_j at k, X_j at k+1 (j ascending), then
+ * U_l at k, U_l at k+1 (l ascending). */
+int orc_jac(int64_t N, int n, int m, const double *A, const double *B,
+            const double *gam, const double *z, int64_t k0, int64_t k1,
+            double *out, double *mu)
+{
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N || k0 > k1 || !z || !out) return ORC_BAD;
+    const double *X = z;
+    double hh = 0.5 * (1.0 / (double)N);
+    int64_t K = k1 - k0;
+    int64_t T = 2 * (int64_t)n + 2 * (int64_t)m;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = k0; k < k1; k++) {
+        for (int i = 0; i < n; i++) {
+            for (int j = 0; j < n; j++) {
+                double d = (i == j) ? 1.0 : 0.0;
+                double g0, g0a, g1, g1a;
+                dF_dx(N, n, A, gam, X, i, j, k, &g0, &g0a);
+                dF_dx(N, n, A, gam, X, i, j, k + 1, &g1, &g1a);
+                int64_t e0 = ((int64_t)i * T + 2 * j) * K + (k - k0);
+                int64_t e1 = ((int64_t)i * T + 2 * j + 1) * K + (k - k0);
+                out[e0] = -d - hh * g0;
+                out[e1] = d - hh * g1;
+                if (mu) { mu[e0] = d + hh * g0a; mu[e1] = d + hh * g1a; }
+            }
+            for (int l = 0; l < m; l++) {
+                double v = -hh * B[i * m + l];
+                int64_t e0 = ((int64_t)i * T + 2 * n + 2 * l) * K + (k - k0);
+                int64_t e1 = e0 + K;
+                out[e0] = v;
+                out[e1] = v;
+                if (mu) { mu[e0] = fabs(v); mu[e1] = fabs(v); }
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ---- Hessian of the Lagrangian values (o5) ------------------------------- */
+
+/* Nodes k in [k0, k1) of [0, N]; slot s at s K + k-k0.
+ * Slots: state diagonals (n), bilinear pairs (npair), control diagonals (m). */
+int orc_hess(int64_t N, int n, int m, const double *A, const double *B,
+             const double *gam, const double *q, const double *r,
+             const double *z, const double *y, double sigma,
+             int64_t k0, int64_t k1, double *out, double *mu)
+{
+    (void)B;
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N + 1 || k0 > k1 || !z || !y || !out) return ORC_BAD;
+    const double *X = z;
+    double h = 1.0 / (double)N;
+    double hh = 0.5 * h;
+    int np = npair_of(n);
+    int64_t K = k1 - k0;
+    #pragma omp parallel
+    {
+        double *yt = (double *)malloc(sizeof(double) * 2 * n);
+        double *ya = yt + n;
+        #pragma omp for schedule(static)
+        for (int64_t k = k0; k < k1; k++) {
+            double w = weight(N, k);
+            /* Node-combined multiplier: node k appears in the defect of
+             * interval k-1 (as its right end) and of interval k (left end). */
+            for (int i = 0; i < n; i++) {
+                double a = 0.0, aa = 0.0;
+                if (k >= 1) { a += y[(int64_t)i * N + k - 1]; aa += fabs(y[(int64_t)i * N + k - 1]); }
+                if (k <= N - 1) { a += y[(int64_t)i * N + k]; aa += fabs(y[(int64_t)i * N + k]); }
+                yt[i] = a;
+                ya[i] = aa;
+            }
+            for (int j = 0; j < n; j++) {
+                double sx = sin(X[(int64_t)j * (N + 1) + k]);
+                double s = 0.0, sa = 0.0;
+                for (int i = 0; i < n; i++) {
+                    s += yt[i] * A[i * n + j];
+                    sa += ya[i] * fabs(A[i * n + j]);
+                }
+                double v = 2.0 * sigma * w * q[j] + hh * sx * s;
+                double va = fabs(2.0 * sigma * w * q[j]) + hh * fabs(sx) * sa;
+                if (n == 1) {
+                    v += -h * yt[0] * gam[0];
+                    va += h * ya[0] * fabs(gam[0]);
+                }
+                out[(int64_t)j * K + (k - k0)] = v;
+                if (mu) mu[(int64_t)j * K + (k - k0)] = va;
+            }
+            if (n >= 3) {
+                for (int i = 0; i < n; i++) {
+                    int64_t e = (int64_t)(n + i) * K + (k - k0);
+                    out[e] = -hh * yt[i] * gam[i];
+                    if (mu) mu[e] = hh * ya[i] * fabs(gam[i]);
+                }
+            } else if (n == 2) {
+                int64_t e = (int64_t)n * K + (k - k0);
+                out[e] = -hh * (yt[0] * gam[0] + yt[1] * gam[1]);
+                if (mu) mu[e] = hh * (ya[0] * fabs(gam[0]) + ya[1] * fabs(gam[1]));
+            }
+            for (int l = 0; l < m; l++) {
+                int64_t e = (int64_t)(n + np + l) * K + (k - k0);
+                double v = 2.0 * sigma * w * r[l];
+                out[e] = v;
+                if (mu) mu[e] = fabs(v);
+            }
+        }
+        free(yt);
+    }
+    return ORC_OK;
+}
+
+/* ---- sparsity patterns (a1) ---------------------------------------------- */
+
+int orc_pattern(int64_t N, int n, int m, int32_t *jrow, int32_t *jcol,
+                int32_t *hrow, int32_t *hcol)
+{
+    if (bad_sizes(N, n, m)) return ORC_BAD;
+    int64_t s[8];
+    orc_sizes(N, n, m, s);
+    if (s[4] > INT32_MAX || s[2] > INT32_MAX || s[3] > INT32_MAX) return ORC_BAD;
+    int64_t T = s[6];
+    int np = (int)s[5];
+    int64_t NX = (int64_t)n * (N + 1);
+    if (jrow && jcol) {
+        for (int i = 0; i < n; i++)
+            for (int64_t t = 0; t < T; t++)
+                for (int64_t k = 0; k < N; k++) {
+                    int64_t e = ((int64_t)i * T + t) * N + k;
+                    int64_t col;
+                    if (t < 2 * n) {
+                        int64_t j = t / 2;
+                        col = j * (N + 1) + k + (t % 2);
+                    } else {
+                        int64_t l = (t - 2 * n) / 2;
+                        col = NX + l * (N + 1) + k + ((t - 2 * n) % 2);
+                    }
+                    jrow[e] = (int32_t)((int64_t)i * N + k);
+                    jcol[e] = (int32_t)col;
+                }
+    }
+    if (hrow && hcol) {
+        for (int64_t k = 0; k <= N; k++) {
+            for (int j = 0; j < n; j++) {
+                int64_t e = (int64_t)j * (N + 1) + k;
+                hrow[e] = hcol[e] = (int32_t)((int64_t)j * (N + 1) + k);
+            }
+            for (int i = 0; i < np; i++) {
+                int a = i, b = (i + 1) % n;
+                int hi = a > b ? a : b, lo = a < b ? a : b;
+                int64_t e = (int64_t)(n + i) * (N + 1) + k;
+                hrow[e] = (int32_t)((int64_t)hi * (N + 1) + k);
+                hcol[e] = (int32_t)((int64_t)lo * (N + 1) + k);
+            }
+            for (int l = 0; l < m; l++) {
+                int64_t e = (int64_t)(n + np + l) * (N + 1) + k;
+                hrow[e] = hcol[e] = (int32_t)(NX + (int64_t)l * (N + 1) + k);
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ---- generic KKT build (a2) ---------------------------------------------- */
+
+typedef struct { int64_t col; int64_t src; } ent_t;   /* src: -1 diag, 2e H, 2e+1 J */
+
+static int ent_cmp(const void *a, const void *b)
+{
+    const ent_t *x = (const ent_t *)a, *y = (const ent_t *)b;
+    if (x->col != y->col) return x->col < y->col ? -1 : 1;
+    if (x->src != y->src) return x->src < y->src ? -1 : 1;
+    return 0;
+}
+
+/* Lower-triangular CSR of K = [[H, J^T], [J, 0]] from the COO patterns, built
+ * generically: triplets (H entries, J entries shifted down by nvar, and every
+ * diagonal) -> counting sort by row -> sort columns within each row -> merge
+ * duplicates -> map each COO entry to its CSR slot.  No structural shortcut.
+ * rowptr has dim+1 entries; colind must hold nnzh + nnzj + dim entries (an
+ * upper bound); *nnzk receives the true count.  Returns ORC_BAD if any entry
+ * lies above the diagonal or a size exceeds int32. */
+int orc_kkt(int64_t N, int n, int m, const int32_t *jrow, const int32_t *jcol,
+            const int32_t *hrow, const int32_t *hcol, int32_t *rowptr,
+            int32_t *colind, int32_t *perm_j, int32_t *perm_h, int64_t *nnzk)
+{
+    if (bad_sizes(N, n, m)) return ORC_BAD;
+    int64_t s[8];
+    orc_sizes(N, n, m, s);
+    int64_t nvar = s[0], nnzj = s[2], nnzh = s[3], dim = s[4];
+    int64_t ntrip = nnzh + nnzj + dim;
+    if (dim > INT32_MAX || ntrip > INT32_MAX) return ORC_BAD;
+    int64_t *cnt = (int64_t *)calloc((size_t)dim + 1, sizeof(int64_t));
+    ent_t *ent = (ent_t *)malloc(sizeof(ent_t) * (size_t)ntrip);
+    if (!cnt || !ent) { free(cnt); free(ent); return ORC_BAD; }
+    int rc = ORC_OK;
+    /* count per row */
+    for (int64_t e = 0; e < nnzh; e++) cnt[hrow[e] + 1]++;
+    for (int64_t e = 0; e < nnzj; e++) cnt[nvar + jrow[e] + 1]++;
+    for (int64_t d = 0; d < dim; d++) cnt[d + 1]++;
+    for (int64_t d = 0; d < dim; d++) cnt[d + 1] += cnt[d];
+    /* place (stable) */
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)dim);
+    if (!pos) { free(cnt); free(ent); return ORC_BAD; }
+    memcpy(pos, cnt, sizeof(int64_t) * (size_t)dim);
+    for (int64_t e = 0; e < nnzh; e++) {
+        if (hcol[e] > hrow[e]) rc = ORC_BAD;
+        ent_t t = { hcol[e], 2 * e };
+        ent[pos[hrow[e]]++] = t;
+    }
+    for (int64_t e = 0; e < nnzj; e++) {
+        int64_t row = nvar + jrow[e];
+        if (jcol[e] > row) rc = ORC_BAD;
+        ent_t t = { jcol[e], 2 * e + 1 };
+        ent[pos[row]++] = t;
+    }
+    for (int64_t d = 0; d < dim; d++) {
+        ent_t t = { d, -1 };
+        ent[pos[d]++] = t;
+    }
+    free(pos);
+    /* sort within rows, merge duplicates, assign slots */
+    int64_t slot = -1;
+    rowptr[0] = 0;
+    for (int64_t d = 0; d < dim; d++) {
+        int64_t b = cnt[d], en = cnt[d + 1];
+        qsort(ent + b, (size_t)(en - b), sizeof(ent_t), ent_cmp);
+        int64_t prev = -1;
+        for (int64_t x = b; x < en; x++) {
+            if (x == b || ent[x].col != prev) {
+                slot++;
+                colind[slot] = (int32_t)ent[x].col;
+                prev = ent[x].col;
+            }
+            int64_t sr = ent[x].src;
+            if (sr >= 0) {
+                if (sr % 2 == 0) perm_h[sr / 2] = (int32_t)slot;
+                else perm_j[sr / 2] = (int32_t)slot;
+            }
+        }
+        rowptr[d + 1] = (int32_t)(slot + 1);
+    }
+    *nnzk = slot + 1;
+    free(cnt);
+    free(ent);
+    return rc;
+}
+
+/* ---- KKT assembly (o7) --------------------------------------------------- */
+
+/* kkt = 0; kkt[perm_h[e]] = hess[e]; kkt[perm_j[e]] = jac[e];
+ * then, if reg is given, kkt[rowptr[d+1]-1] += reg[d] for every row d. */
+int orc_assemble(int64_t nnzk, int64_t dim, const int32_t *rowptr,
+                 int64_t nnzj, const int32_t *perm_j, const double *jac,
+                 int64_t nnzh, const int32_t *perm_h, const double *hess,
+                 const double *reg, double *kkt)
+{
+    if (!kkt || !rowptr || nnzk < 0) return ORC_BAD;
+    for (int64_t x = 0; x < nnzk; x++) kkt[x] = 0.0;
+    for (int64_t e = 0; e < nnzh; e++) kkt[perm_h[e]] = hess[e];
+    for (int64_t e = 0; e < nnzj; e++) kkt[perm_j[e]] = jac[e];
+    if (reg)
+        for (int64_t d = 0; d < dim; d++) kkt[rowptr[d + 1] - 1] += reg[d];
+    return ORC_OK;
+}

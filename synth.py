@@ -1,0 +1,89 @@
+"""Seeded synthetic inputs for the trapezoidal optimal-control NLP workloads.
+
+This module only draws random numbers and lays them out; it contains none of
+the transcription arithmetic (no dynamics, no derivatives, no weights).  Both
+the CPU oracle and the GPU library consume what it returns.
+
+Workload family (one instance):
+    dynamics   f_i(x, u) = sum_j A_ij sin(x_j) + sum_l B_il u_l + gamma_i x_i x_{(i+1) mod n}
+    cost       integral of x^T Q x + u^T R u, Q = diag(q), R = diag(r)
+    grid       uniform, t in [0, 1], N intervals, N + 1 nodes
+
+Draw order for one instance, from ``numpy.random.default_rng(seed)`` (PCG64):
+    A ~ N(0, 1/n)  (standard deviation n**-0.5), shape (n, n)
+    B ~ N(0, 1), shape (n, m)
+    gamma ~ U(-0.5, 0.5), shape (n,)
+    X ~ N(0, 1), shape (n, N + 1)       state at every node
+    U ~ U(-1, 1), shape (m, N + 1)      control at every node
+    y ~ N(0, 1), shape (n, N)           one multiplier per defect row
+and q = 1, r = 0.1, sigma = 1.  The unknown vector is z = [X.ravel(), U.ravel()]
+(component-major: all nodes of state 0, then state 1, ..., then the controls).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Instance:
+    N: int
+    n: int
+    m: int
+    A: np.ndarray      # (n, n) row-major
+    B: np.ndarray      # (n, m) row-major
+    gamma: np.ndarray  # (n,)
+    q: np.ndarray      # (n,)
+    r: np.ndarray      # (m,)
+    z: np.ndarray      # (nvar,) = [X (n, N+1) | U (m, N+1)], row-major blocks
+    y: np.ndarray      # (n*N,) multipliers, row (i, k) at i*N + k
+    sigma: float
+
+    @property
+    def X(self) -> np.ndarray:
+        return self.z[: self.n * (self.N + 1)].reshape(self.n, self.N + 1)
+
+    @property
+    def U(self) -> np.ndarray:
+        return self.z[self.n * (self.N + 1):].reshape(self.m, self.N + 1)
+
+
+def coefficients(rng: np.random.Generator, n: int, m: int):
+    """Draw (A, B, gamma) in the fixed order."""
+    A = rng.normal(0.0, n ** -0.5, (n, n))
+    B = rng.normal(0.0, 1.0, (n, m))
+    gamma = rng.uniform(-0.5, 0.5, n)
+    return A, B, gamma
+
+
+def point(rng: np.random.Generator, N: int, n: int, m: int):
+    """Draw an evaluation point (X, U) and multipliers y, in that order."""
+    X = rng.normal(0.0, 1.0, (n, N + 1))
+    U = rng.uniform(-1.0, 1.0, (m, N + 1))
+    y = rng.normal(0.0, 1.0, (n, N))
+    return X, U, y
+
+
+def make_instance(N: int, n: int, m: int, seed=0) -> Instance:
+    """One instance of the workload family; ``seed`` may be an int or a list."""
+    rng = np.random.default_rng(seed)
+    A, B, gamma = coefficients(rng, n, m)
+    X, U, y = point(rng, N, n, m)
+    z = np.concatenate([X.ravel(), U.ravel()])
+    return Instance(N=N, n=n, m=m, A=np.ascontiguousarray(A), B=np.ascontiguousarray(B),
+                    gamma=gamma, q=np.ones(n), r=np.full(m, 0.1),
+                    z=np.ascontiguousarray(z), y=np.ascontiguousarray(y.ravel()),
+                    sigma=1.0)
+
+
+# Named workloads: (N, n, m).
+PARITY = (1000, 4, 2)           # one evaluation of everything, seed 0
+IPM_LOOP = (100_000, 8, 4)      # repeated cons + jac + hess + assemble
+LARGE = (1_000_000, 16, 8)      # dense 16x16 A; the roofline workload
+DIFF = (200_000, 8, 4)          # Lagrangian differentiation workload
+
+
+def batched_sizes(count: int = 512, lo: int = 200, hi: int = 20000, seed: int = 0) -> np.ndarray:
+    """Per-instance interval counts N_b ~ U{lo..hi} for the batched workload."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, count)

@@ -1,0 +1,80 @@
+"""Plant plausible mistakes in a copy of the oracle source (on the CPU) and check
+that the pins catch every one of them: a pin set that passes a wrong oracle
+would prove nothing."""
+from __future__ import annotations
+
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as P
+
+# (name, text in ocp_oracle.c, replacement)
+MUTATIONS = [
+    ("defect sign", "(x1 - x0) - hh * (F0[i] + F1[i])", "(x1 - x0) + hh * (F0[i] + F1[i])"),
+    ("defect pairing", "(x1 - x0) - hh * (F0[i] + F1[i])", "(x1 - x0) - hh * (F0[i] + F0[i])"),
+    ("defect direction", "(x1 - x0) - hh * (F0[i] + F1[i])", "(x0 - x1) - hh * (F0[i] + F1[i])"),
+    ("bilinear partner index", "int p = (i + 1) % n;\n        t = gam[i]", "int p = i;\n        t = gam[i]"),
+    ("dropped control term", "t = B[i * m + l] * U", "t = 0.0 * U"),
+    ("transposed A in dynamics", "t = A[i * n + j] * sin(", "t = A[j * n + i] * sin("),
+    ("end weight at N", "(k == 0 || k == N) ? hh : h", "(k == 0) ? hh : h"),
+    ("jac right node", "out[e1] = d - hh * g1;", "out[e1] = d - hh * g0;"),
+    ("jac identity sign", "out[e0] = -d - hh * g0;", "out[e0] = d - hh * g0;"),
+    ("jac cos->sin", "double a = A[i * n + j] * cos(", "double a = A[i * n + j] * sin("),
+    ("jac bilinear partner", "if (j == p) { g += gam[i] * X[(int64_t)i", "if (j == p) { g += gam[i] * X[(int64_t)p"),
+    ("jac control slot", "double v = -hh * B[i * m + l];", "double v = hh * B[i * m + l];"),
+    ("pattern slot order", "col = j * (N + 1) + k + (t % 2);", "col = j * (N + 1) + k + 1 - (t % 2);"),
+    ("hess pair sign", "out[e] = -hh * yt[i] * gam[i];", "out[e] = hh * yt[i] * gam[i];"),
+    ("hess multiplier range", "if (k <= N - 1) { a += y", "if (k < N - 1) { a += y"),
+    ("hess transposed A", "s += yt[i] * A[i * n + j];", "s += yt[i] * A[j * n + i];"),
+    ("hess n=1 fold", "v += -h * yt[0] * gam[0];", "v += -hh * yt[0] * gam[0];"),
+    ("hess sigma", "double v = 2.0 * sigma * w * q[j] + hh * sx * s;", "double v = 2.0 * w * q[j] + hh * sx * s;"),
+    ("pattern pair triangle", "int hi = a > b ? a : b", "int hi = a"),
+    ("grad factor", "double v = 2.0 * w * q[j] * X", "double v = w * q[j] * X"),
+    ("grad control weight", "double v = 2.0 * w * r[l] * U", "double v = 2.0 * r[l] * U"),
+    ("kkt column order", "if (x->col != y->col) return x->col < y->col ? -1 : 1;",
+     "if (x->col != y->col) return x->col < y->col ? 1 : -1;"),
+    ("kkt diagonal position", "kkt[rowptr[d + 1] - 1] += reg[d]", "kkt[rowptr[d]] += reg[d]"),
+    ("obj control term", "double t = r[l] * u * u;", "double t = r[l] * u;"),
+]
+
+# Pins run against each mutant: (test function, arguments after the oracle).
+PINS = [
+    (P.test_golden_generated_code, ()),
+    (P.test_pattern_unique_lower, (5, 2, 0)),
+    (P.test_jacobian_pattern_is_nonzero_set, (3, 3, 1)),
+    (P.test_kkt_matches_scipy, (6, 5, 3)),
+    (P.test_kkt_spmv_equals_dense, (3, 3, 1)),
+    (P.test_kkt_spmv_equals_dense, (3, 1, 0)),
+    (P.test_objective_constant_state, (7,)),
+    (P.test_objective_vs_exact_rational, (1000, 4, 2)),
+    (P.test_linear_quadratic_case, (20, 3, 2)),
+    (P.test_defects_of_exact_trajectory_are_third_order, (4, 2)),
+    (P.test_jacobian_dense_complex_step, (5, 4, 2)),
+    (P.test_jacobian_dense_complex_step, (2, 1, 1)),
+    (P.test_gradient_complex_step_and_central_difference, (5, 3, 2)),
+    (P.test_hessian_dense_mixed_difference, (2, 4, 2)),
+    (P.test_hessian_dense_mixed_difference, (3, 1, 0)),
+]
+
+
+def test_mutations_apply_to_current_source():
+    src = open(oracle.SRC).read()
+    for name, old, _new in MUTATIONS:
+        assert src.count(old) >= 1, name
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    src = open(oracle.SRC).read()
+    assert old in src
+    mutant = oracle.build_variant(src.replace(old, new, 1), os.path.join(tmp_path, "mut.so"))
+    caught = []
+    for fn, args in PINS:
+        try:
+            fn(mutant, *args)
+        except (AssertionError, ValueError) as e:  # noqa: PERF203
+            caught.append(fn.__name__)
+    assert caught, f"no pin catches the planted mistake '{name}'"
