@@ -1,0 +1,253 @@
+"""Benchmark of the evaluation path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
+controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
+already resident in HBM.  One step is one pass of the whole device path:
+eval_obj, eval_grad, eval_cons, eval_jac, eval_hess(sigma = 1) and
+assemble_kkt (with a regularization diagonal).  The KKT structure and slot maps
+are built once on the host before timing (the one-time symbolic step).
+
+Prints ONE JSON line.  `value` is the headline metric, FP64 Jacobian + Hessian
+nonzeros per second: (nnzj + nnzh) / (eval_jac + eval_hess time), measured
+with HIP events on the stream the kernels run on, over the K timed steps.
+`ms_per_step` is the wall time of one whole step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2510_03932_amd", "csrc", "ocp_eval.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_large.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(s, N, n, m):
+    """Bytes each call must move (reads + writes), counting only the parts of
+    z each call reads."""
+    nx = n * (N + 1)
+    return {
+        "eval_obj": 8 * s["nvar"],
+        "eval_grad": 16 * s["nvar"],
+        "eval_cons": 8 * s["nvar"] + 8 * s["ncon"],
+        "eval_jac": 8 * s["nnzj"] + 8 * nx,
+        "eval_hess": 8 * s["nnzh"] + 8 * nx + 8 * s["ncon"],
+        # perm (4 B) + value (8 B) per COO entry, the KKT values, the reg
+        # diagonal, and rowptr at the constraint rows
+        "assemble_kkt": 12 * (s["nnzj"] + s["nnzh"]) + 8 * s["nnzk"] + 8 * s["dim"] + 4 * s["ncon"],
+    }
+
+
+def cpu_baseline(inst, target_s=12.0):
+    """The oracle's Jacobian + Hessian on a bounded slice of the workload,
+    timed on the host cores: intervals [0, K) for the Jacobian and nodes
+    [0, K) for the Hessian, K chosen so the run takes about target_s."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    N = inst.N
+    K = 2000
+    t0 = time.perf_counter()
+    oracle.jac(inst, 0, K)
+    oracle.hess(inst, 0, K)
+    dt = time.perf_counter() - t0
+    K = int(min(N, max(K, K * target_s / max(dt, 1e-6))))
+    T = 2 * inst.n + 2 * inst.m
+    S = oracle.sizes(inst.N, inst.n, inst.m)["S"]
+    t0 = time.perf_counter()
+    oracle.jac(inst, 0, K)
+    oracle.hess(inst, 0, K)
+    dt = time.perf_counter() - t0
+    nnz = K * inst.n * T + K * S
+    return {"value": nnz / dt, "unit": "nonzeros/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle jac on intervals [0,{K}) + hess on nodes [0,{K}) of the "
+                      f"N={N} n={inst.n} m={inst.m} workload ({nnz} nonzeros, {dt:.2f} s, "
+                      f"OpenMP threads={threads})",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--N", type=int, default=None, help="override the interval count")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path shards by node range across GPUs but no multi-GPU run is provided",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2510_03932_amd as ocp
+    import synth
+
+    N, n, m = synth.LARGE
+    if args.N:
+        N = args.N
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"[bench] generating inputs N={N} n={n} m={m}")
+    inst = synth.make_instance(N, n, m, seed=0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    s = prob.sizes
+    log("[bench] building KKT structure on the host")
+    t0 = time.perf_counter()
+    rowptr, _, perm_j, perm_h = ocp.kkt_pattern(N, n, m, colind=False)
+    t_kkt_build = time.perf_counter() - t0
+    z = torch.from_numpy(inst.z).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    pj = torch.from_numpy(perm_j).to(dev)
+    del perm_j
+    ph = torch.from_numpy(perm_h).to(dev)
+    rp = torch.from_numpy(rowptr).to(dev)
+    reg = torch.full((s["dim"],), 1e-8, dtype=torch.float64, device=dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    obj = torch.empty(1, **f64)
+    g = torch.empty(s["nvar"], **f64)
+    c = torch.empty(s["ncon"], **f64)
+    jv = torch.empty(s["nnzj"], **f64)
+    hv = torch.empty(s["nnzh"], **f64)
+    kkt = torch.empty(s["nnzk"], **f64)
+    names = ["eval_obj", "eval_grad", "eval_cons", "eval_jac", "eval_hess", "assemble_kkt"]
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        prob.obj(z, out=obj)
+        if ev is not None:
+            ev[1].record()
+        prob.grad(z, out=g)
+        if ev is not None:
+            ev[2].record()
+        prob.cons(z, out=c)
+        if ev is not None:
+            ev[3].record()
+        prob.jac(z, out=jv)
+        if ev is not None:
+            ev[4].record()
+        prob.hess(z, y, 1.0, out=hv)
+        if ev is not None:
+            ev[5].record()
+        prob.assemble_kkt(pj, ph, rp, jv, hv, reg, out=kkt)
+        if ev is not None:
+            ev[6].record()
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # exactly K timed steps; HIP events on the launch stream split each step
+    # into its kernels (recording an event costs no device time)
+    log(f"[bench] timing {args.steps} steps")
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    per = {nm: [] for nm in names}
+    for ev in events:
+        for i, nm in enumerate(names):
+            per[nm].append(ev[i].elapsed_time(ev[i + 1]))
+    avg = {nm: float(np.mean(v)) for nm, v in per.items()}
+    med = {nm: float(np.median(v)) for nm, v in per.items()}
+
+    byt = algorithmic_bytes(s, N, n, m)
+    kern = {}
+    for nm in names:
+        bw = byt[nm] / (avg[nm] * 1e-3)
+        kern[nm] = {"avg_ms": round(avg[nm], 4), "median_ms": round(med[nm], 4),
+                    "p10_ms": round(float(np.percentile(per[nm], 10)), 4),
+                    "p90_ms": round(float(np.percentile(per[nm], 90)), 4),
+                    "bytes": int(byt[nm]), "GB_per_s": round(bw / 1e9, 1),
+                    "hbm_frac": round(bw / HBM_PEAK, 4)}
+    t_jh = (avg["eval_jac"] + avg["eval_hess"]) * 1e-3
+    nnz_jh = s["nnzj"] + s["nnzh"]
+    value = nnz_jh / t_jh
+    jh_frac = (byt["eval_jac"] + byt["eval_hess"]) / t_jh / HBM_PEAK
+
+    dom = max(names, key=lambda nm: avg[nm])
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        tr = json.load(open(TRAFFIC))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        ent = tr.get("kernels", {}).get(dom)
+        if ent and tr.get("source_sha256") == sha:
+            traffic = int(ent["bytes_per_launch"])
+    roof = {"bound": "hbm", "kernel": dom,
+            "achieved": round(byt[dom] / (avg[dom] * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(byt[dom] / (avg[dom] * 1e-3) / HBM_PEAK, 4),
+            "traffic": traffic}
+
+    # a plain device copy of 2 GiB, for the achievable-bandwidth context
+    a = torch.empty(2 ** 28, **f64)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_bw = 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3)
+    del a, b
+
+    out = {
+        "metric": "FP64 Jac+Hess nonzeros/s at N=1e6 (% HBM peak)",
+        "value": value,
+        "unit": "nonzeros/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single trapezoidal OCP instance N={N} n={n} m={m}, dense A, seed 0",
+                   "N": N, "n": n, "m": m, "nnzj": s["nnzj"], "nnzh": s["nnzh"],
+                   "nnzk": s["nnzk"], "step": "+".join(names)},
+        "jac_hess_ms_per_step": round(t_jh * 1e3, 4),
+        "jac_hess_hbm_frac": round(jh_frac, 4),
+        "step_nnz_per_s": nnz_jh / (ms_per_step * 1e-3),
+        "roofline": roof,
+        "kernels": kern,
+        "copy_GB_per_s": round(copy_bw / 1e9, 1),
+        "kkt_host_build_s": round(t_kkt_build, 2),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cb = cpu_baseline(inst)
+        cb.pop("seconds")
+        out["cpu_baseline"] = cb
+    prob.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

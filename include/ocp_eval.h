@@ -1,0 +1,173 @@
+/*
+ * ocp_eval.h -- C ABI of the MI355X (gfx950) evaluation library for the
+ * trapezoidal direct-transcription NLP of an optimal control problem.
+ *
+ * What it evaluates (paper Sec. 3: direct transcription; Sec. 5: the
+ * trapezoidal constraint and objective generators; Sec. 6: the evaluations an
+ * interior-point iteration requests on the device and the KKT assembly):
+ *
+ *   unknowns   z = [X | U], X_{jk} (n states), U_{lk} (m controls) on the
+ *              nodes k = 0..N of the uniform grid t_k = k h, h = 1/N
+ *   dynamics   F_i(k) = sum_j A_ij sin X_jk + sum_l B_il U_lk
+ *                       + gamma_i X_ik X_{p(i)k},   p(i) = (i+1) mod n
+ *   defects    c_{ik} = (X_{i,k+1} - X_ik) - (h/2) (F_i(k) + F_i(k+1)),  k < N
+ *   cost       f = sum_k w_k (sum_j q_j X_jk^2 + sum_l r_l U_lk^2),
+ *              w_0 = w_N = h/2, w_k = h otherwise (trapezoidal rule)
+ *   Lagrangian L = sigma f + y^T c
+ *   KKT        K = [[H, J^T], [J, 0]], H = Hessian of L, J = Jacobian of c
+ *
+ * Layouts (all structure-of-arrays, node index fastest):
+ *   z          index vx(j,k) = j (N+1) + k, vu(l,k) = n (N+1) + l (N+1) + k;
+ *              nvar = (n+m)(N+1) doubles
+ *   c, y       row r(i,k) = i N + k; ncon = n N doubles
+ *   Jacobian   T = 2n + 2m slots per row, in ascending column order:
+ *              slot 2j: X_j at k, 2j+1: X_j at k+1, 2n+2l: U_l at k,
+ *              2n+2l+1: U_l at k+1.  COO entry e = (i T + t) N + k.
+ *              nnzj = n N T.  Structural: every slot is stored even if zero.
+ *   Hessian    lower triangle, block-diagonal per node; S = n + npair + m
+ *              slots per node, npair = n (n >= 3), 1 (n = 2), 0 (n = 1):
+ *              slot j < n: (vx(j,k), vx(j,k)); slot n+i (n >= 3):
+ *              (vx(max(i,p(i)),k), vx(min(i,p(i)),k)); slot n (n = 2):
+ *              (vx(1,k), vx(0,k)) with both bilinear terms merged; slot
+ *              n+npair+l: (vu(l,k), vu(l,k)).  For n = 1 the bilinear term
+ *              folds into the state diagonal.  COO entry e = s (N+1) + k.
+ *   KKT        lower-triangular CSR of K, dim = nvar + ncon rows, columns
+ *              ascending within a row, every diagonal present and last in its
+ *              row; nnzk = nnzh + nnzj + ncon.  perm_j[e] / perm_h[e] give the
+ *              CSR slot of Jacobian / Hessian COO entry e.
+ *
+ * Precision: IEEE binary64 throughout.  Indices are int32; every size and
+ * index must fit in int32 or the call fails with OCP_ERR_OVERFLOW.
+ *
+ * Ownership: the caller owns every array.  Arrays passed to ocp_eval_* and
+ * ocp_assemble_kkt are device pointers (HBM), contiguous; the index builders
+ * fill host arrays.  The problem handle owns device copies of the dynamics and
+ * cost coefficients and a small device workspace for the objective reduction;
+ * the library never hands out memory for the caller to free.
+ *
+ * Streams: every device call is asynchronous on the given HIP stream (0 = the
+ * null stream) and never synchronizes; the objective lands in a device double.
+ * Each call fully overwrites its output array.  Errors found on the host
+ * (arguments, sizes) are returned before any HIP call; a launch failure is
+ * reported as OCP_ERR_HIP; faults inside a kernel surface at the caller's next
+ * synchronization.  No C++ exception crosses this interface.
+ *
+ * Reentrancy: evaluations on one handle may run concurrently on different
+ * streams, except ocp_eval_obj, which uses the handle's workspace (concurrent
+ * ocp_eval_obj calls on one handle race).  Create and destroy are not
+ * thread-safe for the same handle.
+ */
+#ifndef OCP_EVAL_H
+#define OCP_EVAL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define OCP_OK 0
+#define OCP_ERR_ARG 1       /* null pointer, N < 1, n < 1, m < 0, n or m above OCP_MAX_DIM */
+#define OCP_ERR_OVERFLOW 2  /* a size or index does not fit in int32 */
+#define OCP_ERR_HIP 3       /* a HIP runtime call or kernel launch failed */
+#define OCP_ERR_ALLOC 4     /* host or device allocation failed */
+
+/* Largest supported state or control dimension. */
+#define OCP_MAX_DIM 32
+
+typedef struct ocp_sizes_t {
+    int64_t nvar;   /* (n+m)(N+1)                unknowns */
+    int64_t ncon;   /* n N                       defect rows */
+    int64_t nnzj;   /* n N (2n+2m)               Jacobian entries */
+    int64_t nnzh;   /* (n + npair + m)(N+1)      Hessian (lower) entries */
+    int64_t nnzk;   /* nnzh + nnzj + ncon        KKT (lower CSR) entries */
+    int64_t dim;    /* nvar + ncon               KKT rows */
+    int32_t npair;  /* bilinear Hessian slots per node */
+    int32_t T;      /* Jacobian slots per row */
+    int32_t S;      /* Hessian slots per node */
+} ocp_sizes_t;
+
+typedef struct ocp_problem ocp_problem;
+
+/* Sizes of the transcribed NLP (paper Sec. 3, trapezoidal scheme of Sec. 5).
+ * Host only; no HIP call.  Errors: OCP_ERR_ARG, OCP_ERR_OVERFLOW. */
+int ocp_sizes(int64_t N, int32_t n, int32_t m, ocp_sizes_t *out);
+
+/* Sparsity patterns (the fixed structure the derivative evaluations fill;
+ * paper Sec. 4 and 6: sparsity-preserving derivatives, one-time host
+ * analysis).  Host buffers, caller-owned: jrow, jcol hold nnzj int32 each;
+ * hrow, hcol hold nnzh int32 each.  Either pair may be NULL to skip it.
+ * Entries are written in COO order e as documented above.  Host only.
+ * Errors: OCP_ERR_ARG, OCP_ERR_OVERFLOW. */
+int ocp_build_pattern(int64_t N, int32_t n, int32_t m, int32_t *jrow, int32_t *jcol,
+                      int32_t *hrow, int32_t *hcol);
+
+/* Lower-triangular CSR structure of the KKT matrix and the slot maps of the
+ * Jacobian and Hessian COO entries into it (paper Sec. 6: the one-time host
+ * symbolic step before device-side assembly).  Host buffers, caller-owned:
+ * rowptr dim+1, colind nnzk, perm_j nnzj, perm_h nnzh int32.  Any of them may
+ * be NULL to skip it.  Closed form; uses several host threads.
+ * Errors: OCP_ERR_ARG, OCP_ERR_OVERFLOW. */
+int ocp_build_kkt(int64_t N, int32_t n, int32_t m, int32_t *rowptr, int32_t *colind,
+                  int32_t *perm_j, int32_t *perm_h);
+
+/* Create a problem handle on the current HIP device.  A: n x n row-major,
+ * B: n x m row-major, gamma: n, q: n, r: m (host pointers; B and r may be
+ * NULL when m = 0).  Copies them to the device.
+ * Errors: OCP_ERR_ARG, OCP_ERR_OVERFLOW (checked before any HIP call),
+ * OCP_ERR_ALLOC, OCP_ERR_HIP. */
+int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B,
+               const double *gamma, const double *q, const double *r, ocp_problem **out);
+
+/* Release a handle and its device memory.  NULL-safe.  The caller must make
+ * sure no work using the handle is still in flight. */
+void ocp_destroy(ocp_problem *p);
+
+/* Sizes of a handle's problem. */
+int ocp_problem_sizes(const ocp_problem *p, ocp_sizes_t *out);
+
+/* Objective f(z) (trapezoidal Lagrange cost, Sec. 5) into obj[0] (device).
+ * z: nvar doubles (device).  Deterministic: fixed reduction order for a
+ * given N.  Uses the handle's workspace. */
+int ocp_eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t stream);
+
+/* Gradient of f into g (nvar doubles, device). */
+int ocp_eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t stream);
+
+/* Defects c(z) (Sec. 5, one generator per state component) into c (ncon
+ * doubles, device). */
+int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t stream);
+
+/* Jacobian values at the fixed pattern into jvals (nnzj doubles, device, COO
+ * order e = (i T + t) N + k).  Reads only the state block of z. */
+int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream_t stream);
+
+/* Hessian-of-Lagrangian values of L = sigma f + y^T c at the fixed lower
+ * pattern into hvals (nnzh doubles, device, COO order e = s (N+1) + k).
+ * y: ncon doubles (device). */
+int ocp_eval_hess(const ocp_problem *p, const double *z, const double *y, double sigma,
+                  double *hvals, hipStream_t stream);
+
+/* KKT assembly (Sec. 6: the KKT system is assembled in device buffers):
+ *   kkt[perm_h[e]] = hvals[e], kkt[perm_j[e]] = jvals[e],
+ *   every constraint-row diagonal = reg[d] (0 when reg is NULL), and every
+ *   variable-row diagonal = hvals[e] + reg[d] in one IEEE add.
+ * perm_j (nnzj), perm_h (nnzh), rowptr (dim+1), jvals, hvals, reg (dim,
+ * nullable) and kkt (nnzk) are device arrays.  perm_j / perm_h must be
+ * injective into [0, nnzk) and together with the constraint diagonals cover
+ * every slot (as produced by ocp_build_kkt); rowptr locates the diagonal of
+ * row d at rowptr[d+1] - 1.  Fully overwrites kkt.  No atomics. */
+int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,
+                     const int32_t *rowptr, const double *jvals, const double *hvals,
+                     const double *reg, double *kkt, hipStream_t stream);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *ocp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCP_EVAL_H */

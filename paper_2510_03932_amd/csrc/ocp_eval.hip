@@ -1,0 +1,577 @@
+// Device layer of the evaluation library: HIP kernels for gfx950 (CDNA4,
+// wave64) and the C ABI entry points that validate arguments and launch them.
+//
+// Every evaluation maps one grid node (or one interval) to one lane, the SIMD
+// structure of direct transcription (paper Sec. 3): the same few functions are
+// evaluated at every node.  All arrays are structure-of-arrays with the node
+// index fastest, so the lanes of a wavefront touch consecutive doubles.  The
+// path is HBM-bound sparse evaluation, not a dense contraction: no MFMA.
+//
+// Formulas (component-major unknowns, h = 1/N, hh = h/2, p(i) = (i+1) mod n):
+//   F_i(k)   = sum_j A_ij sin X_jk + sum_l B_il U_lk + gamma_i X_ik X_{p(i)k}
+//   c_{ik}   = (X_{i,k+1} - X_ik) - hh (F_i(k) + F_i(k+1))         [Sec. 5]
+//   f        = sum_k w_k (sum_j q_j X_jk^2 + sum_l r_l U_lk^2)     [Sec. 5]
+//   dF_i/dX_j = A_ij cos X_j + gamma_i (delta_ij X_p(i) + delta_j,p(i) X_i)
+//   Hessian of L = sigma f + y^T c at node k uses the node multiplier
+//   yt_ik = y_{i,k-1} [k >= 1] + y_{ik} [k < N]  (node k is the right end of
+//   interval k-1 and the left end of interval k).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "ocp_internal.h"
+
+using namespace ocp;
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+namespace {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 waves)
+constexpr int kObjBlocks = 1024;     // fixed partial count of the objective sum
+
+// Kernel-side view of a problem: sizes and device coefficient pointers.
+struct KP {
+    int N;         // intervals
+    int N1;        // nodes = N + 1
+    int n, m, npair, T, S;
+    int nnzk;      // KKT entries
+    double h, hh;
+    const double *A;    // n x n row-major
+    const double *B;    // n x m row-major
+    const double *gam;  // n
+    const double *q;    // n
+    const double *r;    // m
+};
+
+__device__ __forceinline__ double node_weight(const KP &P, int k)
+{
+    return (k == 0 || k == P.N) ? P.hh : P.h;
+}
+
+__device__ __forceinline__ void st_nt(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt2(double *p, dbl2 v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<dbl2 *>(p));
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian values.  One lane per NPT consecutive intervals (NPT = 2 stores a
+// 16-byte pair per lane, so one store instruction of a wavefront covers 1 KiB
+// of one slot row).  Loop: state column j outer (2 cosines per node), row i
+// inner; the bilinear term touches only rows i = j (partner X_{j+1}) and
+// i = j-1 (factor X_{j-1}).  Control slots are the constant -hh B_il.
+// ---------------------------------------------------------------------------
+template <int NPT>
+__global__ __launch_bounds__(kBlock) void jac_kernel(KP P, const double *__restrict__ z,
+                                                     double *__restrict__ jac)
+{
+    const int64_t k = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPT;
+    if (k >= P.N) return;
+    const int n = P.n, m = P.m, T = P.T;
+    const int64_t N = P.N, N1 = P.N1;
+    const double hh = P.hh;
+    const double *X = z;
+
+    for (int j = 0; j < n; j++) {
+        const int jn = (j + 1 == n) ? 0 : j + 1;
+        const int jp = (j == 0) ? n - 1 : j - 1;
+        const double *xj = X + j * N1 + k;
+        const double *xn = X + jn * N1 + k;
+        const double *xp = X + jp * N1 + k;
+        double cs[NPT + 1], dg[NPT + 1], lo[NPT + 1];
+#pragma unroll
+        for (int u = 0; u <= NPT; u++) {
+            cs[u] = cos(xj[u]);
+            dg[u] = -hh * P.gam[j] * xn[u];   // row i = j: gamma_j X_{j+1}
+            lo[u] = -hh * P.gam[jp] * xp[u];  // row i = j-1: gamma_{j-1} X_{j-1}
+        }
+        for (int i = 0; i < n; i++) {
+            const double a = -hh * P.A[i * n + j];
+            double v0[NPT], v1[NPT];
+#pragma unroll
+            for (int u = 0; u < NPT; u++) {
+                v0[u] = a * cs[u];
+                v1[u] = a * cs[u + 1];
+            }
+            if (i == j) {
+#pragma unroll
+                for (int u = 0; u < NPT; u++) {
+                    v0[u] += dg[u] - 1.0;
+                    v1[u] += dg[u + 1] + 1.0;
+                }
+            }
+            if (i == jp) {
+#pragma unroll
+                for (int u = 0; u < NPT; u++) {
+                    v0[u] += lo[u];
+                    v1[u] += lo[u + 1];
+                }
+            }
+            double *o0 = jac + ((int64_t)i * T + 2 * j) * N + k;
+            double *o1 = o0 + N;
+            if constexpr (NPT == 2) {
+                st_nt2(o0, dbl2{v0[0], v0[1]});
+                st_nt2(o1, dbl2{v1[0], v1[1]});
+            } else {
+                st_nt(o0, v0[0]);
+                st_nt(o1, v1[0]);
+            }
+        }
+    }
+    for (int i = 0; i < n; i++) {
+        for (int l = 0; l < m; l++) {
+            const double v = -hh * P.B[i * m + l];
+            double *o0 = jac + ((int64_t)i * T + 2 * n + 2 * l) * N + k;
+            double *o1 = o0 + N;
+            if constexpr (NPT == 2) {
+                st_nt2(o0, dbl2{v, v});
+                st_nt2(o1, dbl2{v, v});
+            } else {
+                st_nt(o0, v);
+                st_nt(o1, v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hessian-of-Lagrangian values, one lane per node.  NB >= n is a compile-time
+// bound so the node multipliers stay in registers.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(kBlock) void hess_kernel(KP P, const double *__restrict__ z,
+                                                      const double *__restrict__ y, double sigma,
+                                                      double *__restrict__ hv)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1;
+    const double w = node_weight(P, k);
+    double yt[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        yt[i] = 0.0;
+        if (i < n) {
+            const double *yi = y + i * N + k;
+            double a = 0.0;
+            if (k >= 1) a += yi[-1];
+            if (k < P.N) a += yi[0];
+            yt[i] = a;
+        }
+    }
+    const double *X = z;
+    for (int j = 0; j < n; j++) {
+        const double sx = sin(X[j * N1 + k]);
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) s += yt[i] * P.A[i * n + j];
+        double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
+        if (n == 1) v -= P.h * yt[0] * P.gam[0];
+        st_nt(hv + j * N1 + k, v);
+    }
+    if (n >= 3) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_nt(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
+    } else if (n == 2) {
+        st_nt(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+    }
+    const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
+    for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
+}
+
+// ---------------------------------------------------------------------------
+// Defects.  Workgroup b evaluates the dynamics at nodes [b (B-1), b (B-1) + B)
+// (one node per lane, kept in LDS) and writes the B-1 intervals they close:
+// each node's F is computed once per workgroup, with one node of overlap.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__restrict__ z,
+                                                      double *__restrict__ c)
+{
+    __shared__ double Fs[NB][kBlock];
+    const int tid = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1;
+    const double *X = z;
+    const double *U = z + (int64_t)n * N1;
+    if (k <= N) {
+        double F[NB];
+#pragma unroll
+        for (int i = 0; i < NB; i++) F[i] = 0.0;
+        for (int j = 0; j < n; j++) {
+            const double s = sin(X[j * N1 + k]);
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) F[i] += P.A[i * n + j] * s;
+        }
+        for (int l = 0; l < m; l++) {
+            const double u = U[l * N1 + k];
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) F[i] += P.B[i * m + l] * u;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            if (i < n) {
+                const int p = (i + 1 == n) ? 0 : i + 1;
+                F[i] += P.gam[i] * X[i * N1 + k] * X[p * N1 + k];
+                Fs[i][tid] = F[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < kBlock - 1 && k < N) {
+        for (int i = 0; i < n; i++) {
+            const double *xi = X + i * N1 + k;
+            c[i * N + k] = (xi[1] - xi[0]) - P.hh * (Fs[i][tid] + Fs[i][tid + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient: g = 2 w_k q_j X_jk, 2 w_k r_l U_lk.  blockIdx.y = component.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__restrict__ z,
+                                                      double *__restrict__ g)
+{
+    const int comp = blockIdx.y;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    const double coef = comp < P.n ? P.q[comp] : P.r[comp - P.n];
+    const int64_t e = (int64_t)comp * P.N1 + k;
+    const double w = node_weight(P, k);
+    st_nt(g + e, 2.0 * w * coef * z[e]);
+}
+
+// ---------------------------------------------------------------------------
+// Objective: deterministic two-pass sum.  Pass 1: kObjBlocks workgroups, each
+// lane sums its nodes (grid stride) in order, then a fixed-shape tree over the
+// wavefront (DPP/permute shuffles) and over the 4 waves; pass 2: one
+// workgroup sums the partials in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ double block_sum(double v)
+{
+    __shared__ double ws[kBlock / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) ws[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; i++) t += ws[i];
+    }
+    return t;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double *__restrict__ z,
+                                                             double *__restrict__ partials)
+{
+    const int n = P.n, m = P.m;
+    const int64_t N1 = P.N1;
+    const double *X = z;
+    const double *U = z + (int64_t)n * N1;
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N1;
+         k += (int64_t)gridDim.x * kBlock) {
+        double s = 0.0;
+        for (int j = 0; j < n; j++) {
+            const double x = X[j * N1 + k];
+            s += P.q[j] * x * x;
+        }
+        for (int l = 0; l < m; l++) {
+            const double u = U[l * N1 + k];
+            s += P.r[l] * u * u;
+        }
+        acc += node_weight(P, (int)k) * s;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void obj_final_kernel(const double *__restrict__ partials,
+                                                           int count, double *__restrict__ obj)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) acc += partials[i];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) obj[0] = t;
+}
+
+// ---------------------------------------------------------------------------
+// KKT assembly.  Workgroups [0, gj) take constraint rows (one lane per row
+// (i, k), looping over its T slots: reads of jac and perm_j coalesce across
+// lanes, each lane's writes walk its own CSR row), and write the constraint
+// diagonals; workgroups [gj, gj + gh) take nodes and scatter the Hessian
+// slots, adding reg on the variable diagonals.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void assemble_kernel(
+    KP P, int gj, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
+    const int32_t *__restrict__ rowptr, const double *__restrict__ jv,
+    const double *__restrict__ hv, const double *__restrict__ reg, double *__restrict__ kkt)
+{
+    const int64_t N = P.N, N1 = P.N1;
+    const int64_t nvar = (int64_t)(P.n + P.m) * N1;
+    const uint32_t nnzk = (uint32_t)P.nnzk;  // slots outside [0, nnzk) are skipped
+    if ((int)blockIdx.x < gj) {
+        const uint32_t r = blockIdx.x * kBlock + threadIdx.x;  // constraint row i N + k
+        if (r >= (uint32_t)P.n * (uint32_t)P.N) return;
+        const uint32_t i = r / (uint32_t)P.N, k = r - i * (uint32_t)P.N;
+        const int64_t e0 = (int64_t)i * P.T * N + k;
+        const int32_t *pj = perm_j + e0;
+        const double *vj = jv + e0;
+        const int T = P.T;
+        int t = 0;
+        for (; t + 8 <= T; t += 8) {
+            int32_t p[8];
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                p[u] = __builtin_nontemporal_load(pj + (t + u) * N);
+                v[u] = __builtin_nontemporal_load(vj + (t + u) * N);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if ((uint32_t)p[u] < nnzk) kkt[p[u]] = v[u];
+        }
+        for (; t < T; t++) {
+            const int32_t q = pj[t * N];
+            if ((uint32_t)q < nnzk) kkt[q] = vj[t * N];
+        }
+        const int64_t d = nvar + r;
+        const uint32_t dq = (uint32_t)(rowptr[d + 1] - 1);
+        if (dq < nnzk) kkt[dq] = reg ? reg[d] : 0.0;
+    } else {
+        const int64_t k = (int64_t)(blockIdx.x - gj) * kBlock + threadIdx.x;
+        if (k >= N1) return;
+        const int n = P.n, np = P.npair, S = P.S;
+        for (int s = 0; s < S; s++) {
+            const int64_t e = (int64_t)s * N1 + k;
+            double v = hv[e];
+            if (reg && (s < n || s >= n + np)) {
+                const int64_t row = (s < n) ? (int64_t)s * N1 + k : (int64_t)(s - np) * N1 + k;
+                v += reg[row];
+            }
+            const uint32_t q = (uint32_t)perm_h[e];
+            if (q < nnzk) kkt[q] = v;
+        }
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+struct ocp_problem {
+    Dims d;
+    int device;
+    double *coef;      // device: A | B | gamma | q | r
+    double *partials;  // device: kObjBlocks doubles
+    KP kp;
+};
+
+static int hip_fail(const char *what, hipError_t e)
+{
+    return fail(OCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(what, e);
+    return OCP_OK;
+}
+
+static int check_handle(const ocp_problem *p, const char *what)
+{
+    if (!p) return fail(OCP_ERR_ARG, std::string(what) + ": problem handle is NULL");
+    return OCP_OK;
+}
+
+static unsigned blocks_for(int64_t count, int per_block)
+{
+    return (unsigned)((count + per_block - 1) / per_block);
+}
+
+extern "C" {
+
+int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B,
+               const double *gamma, const double *q, const double *r, ocp_problem **out)
+{
+    clear_error();
+    if (!out) return fail(OCP_ERR_ARG, "ocp_create: out is NULL");
+    *out = nullptr;
+    Dims d;
+    int rc = make_dims(N, n, m, &d);
+    if (rc) return rc;
+    if (!A || !gamma || !q || (m > 0 && (!B || !r)))
+        return fail(OCP_ERR_ARG, "ocp_create: coefficient pointer is NULL");
+    for (int64_t x = 0; x < (int64_t)n * n; x++)
+        if (!std::isfinite(A[x])) return fail(OCP_ERR_ARG, "ocp_create: A has a non-finite entry");
+
+    ocp_problem *p = new (std::nothrow) ocp_problem();
+    if (!p) return fail(OCP_ERR_ALLOC, "ocp_create: out of host memory");
+    p->d = d;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail("ocp_create: hipGetDevice", e); }
+    const size_t ncoef = (size_t)n * n + (size_t)n * m + 3 * (size_t)n + (size_t)m;
+    e = hipMalloc(&p->coef, ncoef * sizeof(double));
+    if (e != hipSuccess) { delete p; return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e)); }
+    e = hipMalloc(&p->partials, kObjBlocks * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipFree(p->coef);
+        delete p;
+        return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e));
+    }
+    double *host = new (std::nothrow) double[ncoef];
+    if (!host) { ocp_destroy(p); return fail(OCP_ERR_ALLOC, "ocp_create: out of host memory"); }
+    size_t o = 0;
+    std::memcpy(host + o, A, sizeof(double) * n * n); o += (size_t)n * n;
+    if (m) std::memcpy(host + o, B, sizeof(double) * n * m); o += (size_t)n * m;
+    std::memcpy(host + o, gamma, sizeof(double) * n); o += n;
+    std::memcpy(host + o, q, sizeof(double) * n); o += n;
+    if (m) std::memcpy(host + o, r, sizeof(double) * m);
+    e = hipMemcpy(p->coef, host, ncoef * sizeof(double), hipMemcpyHostToDevice);
+    delete[] host;
+    if (e != hipSuccess) { ocp_destroy(p); return hip_fail("ocp_create: hipMemcpy", e); }
+
+    KP &kp = p->kp;
+    kp.N = (int)d.N;
+    kp.N1 = (int)d.N1;
+    kp.n = n;
+    kp.m = m;
+    kp.npair = d.npair;
+    kp.T = d.T;
+    kp.S = d.S;
+    kp.nnzk = (int)d.nnzk;
+    kp.h = 1.0 / (double)d.N;
+    kp.hh = 0.5 * kp.h;
+    kp.A = p->coef;
+    kp.B = p->coef + (size_t)n * n;
+    kp.gam = kp.B + (size_t)n * m;
+    kp.q = kp.gam + n;
+    kp.r = kp.q + n;
+    *out = p;
+    return OCP_OK;
+}
+
+void ocp_destroy(ocp_problem *p)
+{
+    if (!p) return;
+    if (p->coef) (void)hipFree(p->coef);
+    if (p->partials) (void)hipFree(p->partials);
+    delete p;
+}
+
+int ocp_problem_sizes(const ocp_problem *p, ocp_sizes_t *out)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_problem_sizes")) return rc;
+    if (!out) return fail(OCP_ERR_ARG, "ocp_problem_sizes: out is NULL");
+    to_public(p->d, out);
+    return OCP_OK;
+}
+
+int ocp_eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_obj")) return rc;
+    if (!z || !obj) return fail(OCP_ERR_ARG, "ocp_eval_obj: null array");
+    const unsigned g = (unsigned)std::min<int64_t>(kObjBlocks, blocks_for(p->d.N1, kBlock));
+    hipLaunchKernelGGL(obj_partial_kernel, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
+    if (int rc = check_launch("ocp_eval_obj")) return rc;
+    hipLaunchKernelGGL(obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, (int)g, obj);
+    return check_launch("ocp_eval_obj");
+}
+
+int ocp_eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_grad")) return rc;
+    if (!z || !g) return fail(OCP_ERR_ARG, "ocp_eval_grad: null array");
+    dim3 grid(blocks_for(p->d.N1, kBlock), p->d.n + p->d.m);
+    hipLaunchKernelGGL(grad_kernel, grid, dim3(kBlock), 0, stream, p->kp, z, g);
+    return check_launch("ocp_eval_grad");
+}
+
+int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_cons")) return rc;
+    if (!z || !c) return fail(OCP_ERR_ARG, "ocp_eval_cons: null array");
+    const unsigned g = blocks_for(p->d.N, kBlock - 1);
+    const int n = p->d.n;
+    if (n <= 4) hipLaunchKernelGGL(cons_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    else if (n <= 8) hipLaunchKernelGGL(cons_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    else if (n <= 16) hipLaunchKernelGGL(cons_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    else hipLaunchKernelGGL(cons_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    return check_launch("ocp_eval_cons");
+}
+
+int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_jac")) return rc;
+    if (!z || !jvals) return fail(OCP_ERR_ARG, "ocp_eval_jac: null array");
+    // Paired 16-byte stores need every slot row 16-byte aligned: N even and
+    // the output 16-byte aligned.
+    const bool pair = (p->d.N % 2 == 0) && ((uintptr_t)jvals % 16 == 0);
+    if (pair) {
+        hipLaunchKernelGGL(jac_kernel<2>, dim3(blocks_for(p->d.N / 2, kBlock)), dim3(kBlock), 0,
+                           stream, p->kp, z, jvals);
+    } else {
+        hipLaunchKernelGGL(jac_kernel<1>, dim3(blocks_for(p->d.N, kBlock)), dim3(kBlock), 0,
+                           stream, p->kp, z, jvals);
+    }
+    return check_launch("ocp_eval_jac");
+}
+
+int ocp_eval_hess(const ocp_problem *p, const double *z, const double *y, double sigma,
+                  double *hvals, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_hess")) return rc;
+    if (!z || !y || !hvals) return fail(OCP_ERR_ARG, "ocp_eval_hess: null array");
+    if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_hess: sigma is not finite");
+    const unsigned g = blocks_for(p->d.N1, kBlock);
+    const int n = p->d.n;
+    if (n <= 4) hipLaunchKernelGGL(hess_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
+    else if (n <= 8) hipLaunchKernelGGL(hess_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
+    else if (n <= 16) hipLaunchKernelGGL(hess_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
+    else hipLaunchKernelGGL(hess_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
+    return check_launch("ocp_eval_hess");
+}
+
+int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,
+                     const int32_t *rowptr, const double *jvals, const double *hvals,
+                     const double *reg, double *kkt, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_assemble_kkt")) return rc;
+    if (!perm_j || !perm_h || !rowptr || !jvals || !hvals || !kkt)
+        return fail(OCP_ERR_ARG, "ocp_assemble_kkt: null array");
+    const unsigned gj = blocks_for(p->d.ncon, kBlock);
+    const unsigned gh = blocks_for(p->d.N1, kBlock);
+    hipLaunchKernelGGL(assemble_kernel, dim3(gj + gh), dim3(kBlock), 0, stream, p->kp, (int)gj,
+                       perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
+    return check_launch("ocp_assemble_kkt");
+}
+
+}  // extern "C"

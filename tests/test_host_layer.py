@@ -1,0 +1,120 @@
+"""The library's host side, without a GPU: it loads, exports every declared
+entry point, validates arguments before any HIP call, and its closed-form
+pattern and KKT index builders equal the oracle's generic sort-based build
+bit for bit."""
+from __future__ import annotations
+
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import paper_2510_03932_amd as ocp
+
+GRID = [(1, 1, 0), (1, 1, 1), (2, 1, 0), (3, 2, 0), (2, 2, 1), (5, 3, 0), (4, 3, 1), (3, 4, 2),
+        (7, 5, 3), (10, 6, 3), (1, 16, 8), (33, 16, 8), (17, 32, 32), (1000, 4, 2), (999, 8, 4)]
+
+
+def test_library_exports_every_declared_symbol():
+    L = ocp.lib()
+    names = ocp.exported_names()
+    assert len(names) == 13, names
+    for name in names:
+        assert hasattr(L, name), name
+    text = open(ocp.HEADER).read()
+    # every entry point documents its arguments in a comment right above it
+    for name in names:
+        assert re.search(r"\*/\s*\n(?:[^\n]*\n)?[^\n]*\b" + name + r"\s*\(", text), name
+
+
+@pytest.mark.parametrize("N,n,m", GRID)
+def test_sizes_match_oracle(orc, N, n, m):
+    s = ocp.sizes(N, n, m)
+    o = orc.sizes(N, n, m)
+    for k in ("nvar", "ncon", "nnzj", "nnzh", "dim", "npair", "T", "S"):
+        assert s[k] == o[k], k
+    assert s["nnzk"] == o["nnzh"] + o["nnzj"] + o["ncon"]
+
+
+@pytest.mark.parametrize("N,n,m", GRID)
+def test_pattern_bit_exact(orc, N, n, m):
+    got = ocp.pattern(N, n, m)
+    want = orc.pattern(N, n, m)
+    for g, w in zip(got, want):
+        assert g.dtype == np.int32
+        assert np.array_equal(g, w)
+
+
+@pytest.mark.parametrize("N,n,m", GRID)
+def test_kkt_bit_exact(orc, N, n, m):
+    got = ocp.kkt_pattern(N, n, m)
+    want = orc.kkt(N, n, m)
+    for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h"), got, want):
+        assert g.dtype == np.int32
+        assert np.array_equal(g, w), name
+
+
+@pytest.mark.slow
+def test_kkt_bit_exact_ipm_loop_size(orc):
+    """The 1e5-interval, n = 8, m = 4 workload: 2.2e7 KKT entries."""
+    N, n, m = 100_000, 8, 4
+    got = ocp.kkt_pattern(N, n, m)
+    want = orc.kkt(N, n, m)
+    for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h"), got, want):
+        assert np.array_equal(g, w), name
+
+
+def test_kkt_partial_outputs():
+    N, n, m = 50, 3, 1
+    full = ocp.kkt_pattern(N, n, m)
+    part = ocp.kkt_pattern(N, n, m, rowptr=False, colind=False)
+    assert part[0] is None and part[1] is None
+    assert np.array_equal(part[2], full[2]) and np.array_equal(part[3], full[3])
+
+
+@pytest.mark.parametrize("N,n,m,code", [
+    (0, 4, 2, ocp.OCP_ERR_ARG), (-5, 4, 2, ocp.OCP_ERR_ARG), (10, 0, 2, ocp.OCP_ERR_ARG),
+    (10, 33, 2, ocp.OCP_ERR_ARG), (10, 4, -1, ocp.OCP_ERR_ARG), (10, 4, 33, ocp.OCP_ERR_ARG),
+    (2**31, 1, 0, ocp.OCP_ERR_OVERFLOW), (10_000_000, 16, 8, ocp.OCP_ERR_OVERFLOW),
+    (2_700_000, 16, 8, ocp.OCP_ERR_OVERFLOW),
+])
+def test_size_errors(N, n, m, code):
+    with pytest.raises(ocp.OcpError) as e:
+        ocp.sizes(N, n, m)
+    assert e.value.code == code
+    assert str(e.value).strip()
+    # the builders validate on their own, before touching any output
+    assert ocp.lib().ocp_build_kkt(N, n, m, None, None, None, None) == code
+    assert ocp.lib().ocp_build_pattern(N, n, m, None, None, None, None) == code
+
+
+def test_largest_workload_fits_int32():
+    s = ocp.sizes(1_000_000, 16, 8)
+    assert s["nnzk"] == 824_000_040 and s["nnzj"] == 768_000_000 and s["nnzh"] == 40_000_040
+    assert s["dim"] == 40_000_024
+
+
+def test_create_rejects_bad_arguments_before_any_hip_call():
+    """These fail validation on the host, so they are safe without a GPU."""
+    L = ocp.lib()
+    h = ctypes.c_void_p()
+    A = np.zeros((4, 4))
+    g = np.zeros(4)
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    assert L.ocp_create(0, 4, 2, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert b"N must be" in L.ocp_last_error()
+    assert L.ocp_create(10, 4, 2, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert b"NULL" in L.ocp_last_error()
+    assert L.ocp_create(10, 4, 0, None, None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_create(10, 4, 0, ptr(A), None, ptr(g), ptr(g), None, None) == ocp.OCP_ERR_ARG
+    bad = A.copy()
+    bad[1, 2] = np.nan
+    assert L.ocp_create(10, 4, 0, ptr(bad), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert h.value is None
+    # every evaluation rejects a NULL handle
+    for name in ("ocp_eval_obj", "ocp_eval_grad", "ocp_eval_cons", "ocp_eval_jac"):
+        assert getattr(L, name)(None, None, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_eval_hess(None, None, None, 1.0, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_assemble_kkt(None, None, None, None, None, None, None, None, None) == ocp.OCP_ERR_ARG
+    L.ocp_destroy(None)  # NULL-safe
