@@ -31,7 +31,7 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 namespace {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 waves)
-constexpr int kObjBlocks = 1024;     // fixed partial count of the objective sum
+constexpr int kObjBlocks = 4096;     // most partials of the objective sum
 
 // Kernel-side view of a problem: sizes and device coefficient pointers.
 struct KP {
@@ -152,28 +152,33 @@ __global__ __launch_bounds__(kBlock) void hess_kernel(KP P, const double *__rest
     const int n = P.n, m = P.m;
     const int64_t N = P.N, N1 = P.N1;
     const double w = node_weight(P, k);
-    double yt[NB];
+    // all loads first (state and both multipliers of every component)
+    double x[NB], yl[NB], yr[NB];
 #pragma unroll
     for (int i = 0; i < NB; i++) {
-        yt[i] = 0.0;
+        x[i] = yl[i] = yr[i] = 0.0;
         if (i < n) {
+            x[i] = z[i * N1 + k];
             const double *yi = y + i * N + k;
-            double a = 0.0;
-            if (k >= 1) a += yi[-1];
-            if (k < P.N) a += yi[0];
-            yt[i] = a;
+            if (k >= 1) yl[i] = yi[-1];
+            if (k < P.N) yr[i] = yi[0];
         }
     }
-    const double *X = z;
-    for (int j = 0; j < n; j++) {
-        const double sx = sin(X[j * N1 + k]);
-        double s = 0.0;
+    double yt[NB];
 #pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < n) s += yt[i] * P.A[i * n + j];
-        double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
-        if (n == 1) v -= P.h * yt[0] * P.gam[0];
-        st_nt(hv + j * N1 + k, v);
+    for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        if (j < n) {
+            const double sx = sin(x[j]);
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) s += yt[i] * P.A[i * n + j];
+            double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
+            if (n == 1) v -= P.h * yt[0] * P.gam[0];
+            st_nt(hv + j * N1 + k, v);
+        }
     }
     if (n >= 3) {
 #pragma unroll
@@ -187,30 +192,39 @@ __global__ __launch_bounds__(kBlock) void hess_kernel(KP P, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Defects.  Workgroup b evaluates the dynamics at nodes [b (B-1), b (B-1) + B)
-// (one node per lane, kept in LDS) and writes the B-1 intervals they close:
-// each node's F is computed once per workgroup, with one node of overlap.
+// Defects.  Workgroup b evaluates the dynamics at nodes [b (B-1), b (B-1) + B),
+// one node per lane, and writes the B-1 intervals they close (one node of
+// overlap between workgroups).  With
+//   c_ik = (X_{i,k+1} - hh F_i(k+1)) - (X_ik + hh F_i(k)),
+// lane k keeps X_ik + hh F_i(k) in registers and publishes X_ik - hh F_i(k)
+// in LDS for lane k-1, so every state value is read from HBM once.
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__restrict__ z,
                                                       double *__restrict__ c)
 {
-    __shared__ double Fs[NB][kBlock];
+    __shared__ double Ms[NB][kBlock];
     const int tid = threadIdx.x;
     const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
     const int n = P.n, m = P.m;
     const int64_t N = P.N, N1 = P.N1;
-    const double *X = z;
     const double *U = z + (int64_t)n * N1;
+    double Pk[NB];
     if (k <= N) {
-        double F[NB];
+        double x[NB], F[NB];
 #pragma unroll
-        for (int i = 0; i < NB; i++) F[i] = 0.0;
-        for (int j = 0; j < n; j++) {
-            const double s = sin(X[j * N1 + k]);
+        for (int i = 0; i < NB; i++) {
+            x[i] = (i < n) ? z[i * N1 + k] : 0.0;
+            F[i] = 0.0;
+        }
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) F[i] += P.A[i * n + j] * s;
+        for (int j = 0; j < NB; j++) {
+            if (j < n) {
+                const double s = sin(x[j]);
+#pragma unroll
+                for (int i = 0; i < NB; i++)
+                    if (i < n) F[i] += P.A[i * n + j] * s;
+            }
         }
         for (int l = 0; l < m; l++) {
             const double u = U[l * N1 + k];
@@ -221,18 +235,18 @@ __global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__rest
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             if (i < n) {
-                const int p = (i + 1 == n) ? 0 : i + 1;
-                F[i] += P.gam[i] * X[i * N1 + k] * X[p * N1 + k];
-                Fs[i][tid] = F[i];
+                const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
+                F[i] += P.gam[i] * x[i] * xp;
+                Ms[i][tid] = x[i] - P.hh * F[i];
+                Pk[i] = x[i] + P.hh * F[i];
             }
         }
     }
     __syncthreads();
     if (tid < kBlock - 1 && k < N) {
-        for (int i = 0; i < n; i++) {
-            const double *xi = X + i * N1 + k;
-            c[i * N + k] = (xi[1] - xi[0]) - P.hh * (Fs[i][tid] + Fs[i][tid + 1]);
-        }
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_nt(c + i * N + k, Ms[i][tid + 1] - Pk[i]);
     }
 }
 
@@ -252,10 +266,11 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Objective: deterministic two-pass sum.  Pass 1: kObjBlocks workgroups, each
-// lane sums its nodes (grid stride) in order, then a fixed-shape tree over the
-// wavefront (DPP/permute shuffles) and over the 4 waves; pass 2: one
-// workgroup sums the partials in a fixed order.
+// Objective: deterministic two-pass sum.  Pass 1: min(ceil((N+1)/256), 4096)
+// workgroups (so one node per lane up to 1M nodes), each lane summing its
+// nodes in order, then a fixed-shape tree over the wavefront (cross-lane
+// shuffles) and over the 4 waves; pass 2: one workgroup sums the partials in a
+// fixed order.  The grid depends only on N, so the result is reproducible.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -282,21 +297,16 @@ __device__ double block_sum(double v)
 __global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double *__restrict__ z,
                                                              double *__restrict__ partials)
 {
-    const int n = P.n, m = P.m;
+    const int n = P.n, nc = P.n + P.m;
     const int64_t N1 = P.N1;
-    const double *X = z;
-    const double *U = z + (int64_t)n * N1;
     double acc = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N1;
          k += (int64_t)gridDim.x * kBlock) {
         double s = 0.0;
-        for (int j = 0; j < n; j++) {
-            const double x = X[j * N1 + k];
-            s += P.q[j] * x * x;
-        }
-        for (int l = 0; l < m; l++) {
-            const double u = U[l * N1 + k];
-            s += P.r[l] * u * u;
+#pragma unroll 8
+        for (int c = 0; c < nc; c++) {
+            const double v = z[c * N1 + k];
+            s += (c < n ? P.q[c] : P.r[c - n]) * v * v;
         }
         acc += node_weight(P, (int)k) * s;
     }
@@ -314,48 +324,102 @@ __global__ __launch_bounds__(kBlock) void obj_final_kernel(const double *__restr
 }
 
 // ---------------------------------------------------------------------------
-// KKT assembly.  Workgroups [0, gj) take constraint rows (one lane per row
-// (i, k), looping over its T slots: reads of jac and perm_j coalesce across
-// lanes, each lane's writes walk its own CSR row), and write the constraint
-// diagonals; workgroups [gj, gj + gh) take nodes and scatter the Hessian
-// slots, adding reg on the variable diagonals.
+// KKT assembly.
+//
+// Jacobian part: the COO values are slot-major (node fastest) while the CSR
+// rows of the constraint block are row-major, so the scatter is a transpose.
+// Workgroup g < gj owns a tile of up to KT consecutive constraint rows of one
+// state component i (intervals k0 .. k0+kn-1).  It reads the tile's T slot rows
+// coalesced (one wavefront per slot row), drops each value into LDS at
+// perm_j[e] - base, where [base, base + ext) is the tile's CSR range from
+// rowptr, adds the tile's diagonals, and then writes the whole range with
+// contiguous full-line stores.  A slot outside the range is stored directly.
+// If the values that landed in LDS do not cover the range exactly (a slot map
+// other than the closed-form one), the tile is redone with direct stores, so
+// the result is the same for any injective slot map.
+//
+// Hessian part: workgroups gj.. take nodes and scatter the S Hessian slots
+// directly (rows of 1 to 3 entries, close to contiguous across lanes), adding
+// reg on the variable diagonals in the same IEEE add.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void assemble_kernel(
-    KP P, int gj, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
+    KP P, int gj, int KT, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
     const int32_t *__restrict__ rowptr, const double *__restrict__ jv,
     const double *__restrict__ hv, const double *__restrict__ reg, double *__restrict__ kkt)
 {
+    extern __shared__ double tile[];
+    __shared__ int filled;
     const int64_t N = P.N, N1 = P.N1;
     const int64_t nvar = (int64_t)(P.n + P.m) * N1;
     const uint32_t nnzk = (uint32_t)P.nnzk;  // slots outside [0, nnzk) are skipped
+    const int T = P.T;
     if ((int)blockIdx.x < gj) {
-        const uint32_t r = blockIdx.x * kBlock + threadIdx.x;  // constraint row i N + k
-        if (r >= (uint32_t)P.n * (uint32_t)P.N) return;
-        const uint32_t i = r / (uint32_t)P.N, k = r - i * (uint32_t)P.N;
-        const int64_t e0 = (int64_t)i * P.T * N + k;
-        const int32_t *pj = perm_j + e0;
-        const double *vj = jv + e0;
-        const int T = P.T;
-        int t = 0;
-        for (; t + 8 <= T; t += 8) {
-            int32_t p[8];
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; u++) {
-                p[u] = __builtin_nontemporal_load(pj + (t + u) * N);
-                v[u] = __builtin_nontemporal_load(vj + (t + u) * N);
+        const int tiles_per_i = (P.N + KT - 1) / KT;
+        const int i = blockIdx.x / tiles_per_i;
+        const int k0 = (blockIdx.x - i * tiles_per_i) * KT;
+        const int kn = min(KT, P.N - k0);
+        const int64_t r0 = nvar + (int64_t)i * N + k0;  // first KKT row of the tile
+        const int32_t base = rowptr[r0];
+        const int32_t ext = (int32_t)((uint32_t)rowptr[r0 + kn] - (uint32_t)base);
+        const int cap = KT * (T + 1);
+        const bool staged = ext >= 0 && ext <= cap;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (threadIdx.x == 0) filled = 0;
+        if (staged)
+            for (int x = threadIdx.x; x < ext; x += kBlock) tile[x] = 0.0;
+        __syncthreads();
+        int mine = 0;
+        const int64_t e0 = (int64_t)i * T * N + k0;
+        // lanes map to intervals; with KT = 32 two slot rows share a wavefront
+        const int kl = lane % KT;
+        const int sub = lane / KT, subs = 64 / KT;
+        if (kl < kn) {
+            for (int t = wave * subs + sub; t < T; t += 4 * subs) {
+                const int64_t e = e0 + (int64_t)t * N + kl;
+                const int32_t q = __builtin_nontemporal_load(perm_j + e);
+                const double v = __builtin_nontemporal_load(jv + e);
+                const uint32_t loc = (uint32_t)q - (uint32_t)base;
+                if (staged && loc < (uint32_t)ext) {
+                    tile[loc] = v;
+                    mine++;
+                } else if ((uint32_t)q < nnzk) {
+                    kkt[q] = v;
+                }
             }
-#pragma unroll
-            for (int u = 0; u < 8; u++)
-                if ((uint32_t)p[u] < nnzk) kkt[p[u]] = v[u];
         }
-        for (; t < T; t++) {
-            const int32_t q = pj[t * N];
-            if ((uint32_t)q < nnzk) kkt[q] = vj[t * N];
+        if (threadIdx.x < kn) {
+            const int64_t d = r0 + threadIdx.x;
+            const int32_t q = rowptr[d + 1] - 1;
+            const double v = reg ? reg[d] : 0.0;
+            const uint32_t loc = (uint32_t)q - (uint32_t)base;
+            if (staged && loc < (uint32_t)ext) {
+                tile[loc] = v;
+                mine++;
+            } else if ((uint32_t)q < nnzk) {
+                kkt[q] = v;
+            }
         }
-        const int64_t d = nvar + r;
-        const uint32_t dq = (uint32_t)(rowptr[d + 1] - 1);
-        if (dq < nnzk) kkt[dq] = reg ? reg[d] : 0.0;
+        if (mine) atomicAdd(&filled, mine);
+        __syncthreads();
+        if (!staged) return;
+        if (filled == ext) {
+            double *out = kkt + base;
+            for (int x = threadIdx.x; x < ext; x += kBlock) st_nt(out + x, tile[x]);
+        } else {
+            // not an exact cover: store this tile's values directly
+            if (kl < kn) {
+                for (int t = wave * subs + sub; t < T; t += 4 * subs) {
+                    const int64_t e = e0 + (int64_t)t * N + kl;
+                    const int32_t q = perm_j[e];
+                    if ((uint32_t)q < nnzk) kkt[q] = jv[e];
+                }
+            }
+            if (threadIdx.x < kn) {
+                const int64_t d = r0 + threadIdx.x;
+                const int32_t q = rowptr[d + 1] - 1;
+                if ((uint32_t)q < nnzk) kkt[q] = reg ? reg[d] : 0.0;
+            }
+        }
     } else {
         const int64_t k = (int64_t)(blockIdx.x - gj) * kBlock + threadIdx.x;
         if (k >= N1) return;
@@ -567,10 +631,15 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
     if (int rc = check_handle(p, "ocp_assemble_kkt")) return rc;
     if (!perm_j || !perm_h || !rowptr || !jvals || !hvals || !kkt)
         return fail(OCP_ERR_ARG, "ocp_assemble_kkt: null array");
-    const unsigned gj = blocks_for(p->d.ncon, kBlock);
+    // Tile height: 64 constraint rows (one per lane) while the staged CSR
+    // range fits in 64 KiB of LDS, else 32.
+    const int KT = (64 * (p->d.T + 1) * 8 <= 64 * 1024) ? 64 : 32;
+    const unsigned tiles_per_i = (unsigned)((p->d.N + KT - 1) / KT);
+    const unsigned gj = tiles_per_i * (unsigned)p->d.n;
     const unsigned gh = blocks_for(p->d.N1, kBlock);
-    hipLaunchKernelGGL(assemble_kernel, dim3(gj + gh), dim3(kBlock), 0, stream, p->kp, (int)gj,
-                       perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
+    const size_t lds = (size_t)KT * (p->d.T + 1) * sizeof(double);
+    hipLaunchKernelGGL(assemble_kernel, dim3(gj + gh), dim3(kBlock), lds, stream, p->kp, (int)gj,
+                       KT, perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
     return check_launch("ocp_assemble_kkt");
 }
 
