@@ -27,6 +27,7 @@
 using namespace ocp;
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef int32_t int2v __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -59,11 +60,14 @@ __device__ __forceinline__ void st_nt2(double *p, dbl2 v)
 }
 
 // ---------------------------------------------------------------------------
-// Jacobian values.  One lane per NPT consecutive intervals (NPT = 2 stores a
-// 16-byte pair per lane, so one store instruction of a wavefront covers 1 KiB
-// of one slot row).  Loop: state column j outer (2 cosines per node), row i
-// inner; the bilinear term touches only rows i = j (partner X_{j+1}) and
-// i = j-1 (factor X_{j-1}).  Control slots are the constant -hh B_il.
+// Jacobian values.  2-D grid: blockIdx.y = j < n takes state column j (slots
+// 2j, 2j+1 of every row i), blockIdx.y = n + l takes control column l (slots
+// 2n+2l, 2n+2l+1, the constant -hh B_il).  One lane per NPT consecutive
+// intervals: NPT = 2 stores a 16-byte pair per lane, so a wavefront store is
+// one contiguous KiB of a slot row.  Per state column a lane needs NPT+1
+// cosines; the bilinear term touches only rows i = j (partner X_{j+1}) and
+// i = j-1 (factor X_{j-1}).  Many short lanes (a grid of (N/NPT) x (n+m)) keep
+// the write stream at the device's streaming-store rate.
 // ---------------------------------------------------------------------------
 template <int NPT>
 __global__ __launch_bounds__(kBlock) void jac_kernel(KP P, const double *__restrict__ z,
@@ -71,17 +75,16 @@ __global__ __launch_bounds__(kBlock) void jac_kernel(KP P, const double *__restr
 {
     const int64_t k = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPT;
     if (k >= P.N) return;
-    const int n = P.n, m = P.m, T = P.T;
+    const int n = P.n, T = P.T;
     const int64_t N = P.N, N1 = P.N1;
     const double hh = P.hh;
-    const double *X = z;
-
-    for (int j = 0; j < n; j++) {
+    const int j = blockIdx.y;
+    if (j < n) {
         const int jn = (j + 1 == n) ? 0 : j + 1;
         const int jp = (j == 0) ? n - 1 : j - 1;
-        const double *xj = X + j * N1 + k;
-        const double *xn = X + jn * N1 + k;
-        const double *xp = X + jp * N1 + k;
+        const double *xj = z + j * N1 + k;
+        const double *xn = z + jn * N1 + k;
+        const double *xp = z + jp * N1 + k;
         double cs[NPT + 1], dg[NPT + 1], lo[NPT + 1];
 #pragma unroll
         for (int u = 0; u <= NPT; u++) {
@@ -121,9 +124,9 @@ __global__ __launch_bounds__(kBlock) void jac_kernel(KP P, const double *__restr
                 st_nt(o1, v1[0]);
             }
         }
-    }
-    for (int i = 0; i < n; i++) {
-        for (int l = 0; l < m; l++) {
+    } else {
+        const int l = j - n, m = P.m;
+        for (int i = 0; i < n; i++) {
             const double v = -hh * P.B[i * m + l];
             double *o0 = jac + ((int64_t)i * T + 2 * n + 2 * l) * N + k;
             double *o1 = o0 + N;
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void obj_final_kernel(const double *__restr
 // reg on the variable diagonals in the same IEEE add.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void assemble_kernel(
-    KP P, int gj, int KT, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
+    KP P, int gj, int KT, bool vec_ok, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
     const int32_t *__restrict__ rowptr, const double *__restrict__ jv,
     const double *__restrict__ hv, const double *__restrict__ reg, double *__restrict__ kkt)
 {
@@ -370,27 +373,14 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
         __syncthreads();
         int mine = 0;
         const int64_t e0 = (int64_t)i * T * N + k0;
-        // lanes map to intervals; with KT = 32 two slot rows share a wavefront
-        const int kl = lane % KT;
-        const int sub = lane / KT, subs = 64 / KT;
-        if (kl < kn) {
-            for (int t = wave * subs + sub; t < T; t += 4 * subs) {
-                const int64_t e = e0 + (int64_t)t * N + kl;
-                const int32_t q = __builtin_nontemporal_load(perm_j + e);
-                const double v = __builtin_nontemporal_load(jv + e);
-                const uint32_t loc = (uint32_t)q - (uint32_t)base;
-                if (staged && loc < (uint32_t)ext) {
-                    tile[loc] = v;
-                    mine++;
-                } else if ((uint32_t)q < nnzk) {
-                    kkt[q] = v;
-                }
-            }
-        }
-        if (threadIdx.x < kn) {
-            const int64_t d = r0 + threadIdx.x;
-            const int32_t q = rowptr[d + 1] - 1;
-            const double v = reg ? reg[d] : 0.0;
+        // Each lane takes two adjacent intervals of a slot row (16-byte value
+        // and 8-byte slot loads when aligned), so KT/2 lanes cover a slot row
+        // and a wavefront covers 128/KT slot rows per pass.
+        const int lanes_per_row = KT / 2;
+        const int rows_per_wave = 64 / lanes_per_row;
+        const int kl = (lane % lanes_per_row) * 2;
+        const int sub = lane / lanes_per_row;
+        auto place = [&](int32_t q, double v) {
             const uint32_t loc = (uint32_t)q - (uint32_t)base;
             if (staged && loc < (uint32_t)ext) {
                 tile[loc] = v;
@@ -398,6 +388,24 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
             } else if ((uint32_t)q < nnzk) {
                 kkt[q] = v;
             }
+        };
+        if (kl < kn) {
+            for (int t = wave * rows_per_wave + sub; t < T; t += 4 * rows_per_wave) {
+                const int64_t e = e0 + (int64_t)t * N + kl;
+                if (vec_ok && kl + 1 < kn && (e & 1) == 0) {
+                    const int2v q = __builtin_nontemporal_load(reinterpret_cast<const int2v *>(perm_j + e));
+                    const dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(jv + e));
+                    place(q.x, v.x);
+                    place(q.y, v.y);
+                } else {
+                    place(perm_j[e], jv[e]);
+                    if (kl + 1 < kn) place(perm_j[e + 1], jv[e + 1]);
+                }
+            }
+        }
+        if (threadIdx.x < kn) {
+            const int64_t d = r0 + threadIdx.x;
+            place(rowptr[d + 1] - 1, reg ? reg[d] : 0.0);
         }
         if (mine) atomicAdd(&filled, mine);
         __syncthreads();
@@ -408,10 +416,12 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
         } else {
             // not an exact cover: store this tile's values directly
             if (kl < kn) {
-                for (int t = wave * subs + sub; t < T; t += 4 * subs) {
+                for (int t = wave * rows_per_wave + sub; t < T; t += 4 * rows_per_wave) {
                     const int64_t e = e0 + (int64_t)t * N + kl;
-                    const int32_t q = perm_j[e];
-                    if ((uint32_t)q < nnzk) kkt[q] = jv[e];
+                    for (int u = 0; u < 2 && kl + u < kn; u++) {
+                        const int32_t q = perm_j[e + u];
+                        if ((uint32_t)q < nnzk) kkt[q] = jv[e + u];
+                    }
                 }
             }
             if (threadIdx.x < kn) {
@@ -597,11 +607,12 @@ int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream
     // Paired 16-byte stores need every slot row 16-byte aligned: N even and
     // the output 16-byte aligned.
     const bool pair = (p->d.N % 2 == 0) && ((uintptr_t)jvals % 16 == 0);
+    const unsigned cols = (unsigned)(p->d.n + p->d.m);
     if (pair) {
-        hipLaunchKernelGGL(jac_kernel<2>, dim3(blocks_for(p->d.N / 2, kBlock)), dim3(kBlock), 0,
-                           stream, p->kp, z, jvals);
+        hipLaunchKernelGGL(jac_kernel<2>, dim3(blocks_for(p->d.N / 2, kBlock), cols), dim3(kBlock),
+                           0, stream, p->kp, z, jvals);
     } else {
-        hipLaunchKernelGGL(jac_kernel<1>, dim3(blocks_for(p->d.N, kBlock)), dim3(kBlock), 0,
+        hipLaunchKernelGGL(jac_kernel<1>, dim3(blocks_for(p->d.N, kBlock), cols), dim3(kBlock), 0,
                            stream, p->kp, z, jvals);
     }
     return check_launch("ocp_eval_jac");
@@ -638,8 +649,10 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
     const unsigned gj = tiles_per_i * (unsigned)p->d.n;
     const unsigned gh = blocks_for(p->d.N1, kBlock);
     const size_t lds = (size_t)KT * (p->d.T + 1) * sizeof(double);
+    // paired loads need 16-byte aligned values and 8-byte aligned slots
+    const bool vec_ok = ((uintptr_t)jvals % 16 == 0) && ((uintptr_t)perm_j % 8 == 0);
     hipLaunchKernelGGL(assemble_kernel, dim3(gj + gh), dim3(kBlock), lds, stream, p->kp, (int)gj,
-                       KT, perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
+                       KT, vec_ok, perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
     return check_launch("ocp_assemble_kkt");
 }
 

@@ -87,3 +87,16 @@ DIFF = (200_000, 8, 4)          # Lagrangian differentiation workload
 def batched_sizes(count: int = 512, lo: int = 200, hi: int = 20000, seed: int = 0) -> np.ndarray:
     """Per-instance interval counts N_b ~ U{lo..hi} for the batched workload."""
     return np.random.default_rng(seed).integers(lo, hi + 1, count)
+
+
+def device_point(torch, device, N: int, n: int, m: int, seed: int):
+    """A fresh evaluation point drawn on the GPU with torch's generator:
+    z = [X ~ N(0,1) (n, N+1) | U ~ U(-1,1) (m, N+1)] and y ~ N(0,1) (n*N),
+    drawn in that order from ``torch.Generator(device).manual_seed(seed)``."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = dict(dtype=torch.float64, device=device)
+    X = torch.randn(n * (N + 1), generator=g, **f64)
+    U = torch.rand(m * (N + 1), generator=g, **f64) * 2.0 - 1.0
+    y = torch.randn(n * N, generator=g, **f64)
+    return torch.cat([X, U]), y

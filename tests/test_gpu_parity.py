@@ -219,14 +219,10 @@ def test_ipm_loop_workload_full_arrays(ocp):
     prob = ocp.Problem.from_instance(inst, dev)
     rowptr, _, perm_j, perm_h = ocp.kkt_pattern(N, n, m, colind=False)
     pj, ph, rp = (torch.from_numpy(a).to(dev) for a in (perm_j, perm_h, rowptr))
-    rng = np.random.default_rng(1000)
-    for it in range(2):  # two fresh evaluation points, as inside an interior-point loop
-        if it:
-            X, U, y = synth.point(rng, N, n, m)
-            inst.z = np.concatenate([X.ravel(), U.ravel()])
-            inst.y = y.ravel().copy()
-        z = torch.from_numpy(inst.z).to(dev)
-        y = torch.from_numpy(inst.y).to(dev)
+    for it in (0, 49):  # first and last point of the 50-iteration loop the benchmark times
+        z, y = synth.device_point(torch, dev, N, n, m, 1000 + it)
+        inst.z = z.cpu().numpy()
+        inst.y = y.cpu().numpy()
         c, jv, hv = prob.cons(z), prob.jac(z), prob.hess(z, y, 1.0)
         reg = torch.linspace(-1.0, 1.0, prob.sizes["dim"], dtype=torch.float64, device=dev)
         kkt = prob.assemble_kkt(pj, ph, rp, jv, hv, reg)
