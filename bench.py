@@ -1,6 +1,6 @@
 """Benchmark of the evaluation path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched]
 
 Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
 controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
@@ -126,12 +126,76 @@ def ipm_loop(torch, ocp, synth, iters=50):
             "note": "J+H values fit in the 256 MiB Infinity Cache"}
 
 
+def batched(torch, ocp, synth, reps=10):
+    """The batched workload: 512 instances, N_b ~ U{200..20000}, n = 6, m = 3,
+    Jacobian + Hessian values of all of them.  Four ways: one single-instance
+    launch per instance and evaluation (1024 launches), the same captured in a
+    HIP graph, the persistent launch over the tile list (after autotuning its
+    tile shape), and the persistent launch replayed from a graph."""
+    import tempfile
+    insts = synth.make_batch(512, 6, 3, seed=0)
+    dev = torch.device("cuda", 0)
+    batch = ocp.Batch.from_instances(insts, dev)
+    zp, yp = synth.pack(insts)
+    z = torch.from_numpy(zp).to(dev)
+    y = torch.from_numpy(yp).to(dev)
+    tot = {k: int(v[-1]) for k, v in batch.offsets.items()}
+    jac = torch.empty(tot["jac"], dtype=torch.float64, device=dev)
+    hess = torch.empty(tot["hess"], dtype=torch.float64, device=dev)
+    nnz = tot["jac"] + tot["hess"]
+    nbytes = 8 * nnz + 8 * sum(i.n * (i.N + 1) for i in insts) * 2 + 8 * tot["c"]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {}
+    res["per_instance_ms"] = timed(lambda: batch.eval(z, y, 1.0, jac, hess, mode="per_instance"))
+    g1, _, _ = batch.graph(z, y, 1.0, jac, hess, mode="per_instance")
+    res["per_instance_graph_ms"] = timed(g1.launch)
+    g1.close()
+    with tempfile.TemporaryDirectory() as td:
+        cfg, tune_ms = batch.autotune(z, y, 1.0, jac, hess, reps=3, cache=os.path.join(td, "t.json"))
+    table = batch.tuning
+    looped = min((t for t in table if t["wgs_per_cu"] > 0), key=lambda t: t["ms"])
+    res["persistent_ms"] = timed(lambda: batch.eval(z, y, 1.0, jac, hess))
+    g2, _, _ = batch.graph(z, y, 1.0, jac, hess)
+    res["persistent_graph_ms"] = timed(g2.launch)
+    g2.close()
+    batch.close()
+    out = {"workload": "512 instances, N_b ~ U{200..20000} (sum %d), n=6, m=3, jac+hess" % sum(
+               i.N for i in insts),
+           "nnz": nnz, "autotuned_config": cfg,
+           "best_looping_shape": looped,
+           "autotune_table_ms": {"%d/%d/%d/%d" % (t["block"], t["pair"], t["wgs_per_cu"], t["order"]):
+                                 round(t["ms"], 4) for t in table}}
+    for k, v in res.items():
+        out[k] = round(v, 4)
+        out[k.replace("_ms", "_nnz_per_s")] = nnz / (v * 1e-3)
+    out["persistent_graph_hbm_frac"] = round(nbytes / (res["persistent_graph_ms"] * 1e-3) / HBM_PEAK, 4)
+    out["speedup_persistent_graph_vs_per_instance"] = round(res["per_instance_ms"] / res["persistent_graph_ms"], 3)
+    out["speedup_persistent_graph_vs_per_instance_graph"] = round(
+        res["per_instance_graph_ms"] / res["persistent_graph_ms"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the 512-instance batched measurement (profiling runs)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 512-instance batched measurement (profiling runs)")
     ap.add_argument("--no-ipm-loop", action="store_true",
                     help="skip the N=1e5 interior-point-loop measurement (profiling runs)")
     ap.add_argument("--N", type=int, default=None, help="override the interval count")
@@ -146,6 +210,12 @@ def main():
 
     import paper_2510_03932_amd as ocp
     import synth
+
+    if args.only_batched:
+        torch.cuda.set_device(0)
+        log("[bench] batched workload only")
+        print(json.dumps({"batched": batched(torch, ocp, synth)}), flush=True)
+        return
 
     N, n, m = synth.LARGE
     if args.N:
@@ -299,6 +369,9 @@ def main():
     if not args.no_ipm_loop:
         log("[bench] interior-point loop workload")
         out["ipm_loop"] = ipm_loop(torch, ocp, synth)
+    if not args.no_batched:
+        log("[bench] batched workload")
+        out["batched"] = batched(torch, ocp, synth)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         cb = cpu_baseline(inst)

@@ -163,6 +163,106 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
                      const int32_t *rowptr, const double *jvals, const double *hvals,
                      const double *reg, double *kkt, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent instances with their own N_b and coefficients
+ * (shared n, m), evaluated together.  The paper motivates data parallelism
+ * across grid nodes (Sec. 3) and real-time use; a batch extends the same
+ * node-parallel evaluation across instances.
+ *
+ * Packed layout: instance b's z, y/c, Jacobian and Hessian values are the
+ * single-instance arrays of that instance (same layouts as above, with its
+ * own N_b), stored back to back in instance order.  ocp_batch_offsets gives
+ * the int64 start of each instance in each packed array.
+ * ------------------------------------------------------------------------- */
+
+typedef struct ocp_batch ocp_batch;
+typedef struct ocp_graph ocp_graph;
+
+/* What a batched evaluation computes (bit mask). */
+#define OCP_EVAL_JAC 1
+#define OCP_EVAL_HESS 2
+
+/* How a batched evaluation runs. */
+#define OCP_BATCH_PERSISTENT 0    /* one persistent launch over a static tile list */
+#define OCP_BATCH_PER_INSTANCE 1  /* one single-instance launch per instance and evaluation */
+
+/* Tile shape of the persistent launch. */
+typedef struct ocp_batch_config {
+    int32_t block;        /* threads per workgroup: 128 or 256 */
+    int32_t pair;         /* 1: Jacobian lanes take two intervals (16-byte stores) where the
+                             instance allows it (N_b even, output 16-byte aligned); 0: one */
+    int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..32; 0: one
+                             workgroup per tile (the loop over tiles runs once) */
+    int32_t order;        /* tile order within an instance: 0 node range major (all columns
+                             of a node range together), 1 column major (a column's node
+                             ranges together) */
+} ocp_batch_config;
+
+/* Create a batch of `count` instances on the current HIP device.  Ns: count
+ * interval counts (host int64, each >= 1).  A: count x n x n, B: count x n x m,
+ * gamma: count x n, q: count x n, r: count x m, all host, instance-major and
+ * row-major within an instance (B and r may be NULL when m = 0).  Copies the
+ * coefficients to the device, builds the offset table and the tile list of
+ * the default configuration {256, 1, 8}.
+ * Errors: OCP_ERR_ARG (count < 1, bad N_b, n, m or pointers), OCP_ERR_OVERFLOW
+ * (an instance's sizes do not fit int32), OCP_ERR_ALLOC, OCP_ERR_HIP. */
+int ocp_batch_create(int32_t count, const int64_t *Ns, int32_t n, int32_t m, const double *A,
+                     const double *B, const double *gamma, const double *q, const double *r,
+                     ocp_batch **out);
+
+/* Release a batch.  NULL-safe.  No work using it may be in flight. */
+void ocp_batch_destroy(ocp_batch *b);
+
+/* Packed offsets (host int64 arrays of count+1 entries each, any may be NULL):
+ * z_off (nvar_b), c_off (ncon_b; also y), jac_off (nnzj_b), hess_off (nnzh_b).
+ * Entry `count` holds the total length of the packed array. */
+int ocp_batch_offsets(const ocp_batch *b, int64_t *z_off, int64_t *c_off, int64_t *jac_off,
+                      int64_t *hess_off);
+
+/* Current tile shape, and setting a new one.  Setting rebuilds the tile list
+ * and synchronizes the device first (no evaluation with the batch may be in
+ * flight on another thread).  Graphs captured earlier keep their own copy of
+ * the tile list and are unaffected.  Errors: OCP_ERR_ARG for a shape outside
+ * the documented ranges. */
+int ocp_batch_get_config(const ocp_batch *b, ocp_batch_config *cfg);
+int ocp_batch_set_config(ocp_batch *b, const ocp_batch_config *cfg);
+
+/* Evaluate Jacobian and/or Hessian values (`what`) of every instance into the
+ * packed device arrays jac / hess (NULL when not requested), from packed z and
+ * y (y may be NULL without OCP_EVAL_HESS).  `mode` selects the single
+ * persistent launch or the per-instance launches; both give bitwise the same
+ * values, independent of the tile shape.  Asynchronous on `stream`. */
+int ocp_batch_eval(const ocp_batch *b, int32_t what, int32_t mode, const double *z,
+                   const double *y, double sigma, double *jac, double *hess, hipStream_t stream);
+
+/* Capture one ocp_batch_eval (same arguments, pointers bound at capture) into
+ * a HIP graph on a private stream and instantiate it.  The graph owns a copy of
+ * the tile list, so later configuration changes do not affect it.  Errors: as
+ * ocp_batch_eval, plus OCP_ERR_HIP when capture or instantiation fails. */
+int ocp_batch_graph_create(const ocp_batch *b, int32_t what, int32_t mode, const double *z,
+                           const double *y, double sigma, double *jac, double *hess,
+                           ocp_graph **out);
+
+/* Replay a captured evaluation on `stream` (asynchronous).  The arrays bound
+ * at capture must still be alive. */
+int ocp_graph_launch(const ocp_graph *g, hipStream_t stream);
+
+/* Release a graph and its tile list.  NULL-safe; no replay may be in flight. */
+void ocp_graph_destroy(ocp_graph *g);
+
+/* Autotuner: time every tile shape in {128, 256} x {pair 0, 1} x
+ * {1, 2, 4, 8, 16, 32, 0 = one per tile} workgroups per CU x {order 0, 1}
+ * (56 shapes, in that nesting order, order fastest) with `reps` persistent
+ * evaluations each (HIP events on `stream`, after one untimed run), keep the
+ * fastest as the batch's config and return it with its mean time in
+ * milliseconds.  `all_ms` (nullable, OCP_AUTOTUNE_SHAPES floats) receives
+ * every shape's mean time.  Synchronizes the device.  Outputs are overwritten
+ * by the trial runs. */
+#define OCP_AUTOTUNE_SHAPES 56
+int ocp_batch_autotune(ocp_batch *b, int32_t what, const double *z, const double *y, double sigma,
+                       double *jac, double *hess, int32_t reps, hipStream_t stream,
+                       ocp_batch_config *best, float *best_ms, float *all_ms);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char *ocp_last_error(void);
 

@@ -44,6 +44,19 @@ class Sizes(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("pair", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+EVAL_JAC, EVAL_HESS = 1, 2
+AUTOTUNE_SHAPES = [{"block": b, "pair": p, "wgs_per_cu": w, "order": o}
+                   for b in (128, 256) for p in (0, 1) for w in (1, 2, 4, 8, 16, 32, 0) for o in (0, 1)]
+MODES = {"persistent": 0, "per_instance": 1}
+
 _lib = None
 
 
@@ -70,6 +83,20 @@ def lib():
         L.ocp_eval_hess.argtypes = [vp, vp, vp, dbl, vp, vp]
         L.ocp_assemble_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_last_error.restype = ctypes.c_char_p
+        L.ocp_batch_create.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.ocp_batch_destroy.argtypes = [vp]
+        L.ocp_batch_destroy.restype = None
+        L.ocp_batch_offsets.argtypes = [vp, vp, vp, vp, vp]
+        L.ocp_batch_get_config.argtypes = [vp, ctypes.POINTER(BatchConfig)]
+        L.ocp_batch_set_config.argtypes = [vp, ctypes.POINTER(BatchConfig)]
+        L.ocp_batch_eval.argtypes = [vp, i32, i32, vp, vp, dbl, vp, vp, vp]
+        L.ocp_batch_graph_create.argtypes = [vp, i32, i32, vp, vp, dbl, vp, vp, ctypes.POINTER(vp)]
+        L.ocp_graph_launch.argtypes = [vp, vp]
+        L.ocp_graph_destroy.argtypes = [vp]
+        L.ocp_graph_destroy.restype = None
+        L.ocp_batch_autotune.argtypes = [vp, i32, vp, vp, dbl, vp, vp, i32, vp,
+                                         ctypes.POINTER(BatchConfig), ctypes.POINTER(ctypes.c_float),
+                                         vp]
         missing = [name for name in exported_names() if not hasattr(L, name)]
         if missing:
             raise OcpError(OCP_ERR_HIP, f"{LIB_PATH} lacks {missing}: rebuild it")
@@ -242,3 +269,171 @@ class Problem:
         _check(lib().ocp_assemble_kkt(self._h, pj, ph, rp, jp, hp, gp, op, self._stream()),
                "ocp_assemble_kkt")
         return out
+
+
+def _autotune_cache_path() -> str:
+    return os.environ.get("OCP_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2510_03932_amd",
+                                       "autotune.json"))
+
+
+class Graph:
+    """An instantiated HIP graph of one batched evaluation (pointers bound at
+    capture).  launch() replays it on the current torch stream."""
+
+    def __init__(self, handle, device, keep):
+        self._h = handle
+        self.device = device
+        self._keep = keep  # tensors the graph reads or writes stay alive with it
+
+    def launch(self):
+        stream = ctypes.c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
+        _check(lib().ocp_graph_launch(self._h, stream), "ocp_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ocp_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent instances (own N_b, A, B, gamma, q, r; shared n, m)
+    evaluated together.  Packed arrays hold each instance's single-instance
+    array back to back; ``offsets`` gives the starts."""
+
+    def __init__(self, Ns, n, m, A, B, gamma, q, r, device=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise OcpError(OCP_ERR_HIP, "no GPU visible: this library runs only on gfx950 devices")
+        Ns = np.ascontiguousarray(np.asarray(Ns, np.int64))
+        self.count, self.n, self.m = int(len(Ns)), int(n), int(m)
+        self.Ns = Ns
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        c = self.count
+        f64 = lambda a, shape: np.ascontiguousarray(np.asarray(a, np.float64).reshape(shape))
+        A = f64(A, (c, n, n))
+        B = f64(B, (c, n, m)) if m else np.zeros((c, n, 0))
+        gamma, q = f64(gamma, (c, n)), f64(q, (c, n))
+        r = f64(r, (c, m)) if m else np.zeros((c, 0))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().ocp_batch_create(c, _hp(Ns), self.n, self.m, _hp(A), _hp(B) if m else None,
+                                          _hp(gamma), _hp(q), _hp(r) if m else None,
+                                          ctypes.byref(h)), "ocp_batch_create")
+        self._h = h
+        offs = [np.zeros(c + 1, np.int64) for _ in range(4)]
+        _check(lib().ocp_batch_offsets(self._h, *(_hp(o) for o in offs)), "ocp_batch_offsets")
+        self.offsets = dict(zip(("z", "c", "jac", "hess"), offs))
+        self.tuning = None  # the autotuner's table of (shape, ms), once tuned
+
+    @classmethod
+    def from_instances(cls, insts, device=None):
+        n, m = insts[0].n, insts[0].m
+        return cls([i.N for i in insts], n, m, np.stack([i.A for i in insts]),
+                   np.stack([i.B for i in insts]), np.stack([i.gamma for i in insts]),
+                   np.stack([i.q for i in insts]), np.stack([i.r for i in insts]), device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ocp_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def config(self) -> dict:
+        c = BatchConfig()
+        _check(lib().ocp_batch_get_config(self._h, ctypes.byref(c)), "ocp_batch_get_config")
+        return c.as_dict()
+
+    @config.setter
+    def config(self, cfg: dict):
+        c = BatchConfig(int(cfg["block"]), int(cfg["pair"]), int(cfg["wgs_per_cu"]), int(cfg["order"]))
+        _check(lib().ocp_batch_set_config(self._h, ctypes.byref(c)), "ocp_batch_set_config")
+
+    def _args(self, z, y, jac, hess, what):
+        torch = _torch()
+        tot = {k: int(v[-1]) for k, v in self.offsets.items()}
+        chk = self._dev  # the same tensor checks as a single problem
+        zp = chk(z, tot["z"], torch.float64, "z")
+        yp = chk(y, tot["c"], torch.float64, "y") if (what & EVAL_HESS) else None
+        if (what & EVAL_JAC) and jac is None:
+            jac = torch.empty(tot["jac"], dtype=torch.float64, device=self.device)
+        if (what & EVAL_HESS) and hess is None:
+            hess = torch.empty(tot["hess"], dtype=torch.float64, device=self.device)
+        jp = chk(jac, tot["jac"], torch.float64, "jac") if (what & EVAL_JAC) else None
+        hp = chk(hess, tot["hess"], torch.float64, "hess") if (what & EVAL_HESS) else None
+        return zp, yp, jp, hp, jac, hess
+
+    _dev = Problem._dev
+
+    def eval(self, z, y=None, sigma=1.0, jac=None, hess=None, what=EVAL_JAC | EVAL_HESS,
+             mode="persistent"):
+        """Packed Jacobian and/or Hessian values of every instance: (jac, hess)."""
+        zp, yp, jp, hp, jac, hess = self._args(z, y, jac, hess, what)
+        stream = ctypes.c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
+        _check(lib().ocp_batch_eval(self._h, what, MODES[mode], zp, yp, float(sigma), jp, hp, stream),
+               "ocp_batch_eval")
+        return jac, hess
+
+    def graph(self, z, y=None, sigma=1.0, jac=None, hess=None, what=EVAL_JAC | EVAL_HESS,
+              mode="persistent"):
+        """Capture one evaluation into a HIP graph: returns (Graph, jac, hess)."""
+        zp, yp, jp, hp, jac, hess = self._args(z, y, jac, hess, what)
+        g = ctypes.c_void_p()
+        with _torch().cuda.device(self.device):
+            _check(lib().ocp_batch_graph_create(self._h, what, MODES[mode], zp, yp, float(sigma), jp,
+                                                hp, ctypes.byref(g)), "ocp_batch_graph_create")
+        return Graph(g, self.device, (z, y, jac, hess)), jac, hess
+
+    def autotune(self, z, y=None, sigma=1.0, jac=None, hess=None, what=EVAL_JAC | EVAL_HESS,
+                 reps=5, cache: str | None = None, use_cache=True):
+        """Pick the fastest tile shape of the persistent launch (timed in the
+        library), remember it in a JSON cache keyed by device, shape and work,
+        and set it.  Returns (config, ms per evaluation)."""
+        import json
+        torch = _torch()
+        key = "|".join([torch.cuda.get_device_name(self.device), f"n{self.n}", f"m{self.m}",
+                        f"count{self.count}", f"sumN{int(self.Ns.sum())}", f"what{what}"])
+        path = cache or _autotune_cache_path()
+        db = {}
+        if use_cache and os.path.exists(path):
+            try:
+                db = json.load(open(path))
+            except (OSError, ValueError):
+                db = {}
+        if use_cache and key in db:
+            self.config = db[key]["config"]
+            self.tuning = db[key].get("table")
+            return db[key]["config"], float(db[key]["ms"])
+        zp, yp, jp, hp, jac, hess = self._args(z, y, jac, hess, what)
+        best = BatchConfig()
+        ms = ctypes.c_float()
+        table = np.zeros(len(AUTOTUNE_SHAPES), np.float32)
+        stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(lib().ocp_batch_autotune(self._h, what, zp, yp, float(sigma), jp, hp, int(reps), stream,
+                                        ctypes.byref(best), ctypes.byref(ms), _hp(table)),
+               "ocp_batch_autotune")
+        cfg = best.as_dict()
+        self.tuning = [dict(shape, ms=float(t)) for shape, t in zip(AUTOTUNE_SHAPES, table)]
+        db[key] = {"config": cfg, "ms": float(ms.value), "table": self.tuning}
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(db, fh, indent=1)
+            os.replace(tmp, path)
+        except OSError:
+            pass  # an unwritable cache only costs a re-tune next time
+        return cfg, float(ms.value)

@@ -1,0 +1,195 @@
+// Per-node device arithmetic shared by the single-instance kernels and the
+// batched persistent kernel of the evaluation library (gfx950, wave64).
+//
+// Every evaluation maps one grid node (or one interval) to one lane, the SIMD
+// structure of direct transcription (paper Sec. 3): the same few functions are
+// evaluated at every node.  All arrays are structure-of-arrays with the node
+// index fastest, so the lanes of a wavefront touch consecutive doubles.
+//
+// Formulas (component-major unknowns, h = 1/N, hh = h/2, p(i) = (i+1) mod n):
+//   F_i(k)   = sum_j A_ij sin X_jk + sum_l B_il U_lk + gamma_i X_ik X_{p(i)k}
+//   c_{ik}   = (X_{i,k+1} - X_ik) - hh (F_i(k) + F_i(k+1))         [Sec. 5]
+//   f        = sum_k w_k (sum_j q_j X_jk^2 + sum_l r_l U_lk^2)     [Sec. 5]
+//   dF_i/dX_j = A_ij cos X_j + gamma_i (delta_ij X_p(i) + delta_j,p(i) X_i)
+//   Hessian of L = sigma f + y^T c at node k uses the node multiplier
+//   yt_ik = y_{i,k-1} [k >= 1] + y_{ik} [k < N]  (node k is the right end of
+//   interval k-1 and the left end of interval k).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ocp {
+namespace dev {
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef int32_t int2v __attribute__((ext_vector_type(2)));
+
+constexpr int kBlock = 256;  // threads per workgroup of the single-instance kernels (4 waves)
+
+// Kernel-side view of one problem: sizes and device coefficient pointers.
+struct KP {
+    int N;         // intervals
+    int N1;        // nodes = N + 1
+    int n, m, npair, T, S;
+    int nnzk;      // KKT entries
+    double h, hh;
+    const double *A;    // n x n row-major
+    const double *B;    // n x m row-major
+    const double *gam;  // n
+    const double *q;    // n
+    const double *r;    // m
+};
+
+__device__ __forceinline__ double node_weight(const KP &P, int k)
+{
+    return (k == 0 || k == P.N) ? P.hh : P.h;
+}
+
+__device__ __forceinline__ void st_nt(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt2(double *p, dbl2 v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<dbl2 *>(p));
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian values of one column for NPT consecutive intervals k .. k+NPT-1
+// (the caller guarantees k + NPT <= N, and for NPT = 2 a 16-byte aligned
+// output with N even).  Column col < n is state column j: slots 2j, 2j+1 of
+// every row i; col = n + l is control column l: slots 2n+2l, 2n+2l+1, the
+// constant -hh B_il.  NPT = 2 stores a 16-byte pair per lane, so a wavefront
+// store is one contiguous KiB of a slot row.  A state column needs NPT+1
+// cosines per lane; the bilinear term touches only rows i = j (partner
+// X_{j+1}) and i = j-1 (factor X_{j-1}).
+// ---------------------------------------------------------------------------
+template <int NPT>
+__device__ __forceinline__ void jac_column(const KP &P, const double *__restrict__ z,
+                                           double *__restrict__ jac, int64_t k, int col)
+{
+    const int n = P.n, T = P.T;
+    const int64_t N = P.N, N1 = P.N1;
+    const double hh = P.hh;
+    if (col < n) {
+        const int j = col;
+        const int jn = (j + 1 == n) ? 0 : j + 1;
+        const int jp = (j == 0) ? n - 1 : j - 1;
+        const double *xj = z + j * N1 + k;
+        const double *xn = z + jn * N1 + k;
+        const double *xp = z + jp * N1 + k;
+        double cs[NPT + 1], dg[NPT + 1], lo[NPT + 1];
+#pragma unroll
+        for (int u = 0; u <= NPT; u++) {
+            cs[u] = cos(xj[u]);
+            dg[u] = -hh * P.gam[j] * xn[u];   // row i = j: gamma_j X_{j+1}
+            lo[u] = -hh * P.gam[jp] * xp[u];  // row i = j-1: gamma_{j-1} X_{j-1}
+        }
+        for (int i = 0; i < n; i++) {
+            const double a = -hh * P.A[i * n + j];
+            double v0[NPT], v1[NPT];
+#pragma unroll
+            for (int u = 0; u < NPT; u++) {
+                v0[u] = a * cs[u];
+                v1[u] = a * cs[u + 1];
+            }
+            if (i == j) {
+#pragma unroll
+                for (int u = 0; u < NPT; u++) {
+                    v0[u] += dg[u] - 1.0;
+                    v1[u] += dg[u + 1] + 1.0;
+                }
+            }
+            if (i == jp) {
+#pragma unroll
+                for (int u = 0; u < NPT; u++) {
+                    v0[u] += lo[u];
+                    v1[u] += lo[u + 1];
+                }
+            }
+            double *o0 = jac + ((int64_t)i * T + 2 * j) * N + k;
+            double *o1 = o0 + N;
+            if constexpr (NPT == 2) {
+                st_nt2(o0, dbl2{v0[0], v0[1]});
+                st_nt2(o1, dbl2{v1[0], v1[1]});
+            } else {
+                st_nt(o0, v0[0]);
+                st_nt(o1, v1[0]);
+            }
+        }
+    } else {
+        const int l = col - n, m = P.m;
+        for (int i = 0; i < n; i++) {
+            const double v = -hh * P.B[i * m + l];
+            double *o0 = jac + ((int64_t)i * T + 2 * n + 2 * l) * N + k;
+            double *o1 = o0 + N;
+            if constexpr (NPT == 2) {
+                st_nt2(o0, dbl2{v, v});
+                st_nt2(o1, dbl2{v, v});
+            } else {
+                st_nt(o0, v);
+                st_nt(o1, v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hessian-of-Lagrangian values at node k <= N.  NB >= n is a compile-time
+// bound so the node's states and multipliers stay in registers; all loads are
+// issued before the arithmetic.
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void hess_node(const KP &P, const double *__restrict__ z,
+                                          const double *__restrict__ y, double sigma,
+                                          double *__restrict__ hv, int k)
+{
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1;
+    const double w = node_weight(P, k);
+    double x[NB], yl[NB], yr[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        x[i] = yl[i] = yr[i] = 0.0;
+        if (i < n) {
+            x[i] = z[i * N1 + k];
+            const double *yi = y + i * N + k;
+            if (k >= 1) yl[i] = yi[-1];
+            if (k < P.N) yr[i] = yi[0];
+        }
+    }
+    double yt[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        if (j < n) {
+            const double sx = sin(x[j]);
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) s += yt[i] * P.A[i * n + j];
+            double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
+            if (n == 1) v -= P.h * yt[0] * P.gam[0];
+            st_nt(hv + j * N1 + k, v);
+        }
+    }
+    if (n >= 3) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_nt(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
+    } else if (n == 2) {
+        st_nt(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+    }
+    const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
+    for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
+}
+
+// Host-side launchers of the single-instance Jacobian and Hessian kernels
+// (ocp_eval.hip); the batched path uses them for its per-instance mode.
+// `pair_ok`: the Jacobian output is 16-byte aligned.
+hipError_t launch_jac(const KP &P, const double *z, double *jac, bool pair_ok, hipStream_t stream);
+hipError_t launch_hess(const KP &P, const double *z, const double *y, double sigma, double *hv,
+                       hipStream_t stream);
+
+}  // namespace dev
+}  // namespace ocp

@@ -1,73 +1,31 @@
-// Device layer of the evaluation library: HIP kernels for gfx950 (CDNA4,
-// wave64) and the C ABI entry points that validate arguments and launch them.
-//
-// Every evaluation maps one grid node (or one interval) to one lane, the SIMD
-// structure of direct transcription (paper Sec. 3): the same few functions are
-// evaluated at every node.  All arrays are structure-of-arrays with the node
-// index fastest, so the lanes of a wavefront touch consecutive doubles.  The
-// path is HBM-bound sparse evaluation, not a dense contraction: no MFMA.
-//
-// Formulas (component-major unknowns, h = 1/N, hh = h/2, p(i) = (i+1) mod n):
-//   F_i(k)   = sum_j A_ij sin X_jk + sum_l B_il U_lk + gamma_i X_ik X_{p(i)k}
-//   c_{ik}   = (X_{i,k+1} - X_ik) - hh (F_i(k) + F_i(k+1))         [Sec. 5]
-//   f        = sum_k w_k (sum_j q_j X_jk^2 + sum_l r_l U_lk^2)     [Sec. 5]
-//   dF_i/dX_j = A_ij cos X_j + gamma_i (delta_ij X_p(i) + delta_j,p(i) X_i)
-//   Hessian of L = sigma f + y^T c at node k uses the node multiplier
-//   yt_ik = y_{i,k-1} [k >= 1] + y_{ik} [k < N]  (node k is the right end of
-//   interval k-1 and the left end of interval k).
+// Device layer of the evaluation library, single-instance entry points: HIP
+// kernels for gfx950 (CDNA4, wave64) and the C ABI functions that validate
+// arguments and launch them.  The per-node arithmetic shared with the batched
+// path lives in ocp_device.h.  The path is HBM-bound sparse evaluation, not a
+// dense contraction: no MFMA.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
 
+#include "ocp_device.h"
 #include "ocp_internal.h"
 
 using namespace ocp;
-
-typedef double dbl2 __attribute__((ext_vector_type(2)));
-typedef int32_t int2v __attribute__((ext_vector_type(2)));
+using namespace ocp::dev;
 
 namespace {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 waves)
 constexpr int kObjBlocks = 4096;     // most partials of the objective sum
 
-// Kernel-side view of a problem: sizes and device coefficient pointers.
-struct KP {
-    int N;         // intervals
-    int N1;        // nodes = N + 1
-    int n, m, npair, T, S;
-    int nnzk;      // KKT entries
-    double h, hh;
-    const double *A;    // n x n row-major
-    const double *B;    // n x m row-major
-    const double *gam;  // n
-    const double *q;    // n
-    const double *r;    // m
-};
-
-__device__ __forceinline__ double node_weight(const KP &P, int k)
-{
-    return (k == 0 || k == P.N) ? P.hh : P.h;
-}
-
-__device__ __forceinline__ void st_nt(double *p, double v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void st_nt2(double *p, dbl2 v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<dbl2 *>(p));
-}
-
 // ---------------------------------------------------------------------------
-// Jacobian values.  2-D grid: blockIdx.y = j < n takes state column j (slots
-// 2j, 2j+1 of every row i), blockIdx.y = n + l takes control column l (slots
-// 2n+2l, 2n+2l+1, the constant -hh B_il).  One lane per NPT consecutive
-// intervals: NPT = 2 stores a 16-byte pair per lane, so a wavefront store is
-// one contiguous KiB of a slot row.  Per state column a lane needs NPT+1
-// cosines; the bilinear term touches only rows i = j (partner X_{j+1}) and
-// i = j-1 (factor X_{j-1}).  Many short lanes (a grid of (N/NPT) x (n+m)) keep
-// the write stream at the device's streaming-store rate.
+// Jacobian values.  2-D grid: blockIdx.x picks NPT intervals per lane,
+// blockIdx.y the column (state j < n, control n + l).  Many short lanes (a
+// grid of (N/NPT) x (n+m)) keep the write stream at the device's
+// streaming-store rate.
 // ---------------------------------------------------------------------------
 template <int NPT>
 __global__ __launch_bounds__(kBlock) void jac_kernel(KP P, const double *__restrict__ z,
@@ -75,75 +33,11 @@ __global__ __launch_bounds__(kBlock) void jac_kernel(KP P, const double *__restr
 {
     const int64_t k = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPT;
     if (k >= P.N) return;
-    const int n = P.n, T = P.T;
-    const int64_t N = P.N, N1 = P.N1;
-    const double hh = P.hh;
-    const int j = blockIdx.y;
-    if (j < n) {
-        const int jn = (j + 1 == n) ? 0 : j + 1;
-        const int jp = (j == 0) ? n - 1 : j - 1;
-        const double *xj = z + j * N1 + k;
-        const double *xn = z + jn * N1 + k;
-        const double *xp = z + jp * N1 + k;
-        double cs[NPT + 1], dg[NPT + 1], lo[NPT + 1];
-#pragma unroll
-        for (int u = 0; u <= NPT; u++) {
-            cs[u] = cos(xj[u]);
-            dg[u] = -hh * P.gam[j] * xn[u];   // row i = j: gamma_j X_{j+1}
-            lo[u] = -hh * P.gam[jp] * xp[u];  // row i = j-1: gamma_{j-1} X_{j-1}
-        }
-        for (int i = 0; i < n; i++) {
-            const double a = -hh * P.A[i * n + j];
-            double v0[NPT], v1[NPT];
-#pragma unroll
-            for (int u = 0; u < NPT; u++) {
-                v0[u] = a * cs[u];
-                v1[u] = a * cs[u + 1];
-            }
-            if (i == j) {
-#pragma unroll
-                for (int u = 0; u < NPT; u++) {
-                    v0[u] += dg[u] - 1.0;
-                    v1[u] += dg[u + 1] + 1.0;
-                }
-            }
-            if (i == jp) {
-#pragma unroll
-                for (int u = 0; u < NPT; u++) {
-                    v0[u] += lo[u];
-                    v1[u] += lo[u + 1];
-                }
-            }
-            double *o0 = jac + ((int64_t)i * T + 2 * j) * N + k;
-            double *o1 = o0 + N;
-            if constexpr (NPT == 2) {
-                st_nt2(o0, dbl2{v0[0], v0[1]});
-                st_nt2(o1, dbl2{v1[0], v1[1]});
-            } else {
-                st_nt(o0, v0[0]);
-                st_nt(o1, v1[0]);
-            }
-        }
-    } else {
-        const int l = j - n, m = P.m;
-        for (int i = 0; i < n; i++) {
-            const double v = -hh * P.B[i * m + l];
-            double *o0 = jac + ((int64_t)i * T + 2 * n + 2 * l) * N + k;
-            double *o1 = o0 + N;
-            if constexpr (NPT == 2) {
-                st_nt2(o0, dbl2{v, v});
-                st_nt2(o1, dbl2{v, v});
-            } else {
-                st_nt(o0, v);
-                st_nt(o1, v);
-            }
-        }
-    }
+    jac_column<NPT>(P, z, jac, k, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
-// Hessian-of-Lagrangian values, one lane per node.  NB >= n is a compile-time
-// bound so the node multipliers stay in registers.
+// Hessian-of-Lagrangian values, one lane per node.
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(kBlock) void hess_kernel(KP P, const double *__restrict__ z,
@@ -152,46 +46,7 @@ __global__ __launch_bounds__(kBlock) void hess_kernel(KP P, const double *__rest
 {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k > P.N) return;
-    const int n = P.n, m = P.m;
-    const int64_t N = P.N, N1 = P.N1;
-    const double w = node_weight(P, k);
-    // all loads first (state and both multipliers of every component)
-    double x[NB], yl[NB], yr[NB];
-#pragma unroll
-    for (int i = 0; i < NB; i++) {
-        x[i] = yl[i] = yr[i] = 0.0;
-        if (i < n) {
-            x[i] = z[i * N1 + k];
-            const double *yi = y + i * N + k;
-            if (k >= 1) yl[i] = yi[-1];
-            if (k < P.N) yr[i] = yi[0];
-        }
-    }
-    double yt[NB];
-#pragma unroll
-    for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
-#pragma unroll
-    for (int j = 0; j < NB; j++) {
-        if (j < n) {
-            const double sx = sin(x[j]);
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) s += yt[i] * P.A[i * n + j];
-            double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
-            if (n == 1) v -= P.h * yt[0] * P.gam[0];
-            st_nt(hv + j * N1 + k, v);
-        }
-    }
-    if (n >= 3) {
-#pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < n) st_nt(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
-    } else if (n == 2) {
-        st_nt(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
-    }
-    const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
-    for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
+    hess_node<NB>(P, z, y, sigma, hv, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,6 +308,38 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
 // C ABI
 // ===========================================================================
 
+namespace ocp {
+namespace dev {
+
+hipError_t launch_jac(const KP &P, const double *z, double *jac, bool pair_ok, hipStream_t stream)
+{
+    // Paired 16-byte stores need every slot row 16-byte aligned: N even and
+    // the output 16-byte aligned.
+    const unsigned cols = (unsigned)(P.n + P.m);
+    if (pair_ok && P.N % 2 == 0) {
+        hipLaunchKernelGGL(jac_kernel<2>, dim3((unsigned)((P.N / 2 + kBlock - 1) / kBlock), cols),
+                           dim3(kBlock), 0, stream, P, z, jac);
+    } else {
+        hipLaunchKernelGGL(jac_kernel<1>, dim3((unsigned)((P.N + kBlock - 1) / kBlock), cols),
+                           dim3(kBlock), 0, stream, P, z, jac);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hess(const KP &P, const double *z, const double *y, double sigma, double *hv,
+                       hipStream_t stream)
+{
+    const dim3 g((unsigned)((P.N1 + kBlock - 1) / kBlock));
+    if (P.n <= 4) hipLaunchKernelGGL(hess_kernel<4>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
+    else if (P.n <= 8) hipLaunchKernelGGL(hess_kernel<8>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
+    else if (P.n <= 16) hipLaunchKernelGGL(hess_kernel<16>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
+    else hipLaunchKernelGGL(hess_kernel<32>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
+    return hipGetLastError();
+}
+
+}  // namespace dev
+}  // namespace ocp
+
 struct ocp_problem {
     Dims d;
     int device;
@@ -604,18 +491,9 @@ int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_jac")) return rc;
     if (!z || !jvals) return fail(OCP_ERR_ARG, "ocp_eval_jac: null array");
-    // Paired 16-byte stores need every slot row 16-byte aligned: N even and
-    // the output 16-byte aligned.
-    const bool pair = (p->d.N % 2 == 0) && ((uintptr_t)jvals % 16 == 0);
-    const unsigned cols = (unsigned)(p->d.n + p->d.m);
-    if (pair) {
-        hipLaunchKernelGGL(jac_kernel<2>, dim3(blocks_for(p->d.N / 2, kBlock), cols), dim3(kBlock),
-                           0, stream, p->kp, z, jvals);
-    } else {
-        hipLaunchKernelGGL(jac_kernel<1>, dim3(blocks_for(p->d.N, kBlock), cols), dim3(kBlock), 0,
-                           stream, p->kp, z, jvals);
-    }
-    return check_launch("ocp_eval_jac");
+    const hipError_t e = launch_jac(p->kp, z, jvals, (uintptr_t)jvals % 16 == 0, stream);
+    if (e != hipSuccess) return hip_fail("ocp_eval_jac", e);
+    return OCP_OK;
 }
 
 int ocp_eval_hess(const ocp_problem *p, const double *z, const double *y, double sigma,
@@ -625,13 +503,9 @@ int ocp_eval_hess(const ocp_problem *p, const double *z, const double *y, double
     if (int rc = check_handle(p, "ocp_eval_hess")) return rc;
     if (!z || !y || !hvals) return fail(OCP_ERR_ARG, "ocp_eval_hess: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_hess: sigma is not finite");
-    const unsigned g = blocks_for(p->d.N1, kBlock);
-    const int n = p->d.n;
-    if (n <= 4) hipLaunchKernelGGL(hess_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
-    else if (n <= 8) hipLaunchKernelGGL(hess_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
-    else if (n <= 16) hipLaunchKernelGGL(hess_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
-    else hipLaunchKernelGGL(hess_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, y, sigma, hvals);
-    return check_launch("ocp_eval_hess");
+    const hipError_t e = launch_hess(p->kp, z, y, sigma, hvals, stream);
+    if (e != hipSuccess) return hip_fail("ocp_eval_hess", e);
+    return OCP_OK;
 }
 
 int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,

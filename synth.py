@@ -100,3 +100,16 @@ def device_point(torch, device, N: int, n: int, m: int, seed: int):
     U = torch.rand(m * (N + 1), generator=g, **f64) * 2.0 - 1.0
     y = torch.randn(n * N, generator=g, **f64)
     return torch.cat([X, U]), y
+
+
+def make_batch(count: int = 512, n: int = 6, m: int = 3, seed: int = 0, Ns=None):
+    """Instances of the batched workload: N_b from ``batched_sizes`` (unless
+    given), instance b drawn from ``default_rng([seed, b])`` in the
+    single-instance order (A, B, gamma, X, U, y)."""
+    Ns = batched_sizes(count, seed=seed) if Ns is None else Ns
+    return [make_instance(int(N), n, m, seed=[seed, b]) for b, N in enumerate(Ns)]
+
+
+def pack(insts):
+    """Packed z and y of a list of instances (instance after instance)."""
+    return (np.concatenate([i.z for i in insts]), np.concatenate([i.y for i in insts]))

@@ -19,7 +19,7 @@ GRID = [(1, 1, 0), (1, 1, 1), (2, 1, 0), (3, 2, 0), (2, 2, 1), (5, 3, 0), (4, 3,
 def test_library_exports_every_declared_symbol():
     L = ocp.lib()
     names = ocp.exported_names()
-    assert len(names) == 13, names
+    assert len(names) == 23, names
     for name in names:
         assert hasattr(L, name), name
     text = open(ocp.HEADER).read()
@@ -118,3 +118,30 @@ def test_create_rejects_bad_arguments_before_any_hip_call():
     assert L.ocp_eval_hess(None, None, None, 1.0, None, None) == ocp.OCP_ERR_ARG
     assert L.ocp_assemble_kkt(None, None, None, None, None, None, None, None, None) == ocp.OCP_ERR_ARG
     L.ocp_destroy(None)  # NULL-safe
+
+
+def test_batch_create_rejects_bad_arguments_before_any_hip_call():
+    L = ocp.lib()
+    h = ctypes.c_void_p()
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    A = np.zeros((2, 3, 3))
+    g = np.zeros((2, 3))
+    Ns = np.array([10, 20], np.int64)
+    assert L.ocp_batch_create(0, ptr(Ns), 3, 0, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_batch_create(2, None, 3, 0, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_batch_create(2, ptr(Ns), 3, 1, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_batch_create(2, ptr(Ns), 0, 0, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    bad = np.array([10, 0], np.int64)
+    assert L.ocp_batch_create(2, ptr(bad), 3, 0, ptr(A), None, ptr(g), ptr(g), None, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert b"instance 1" in L.ocp_last_error()
+    huge = np.array([10, 10_000_000], np.int64)
+    assert L.ocp_batch_create(2, ptr(huge), 16, 8, ptr(np.zeros((2, 16, 16))), ptr(np.zeros((2, 16, 8))),
+                              ptr(np.zeros((2, 16))), ptr(np.zeros((2, 16))), ptr(np.zeros((2, 8))),
+                              ctypes.byref(h)) == ocp.OCP_ERR_OVERFLOW
+    assert h.value is None
+    cfg = ocp.BatchConfig(256, 1, 8, 0)
+    assert L.ocp_batch_set_config(None, ctypes.byref(cfg)) == ocp.OCP_ERR_ARG
+    assert L.ocp_batch_eval(None, 3, 0, None, None, 1.0, None, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_graph_launch(None, None) == ocp.OCP_ERR_ARG
+    L.ocp_batch_destroy(None)
+    L.ocp_graph_destroy(None)
