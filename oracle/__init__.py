@@ -56,6 +56,13 @@ class Oracle:
             L.orc_pattern.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr]
             L.orc_kkt.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, ptr, ptr]
             L.orc_assemble.argtypes = [i64, i64, ptr, i64, ptr, ptr, i64, ptr, ptr, ptr, ptr]
+            L.orc_lagrangian.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, dbl, ptr]
+            L.orc_lag_grad.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, dbl,
+                                       i64, i64, ptr, ptr]
+            L.orc_hvp.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, dbl, ptr,
+                                  i64, i64, ptr, ptr]
+            L.orc_jvp.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, i64, i64, ptr, ptr]
+            L.orc_coef_grad.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, ptr]
             L.orc_set_threads.argtypes = [i32]
             L.orc_set_threads.restype = None
             L.orc_get_threads.restype = i32
@@ -157,6 +164,66 @@ class Oracle:
                                    _p(regp), _p(out)), "assemble")
         return out
 
+    # ---- Lagrangian L = sigma f + y^T c and its derivatives ----------------
+    def lagrangian(self, inst, sigma=None, y=None):
+        """(L, mu_L)."""
+        out = np.zeros(2)
+        sigma = inst.sigma if sigma is None else sigma
+        y = inst.y if y is None else y
+        _check(self.L.orc_lagrangian(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.B)),
+                                     _p(_d(inst.gamma)), _p(_d(inst.q)), _p(_d(inst.r)),
+                                     _p(_d(inst.z)), _p(_d(y)), float(sigma), _p(out)), "lagrangian")
+        return float(out[0]), float(out[1])
+
+    def lag_grad(self, inst, k0=0, k1=None, sigma=None, y=None):
+        """grad_z L at nodes [k0, k1) (layout of grad)."""
+        k1 = inst.N + 1 if k1 is None else k1
+        K = k1 - k0
+        g = np.empty((inst.n + inst.m) * K)
+        mu = np.empty_like(g)
+        sigma = inst.sigma if sigma is None else sigma
+        y = inst.y if y is None else y
+        _check(self.L.orc_lag_grad(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.B)),
+                                   _p(_d(inst.gamma)), _p(_d(inst.q)), _p(_d(inst.r)),
+                                   _p(_d(inst.z)), _p(_d(y)), float(sigma), k0, k1, _p(g), _p(mu)),
+               "lag_grad")
+        return g, mu
+
+    def hvp(self, inst, v, k0=0, k1=None, sigma=None, y=None):
+        """(Hessian of L) v at nodes [k0, k1) (layout of grad); v has nvar entries."""
+        k1 = inst.N + 1 if k1 is None else k1
+        K = k1 - k0
+        g = np.empty((inst.n + inst.m) * K)
+        mu = np.empty_like(g)
+        sigma = inst.sigma if sigma is None else sigma
+        y = inst.y if y is None else y
+        _check(self.L.orc_hvp(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.gamma)),
+                              _p(_d(inst.q)), _p(_d(inst.r)), _p(_d(inst.z)), _p(_d(y)), float(sigma),
+                              _p(_d(v)), k0, k1, _p(g), _p(mu)), "hvp")
+        return g, mu
+
+    def jvp(self, inst, v, k0=0, k1=None):
+        """J v at intervals [k0, k1) (layout of cons); v has nvar entries."""
+        k1 = inst.N if k1 is None else k1
+        K = k1 - k0
+        g = np.empty(inst.n * K)
+        mu = np.empty_like(g)
+        _check(self.L.orc_jvp(inst.N, inst.n, inst.m, _p(_d(inst.A)), _p(_d(inst.B)),
+                              _p(_d(inst.gamma)), _p(_d(inst.z)), _p(_d(v)), k0, k1, _p(g), _p(mu)),
+               "jvp")
+        return g, mu
+
+    def coef_grad(self, inst, y=None):
+        """(dL/dA (n,n), dL/dB (n,m), dL/dgamma (n,)) and their mu arrays."""
+        n, m = inst.n, inst.m
+        y = inst.y if y is None else y
+        gA, gB, gg = np.empty((n, n)), np.empty((n, m)), np.empty(n)
+        mA, mB, mg = np.empty((n, n)), np.empty((n, m)), np.empty(n)
+        _check(self.L.orc_coef_grad(inst.N, n, m, _p(_d(inst.z)), _p(_d(y)), _p(gA),
+                                    _p(gB) if m else None, _p(gg), _p(mA), _p(mB) if m else None,
+                                    _p(mg)), "coef_grad")
+        return (gA, gB, gg), (mA, mB, mg)
+
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
@@ -184,6 +251,11 @@ hess = DEFAULT.hess
 pattern = DEFAULT.pattern
 kkt = DEFAULT.kkt
 assemble = DEFAULT.assemble
+lagrangian = DEFAULT.lagrangian
+lag_grad = DEFAULT.lag_grad
+hvp = DEFAULT.hvp
+jvp = DEFAULT.jvp
+coef_grad = DEFAULT.coef_grad
 
 
 def build_variant(src_text: str, out_path: str) -> "Oracle":

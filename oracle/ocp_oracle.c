@@ -511,3 +511,288 @@ int orc_assemble(int64_t nnzk, int64_t dim, const int32_t *rowptr,
         for (int64_t d = 0; d < dim; d++) kkt[rowptr[d + 1] - 1] += reg[d];
     return ORC_OK;
 }
+
+/* ---- Lagrangian and its derivatives (differentiation workload) ----------- */
+/*
+ * L(z, y; A, B, gamma, sigma) = sigma f(z) + y^T c(z).  Each function below is
+ * the plain definition written as a sum over the Jacobian / Hessian entries
+ * defined above (no rearranged closed forms):
+ *   orc_lagrangian  L and mu(L)
+ *   orc_lag_grad    grad_z L = sigma grad f + J^T y            (node range)
+ *   orc_hvp         (Hessian of L) v, block by block per node   (node range)
+ *   orc_jvp         J v                                          (interval range)
+ *   orc_coef_grad   dL/dA, dL/dB, dL/dgamma: sum over all defect rows of
+ *                   y_ik dc_ik/dtheta (fixed-chunk Neumaier sums)
+ */
+
+/* L = sigma f + sum_r y_r c_r: f as orc_obj; the product sum compensated in
+ * fixed chunks of OBJ_CHUNK intervals.  out = {L, mu}. */
+int orc_lagrangian(int64_t N, int n, int m, const double *A, const double *B,
+                   const double *gam, const double *q, const double *r,
+                   const double *z, const double *y, double sigma, double *out)
+{
+    if (bad_sizes(N, n, m) || !z || !y || !out) return ORC_BAD;
+    double fo[2];
+    if (orc_obj(N, n, m, q, r, z, fo)) return ORC_BAD;
+    double *c = (double *)malloc(sizeof(double) * (size_t)(n * N));
+    double *cm = (double *)malloc(sizeof(double) * (size_t)(n * N));
+    if (!c || !cm) { free(c); free(cm); return ORC_BAD; }
+    orc_cons(N, n, m, A, B, gam, z, 0, N, c, cm);
+    int64_t R = (int64_t)n * N;
+    int64_t nch = (R + OBJ_CHUNK - 1) / OBJ_CHUNK;
+    acc_t tot = {0.0, 0.0};
+    double mu = 0.0;
+    for (int64_t ch = 0; ch < nch; ch++) {
+        acc_t a = {0.0, 0.0};
+        int64_t e = (ch + 1) * OBJ_CHUNK < R ? (ch + 1) * OBJ_CHUNK : R;
+        for (int64_t x = ch * OBJ_CHUNK; x < e; x++) {
+            acc_add(&a, y[x] * c[x]);
+            mu += fabs(y[x]) * cm[x];
+        }
+        acc_add(&tot, a.s);
+        acc_add(&tot, a.c);
+    }
+    double yc = tot.s + tot.c;
+    out[0] = sigma * fo[0] + yc;
+    out[1] = fabs(sigma) * fo[1] + mu;
+    free(c);
+    free(cm);
+    return ORC_OK;
+}
+
+/* Jacobian entry d c_{i,kk} / d X_{j,node} for node in {kk, kk+1}, and its
+ * magnitude (the o4 table: -delta - hh G at the left node, delta - hh G at
+ * the right node). */
+static void jac_entry_x(int64_t N, int n, const double *A, const double *gam,
+                        const double *X, int i, int j, int64_t kk, int right,
+                        double *v, double *va)
+{
+    double hh = 0.5 * (1.0 / (double)N);
+    double d = (i == j) ? 1.0 : 0.0;
+    double g, ga;
+    dF_dx(N, n, A, gam, X, i, j, kk + right, &g, &ga);
+    *v = (right ? d : -d) - hh * g;
+    *va = d + hh * ga;
+}
+
+/* grad_z L at nodes [k0, k1) of [0, N]; layout as orc_grad. */
+int orc_lag_grad(int64_t N, int n, int m, const double *A, const double *B,
+                 const double *gam, const double *q, const double *r,
+                 const double *z, const double *y, double sigma,
+                 int64_t k0, int64_t k1, double *out, double *mu)
+{
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N + 1 || k0 > k1 || !z || !y || !out) return ORC_BAD;
+    const double *X = z;
+    const double *U = z + (int64_t)n * (N + 1);
+    double hh = 0.5 * (1.0 / (double)N);
+    int64_t K = k1 - k0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = k0; k < k1; k++) {
+        double w = weight(N, k);
+        for (int j = 0; j < n; j++) {
+            double s = 2.0 * sigma * w * q[j] * X[(int64_t)j * (N + 1) + k];
+            double sa = fabs(s);
+            for (int i = 0; i < n; i++) {
+                double v, va;
+                if (k >= 1) {  /* row (i, k-1): node k is its right node */
+                    jac_entry_x(N, n, A, gam, X, i, j, k - 1, 1, &v, &va);
+                    s += v * y[(int64_t)i * N + k - 1];
+                    sa += va * fabs(y[(int64_t)i * N + k - 1]);
+                }
+                if (k <= N - 1) {  /* row (i, k): node k is its left node */
+                    jac_entry_x(N, n, A, gam, X, i, j, k, 0, &v, &va);
+                    s += v * y[(int64_t)i * N + k];
+                    sa += va * fabs(y[(int64_t)i * N + k]);
+                }
+            }
+            out[(int64_t)j * K + (k - k0)] = s;
+            if (mu) mu[(int64_t)j * K + (k - k0)] = sa;
+        }
+        for (int l = 0; l < m; l++) {
+            double s = 2.0 * sigma * w * r[l] * U[(int64_t)l * (N + 1) + k];
+            double sa = fabs(s);
+            for (int i = 0; i < n; i++) {
+                double v = -hh * B[i * m + l];
+                if (k >= 1) { s += v * y[(int64_t)i * N + k - 1]; sa += fabs(v * y[(int64_t)i * N + k - 1]); }
+                if (k <= N - 1) { s += v * y[(int64_t)i * N + k]; sa += fabs(v * y[(int64_t)i * N + k]); }
+            }
+            out[(int64_t)(n + l) * K + (k - k0)] = s;
+            if (mu) mu[(int64_t)(n + l) * K + (k - k0)] = sa;
+        }
+    }
+    return ORC_OK;
+}
+
+/* (Hessian of L) v at nodes [k0, k1): the Hessian is block diagonal per node;
+ * each block entry is the second derivative of sigma w_k running cost minus
+ * hh sum_i yt_ik F_i(k), from the definitions
+ *   d2F_i/dX_a dX_b = -A_ia sin X_a [a = b] + gamma_i ([a = i][b = p(i)] + [a = p(i)][b = i]),
+ * controls enter F linearly. */
+int orc_hvp(int64_t N, int n, int m, const double *A, const double *gam,
+            const double *q, const double *r, const double *z, const double *y,
+            double sigma, const double *v, int64_t k0, int64_t k1, double *out, double *mu)
+{
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N + 1 || k0 > k1 || !z || !y || !v || !out) return ORC_BAD;
+    const double *X = z;
+    double hh = 0.5 * (1.0 / (double)N);
+    int64_t K = k1 - k0;
+    int nv = n + m;
+    #pragma omp parallel
+    {
+        double *Hb = (double *)malloc(sizeof(double) * 2 * nv * nv + sizeof(double) * 2 * n);
+        double *Ha = Hb + nv * nv;
+        double *yt = Ha + nv * nv, *ya = yt + n;
+        #pragma omp for schedule(static)
+        for (int64_t k = k0; k < k1; k++) {
+            double w = weight(N, k);
+            for (int i = 0; i < n; i++) {
+                double a = 0.0, aa = 0.0;
+                if (k >= 1) { a += y[(int64_t)i * N + k - 1]; aa += fabs(y[(int64_t)i * N + k - 1]); }
+                if (k <= N - 1) { a += y[(int64_t)i * N + k]; aa += fabs(y[(int64_t)i * N + k]); }
+                yt[i] = a;
+                ya[i] = aa;
+            }
+            for (int a = 0; a < nv; a++)
+                for (int b = 0; b < nv; b++) { Hb[a * nv + b] = 0.0; Ha[a * nv + b] = 0.0; }
+            for (int a = 0; a < n; a++) {
+                Hb[a * nv + a] += 2.0 * sigma * w * q[a];
+                Ha[a * nv + a] += fabs(2.0 * sigma * w * q[a]);
+            }
+            for (int l = 0; l < m; l++) {
+                Hb[(n + l) * nv + n + l] += 2.0 * sigma * w * r[l];
+                Ha[(n + l) * nv + n + l] += fabs(2.0 * sigma * w * r[l]);
+            }
+            for (int i = 0; i < n; i++) {
+                int p = (i + 1) % n;
+                for (int a = 0; a < n; a++) {
+                    double sx = sin(X[(int64_t)a * (N + 1) + k]);
+                    double t = -hh * yt[i] * (-A[i * n + a] * sx);
+                    Hb[a * nv + a] += t;
+                    Ha[a * nv + a] += hh * ya[i] * fabs(A[i * n + a] * sx);
+                }
+                /* gamma_i X_i X_p: d2/dX_i dX_p = d2/dX_p dX_i = gamma_i (both
+                 * on the diagonal, 2 gamma_i, when p = i) */
+                Hb[i * nv + p] += -hh * yt[i] * gam[i];
+                Hb[p * nv + i] += -hh * yt[i] * gam[i];
+                Ha[i * nv + p] += hh * ya[i] * fabs(gam[i]);
+                Ha[p * nv + i] += hh * ya[i] * fabs(gam[i]);
+            }
+            for (int a = 0; a < nv; a++) {
+                double s = 0.0, sa = 0.0;
+                for (int b = 0; b < nv; b++) {
+                    double vb = v[(int64_t)b * (N + 1) + k];
+                    s += Hb[a * nv + b] * vb;
+                    sa += Ha[a * nv + b] * fabs(vb);
+                }
+                out[(int64_t)a * K + (k - k0)] = s;
+                if (mu) mu[(int64_t)a * K + (k - k0)] = sa;
+            }
+        }
+        free(Hb);
+    }
+    return ORC_OK;
+}
+
+/* J v at intervals [k0, k1) of [0, N): (J v)_{ik} = sum over the row's slots
+ * of the Jacobian entry times v at the slot's column; layout as orc_cons. */
+int orc_jvp(int64_t N, int n, int m, const double *A, const double *B,
+            const double *gam, const double *z, const double *v,
+            int64_t k0, int64_t k1, double *out, double *mu)
+{
+    if (bad_sizes(N, n, m) || k0 < 0 || k1 > N || k0 > k1 || !z || !v || !out) return ORC_BAD;
+    const double *X = z;
+    const double *VU = v + (int64_t)n * (N + 1);
+    double hh = 0.5 * (1.0 / (double)N);
+    int64_t K = k1 - k0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = k0; k < k1; k++) {
+        for (int i = 0; i < n; i++) {
+            double s = 0.0, sa = 0.0;
+            for (int j = 0; j < n; j++) {
+                for (int right = 0; right <= 1; right++) {
+                    double e, ea;
+                    jac_entry_x(N, n, A, gam, X, i, j, k, right, &e, &ea);
+                    double vv = v[(int64_t)j * (N + 1) + k + right];
+                    s += e * vv;
+                    sa += ea * fabs(vv);
+                }
+            }
+            for (int l = 0; l < m; l++) {
+                for (int right = 0; right <= 1; right++) {
+                    double e = -hh * B[i * m + l];
+                    double vv = VU[(int64_t)l * (N + 1) + k + right];
+                    s += e * vv;
+                    sa += fabs(e * vv);
+                }
+            }
+            out[(int64_t)i * K + (k - k0)] = s;
+            if (mu) mu[(int64_t)i * K + (k - k0)] = sa;
+        }
+    }
+    return ORC_OK;
+}
+
+/* dL/dA (n x n), dL/dB (n x m), dL/dgamma (n): sum over defect rows (i, k) of
+ * y_ik dc_ik/dtheta, with
+ *   dc_ik/dA_ij = -hh (sin X_jk + sin X_j,k+1),
+ *   dc_ik/dB_il = -hh (U_lk + U_l,k+1),
+ *   dc_ik/dgamma_i = -hh (X_ik X_pk + X_i,k+1 X_p,k+1).
+ * Each sum runs over k in fixed chunks of OBJ_CHUNK with Neumaier
+ * compensation, chunks summed in order (independent of the thread count).
+ * mu arrays (nullable) get the sums of |terms|. */
+int orc_coef_grad(int64_t N, int n, int m, const double *z, const double *y,
+                  double *gA, double *gB, double *gg, double *muA, double *muB, double *mug)
+{
+    if (bad_sizes(N, n, m) || !z || !y || !gA || !gg || (m && !gB)) return ORC_BAD;
+    const double *X = z;
+    const double *U = z + (int64_t)n * (N + 1);
+    double hh = 0.5 * (1.0 / (double)N);
+    int nc = n * n + n * m + n;
+    int64_t nch = (N + OBJ_CHUNK - 1) / OBJ_CHUNK;
+    double *part = (double *)calloc((size_t)(nch * nc * 3), sizeof(double));
+    if (!part) return ORC_BAD;
+    #pragma omp parallel for schedule(static)
+    for (int64_t ch = 0; ch < nch; ch++) {
+        int64_t e = (ch + 1) * OBJ_CHUNK < N ? (ch + 1) * OBJ_CHUNK : N;
+        for (int c = 0; c < nc; c++) {
+            int i, kind, idx;
+            if (c < n * n) { kind = 0; i = c / n; idx = c % n; }
+            else if (c < n * n + n * m) { kind = 1; i = (c - n * n) / m; idx = (c - n * n) % m; }
+            else { kind = 2; i = c - n * n - n * m; idx = 0; }
+            int p = (i + 1) % n;
+            acc_t a = {0.0, 0.0};
+            double ma = 0.0;
+            for (int64_t k = ch * OBJ_CHUNK; k < e; k++) {
+                double d;
+                if (kind == 0)
+                    d = -hh * (sin(X[(int64_t)idx * (N + 1) + k]) + sin(X[(int64_t)idx * (N + 1) + k + 1]));
+                else if (kind == 1)
+                    d = -hh * (U[(int64_t)idx * (N + 1) + k] + U[(int64_t)idx * (N + 1) + k + 1]);
+                else
+                    d = -hh * (X[(int64_t)i * (N + 1) + k] * X[(int64_t)p * (N + 1) + k]
+                               + X[(int64_t)i * (N + 1) + k + 1] * X[(int64_t)p * (N + 1) + k + 1]);
+                double t = y[(int64_t)i * N + k] * d;
+                acc_add(&a, t);
+                ma += fabs(t);
+            }
+            part[(ch * nc + c) * 3 + 0] = a.s;
+            part[(ch * nc + c) * 3 + 1] = a.c;
+            part[(ch * nc + c) * 3 + 2] = ma;
+        }
+    }
+    for (int c = 0; c < nc; c++) {
+        acc_t a = {0.0, 0.0};
+        double ma = 0.0;
+        for (int64_t ch = 0; ch < nch; ch++) {
+            acc_add(&a, part[(ch * nc + c) * 3 + 0]);
+            acc_add(&a, part[(ch * nc + c) * 3 + 1]);
+            ma += part[(ch * nc + c) * 3 + 2];
+        }
+        double val = a.s + a.c;
+        if (c < n * n) { gA[c] = val; if (muA) muA[c] = ma; }
+        else if (c < n * n + n * m) { gB[c - n * n] = val; if (muB) muB[c - n * n] = ma; }
+        else { gg[c - n * n - n * m] = val; if (mug) mug[c - n * n - n * m] = ma; }
+    }
+    free(part);
+    return ORC_OK;
+}

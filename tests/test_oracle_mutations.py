@@ -8,6 +8,7 @@ import os
 import pytest
 
 import oracle
+from tests import test_oracle_diff_pins as D
 from tests import test_oracle_pins as P
 
 # (name, text in ocp_oracle.c, replacement)
@@ -37,6 +38,20 @@ MUTATIONS = [
      "if (x->col != y->col) return x->col < y->col ? 1 : -1;"),
     ("kkt diagonal position", "kkt[rowptr[d + 1] - 1] += reg[d]", "kkt[rowptr[d]] += reg[d]"),
     ("obj control term", "double t = r[l] * u * u;", "double t = r[l] * u;"),
+    ("lagrangian sigma", "out[0] = sigma * fo[0] + yc;", "out[0] = fo[0] + yc;"),
+    ("J^T y node side", "*v = (right ? d : -d) - hh * g;", "*v = (right ? -d : d) - hh * g;"),
+    ("J^T y multiplier index", "s += v * y[(int64_t)i * N + k - 1];", "s += v * y[(int64_t)i * N + k];"),
+    ("J^T y control weight", "double v = -hh * B[i * m + l];\n                if (k >= 1)",
+     "double v = -hh * B[l * n + i];\n                if (k >= 1)"),
+    ("hvp pair symmetry", "Hb[p * nv + i] += -hh * yt[i] * gam[i];", "Hb[p * nv + i] += 0.0 * yt[i];"),
+    ("hvp curvature sign", "double t = -hh * yt[i] * (-A[i * n + a] * sx);",
+     "double t = -hh * yt[i] * (A[i * n + a] * sx);"),
+    ("jvp control node", "double vv = VU[(int64_t)l * (N + 1) + k + right];",
+     "double vv = VU[(int64_t)l * (N + 1) + k];"),
+    ("coef grad A node", "d = -hh * (sin(X[(int64_t)idx * (N + 1) + k]) + sin(X[(int64_t)idx * (N + 1) + k + 1]));",
+     "d = -hh * (sin(X[(int64_t)idx * (N + 1) + k]) + sin(X[(int64_t)idx * (N + 1) + k]));"),
+    ("coef grad gamma partner", "d = -hh * (X[(int64_t)i * (N + 1) + k] * X[(int64_t)p * (N + 1) + k]",
+     "d = -hh * (X[(int64_t)i * (N + 1) + k] * X[(int64_t)i * (N + 1) + k]"),
 ]
 
 # Pins run against each mutant: (test function, arguments after the oracle).
@@ -56,6 +71,13 @@ PINS = [
     (P.test_gradient_complex_step_and_central_difference, (5, 3, 2)),
     (P.test_hessian_dense_mixed_difference, (2, 4, 2)),
     (P.test_hessian_dense_mixed_difference, (3, 1, 0)),
+    (D.test_lagrangian_value_high_precision, (7, 3, 2)),
+    (D.test_lag_grad_complex_step, (4, 3, 1)),
+    (D.test_lag_grad_complex_step, (6, 3, 3)),
+    (D.test_hvp_mixed_difference, (2, 4, 2)),
+    (D.test_hvp_mixed_difference, (3, 1, 0)),
+    (D.test_jvp_complex_step, (5, 4, 2)),
+    (D.test_coef_grad_complex_step_and_central_difference, (5, 3, 2)),
 ]
 
 
