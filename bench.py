@@ -1,6 +1,6 @@
 """Benchmark of the evaluation path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff]
 
 Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
 controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
@@ -186,6 +186,63 @@ def batched(torch, ocp, synth, reps=10):
     return out
 
 
+def differentiation(torch, ocp, synth, reps=20):
+    """The differentiation workload: N = 2e5, n = 8, m = 4.  Each Lagrangian
+    entry point timed on its own (HIP events, mean of `reps`), then one
+    autograd forward + backward of L(z, y) with gradients for z, y, A, B and
+    gamma, and one Hessian-vector product."""
+    from paper_2510_03932_amd.autograd import lagrangian
+    N, n, m = synth.DIFF
+    dev = torch.device("cuda", 0)
+    inst = synth.make_instance(N, n, m, seed=0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    s = prob.sizes
+    z = torch.from_numpy(inst.z).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    v = torch.from_numpy(np.random.default_rng(1).normal(size=s["nvar"])).to(dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    L, g, hv = torch.empty(1, **f64), torch.empty(s["nvar"], **f64), torch.empty(s["nvar"], **f64)
+    jv = torch.empty(s["ncon"], **f64)
+    nx, nv, nc = n * (N + 1), s["nvar"], s["ncon"]
+    calls = {
+        "lagrangian": (lambda: prob.lagrangian(z, y, 1.0, out=L), 8 * (nv + nc)),
+        "lag_grad": (lambda: prob.lag_grad(z, y, 1.0, out=g), 8 * (2 * nv + nc)),
+        "hvp": (lambda: prob.hvp(z, y, v, 1.0, out=hv), 8 * (nx + nc + 2 * nv)),
+        "jvp": (lambda: prob.jvp(z, v, out=jv), 8 * (nx + nv + nc)),
+        "coef_grad": (lambda: prob.coef_grad(z, y), 8 * (nv + nc)),
+    }
+    out = {"workload": f"N={N} n={n} m={m}, seed 0"}
+    for name, (fn, nbytes) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "bytes": nbytes,
+                     "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+    leaf = lambda a: torch.from_numpy(np.array(a)).to(dev).requires_grad_(True)
+    zt, yt, At, Bt, gt = (leaf(a) for a in (inst.z, inst.y, inst.A, inst.B, inst.gamma))
+
+    def fwd_bwd():
+        for t in (zt, yt, At, Bt, gt):
+            t.grad = None
+        lagrangian(prob, zt, yt, At, Bt, gt, 1.0).backward()
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    out["autograd_forward_backward_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+    prob.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +253,8 @@ def main():
                     help="run only the 512-instance batched measurement (profiling runs)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-instance batched measurement (profiling runs)")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the N=2e5 differentiation measurement (profiling runs)")
     ap.add_argument("--no-ipm-loop", action="store_true",
                     help="skip the N=1e5 interior-point-loop measurement (profiling runs)")
     ap.add_argument("--N", type=int, default=None, help="override the interval count")
@@ -369,6 +428,9 @@ def main():
     if not args.no_ipm_loop:
         log("[bench] interior-point loop workload")
         out["ipm_loop"] = ipm_loop(torch, ocp, synth)
+    if not args.no_diff:
+        log("[bench] differentiation workload")
+        out["differentiation"] = differentiation(torch, ocp, synth)
     if not args.no_batched:
         log("[bench] batched workload")
         out["batched"] = batched(torch, ocp, synth)

@@ -164,6 +164,45 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
                      const double *reg, double *kkt, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Lagrangian derivatives for differentiable programming (the paper names
+ * tighter integration with differentiable programming workflows as future
+ * work, Sec. 8).  L(z, y) = sigma f(z) + y^T c(z); the dynamics coefficients
+ * (A, B, gamma) are parameters of c.  All arrays are device pointers; every
+ * sum over nodes uses a fixed reduction order (bitwise reproducible).
+ * ------------------------------------------------------------------------- */
+
+/* Replace the handle's A (n x n), B (n x m; NULL when m = 0) and gamma (n)
+ * with device arrays, by stream-ordered device-to-device copies on `stream`.
+ * Evaluations queued on other streams must be ordered by the caller. */
+int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const double *gamma,
+                         hipStream_t stream);
+
+/* L(z, y) into L[0] (device).  Uses the handle's reduction workspace, like
+ * ocp_eval_obj (concurrent calls on one handle race). */
+int ocp_eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma,
+                        double *L, hipStream_t stream);
+
+/* grad_z L = sigma grad f + J^T y into g (nvar doubles). */
+int ocp_eval_lag_grad(const ocp_problem *p, const double *z, const double *y, double sigma,
+                      double *g, hipStream_t stream);
+
+/* Hessian-vector product (Hessian of L in z) v into out (nvar doubles); v has
+ * nvar doubles in the layout of z. */
+int ocp_eval_hvp(const ocp_problem *p, const double *z, const double *y, double sigma,
+                 const double *v, double *out, hipStream_t stream);
+
+/* Jacobian-vector product J v into out (ncon doubles); v has nvar doubles. */
+int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double *out,
+                 hipStream_t stream);
+
+/* Gradient of L with respect to the dynamics coefficients: gA (n x n
+ * row-major), gB (n x m; may be NULL when m = 0), ggamma (n), each a sum over
+ * all nodes.  Uses the handle's coefficient-gradient workspace (concurrent
+ * calls on one handle race). */
+int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA,
+                       double *gB, double *ggamma, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many independent instances with their own N_b and coefficients
  * (shared n, m), evaluated together.  The paper motivates data parallelism
  * across grid nodes (Sec. 3) and real-time use; a batch extends the same

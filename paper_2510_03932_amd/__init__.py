@@ -83,6 +83,12 @@ def lib():
         L.ocp_eval_hess.argtypes = [vp, vp, vp, dbl, vp, vp]
         L.ocp_assemble_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_last_error.restype = ctypes.c_char_p
+        L.ocp_set_coefficients.argtypes = [vp, vp, vp, vp, vp]
+        L.ocp_eval_lagrangian.argtypes = [vp, vp, vp, dbl, vp, vp]
+        L.ocp_eval_lag_grad.argtypes = [vp, vp, vp, dbl, vp, vp]
+        L.ocp_eval_hvp.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
+        L.ocp_eval_jvp.argtypes = [vp, vp, vp, vp, vp]
+        L.ocp_eval_coef_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ocp_batch_create.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.ocp_batch_destroy.argtypes = [vp]
         L.ocp_batch_destroy.restype = None
@@ -269,6 +275,67 @@ class Problem:
         _check(lib().ocp_assemble_kkt(self._h, pj, ph, rp, jp, hp, gp, op, self._stream()),
                "ocp_assemble_kkt")
         return out
+
+    # -- Lagrangian derivatives ---------------------------------------------------
+    def set_coefficients(self, A, B, gamma):
+        """Copy device tensors A (n, n), B (n, m), gamma (n,) into the handle
+        (stream-ordered on the current stream)."""
+        torch = _torch()
+        n, m = self.n, self.m
+        Ap = self._dev(A.contiguous(), n * n, torch.float64, "A")
+        Bp = self._dev(B.contiguous(), n * m, torch.float64, "B") if m else None
+        gp = self._dev(gamma.contiguous(), n, torch.float64, "gamma")
+        _check(lib().ocp_set_coefficients(self._h, Ap, Bp, gp, self._stream()), "ocp_set_coefficients")
+
+    def lagrangian(self, z, y, sigma=1.0, out=None):
+        torch = _torch()
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        out, op = self._out(out, 1, "L")
+        _check(lib().ocp_eval_lagrangian(self._h, zp, yp, float(sigma), op, self._stream()),
+               "ocp_eval_lagrangian")
+        return out
+
+    def lag_grad(self, z, y, sigma=1.0, out=None):
+        torch = _torch()
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        out, op = self._out(out, self.sizes["nvar"], "grad_z L")
+        _check(lib().ocp_eval_lag_grad(self._h, zp, yp, float(sigma), op, self._stream()),
+               "ocp_eval_lag_grad")
+        return out
+
+    def hvp(self, z, y, v, sigma=1.0, out=None):
+        torch = _torch()
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        vp = self._dev(v, self.sizes["nvar"], torch.float64, "v")
+        out, op = self._out(out, self.sizes["nvar"], "H v")
+        _check(lib().ocp_eval_hvp(self._h, zp, yp, float(sigma), vp, op, self._stream()),
+               "ocp_eval_hvp")
+        return out
+
+    def jvp(self, z, v, out=None):
+        torch = _torch()
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        vp = self._dev(v, self.sizes["nvar"], torch.float64, "v")
+        out, op = self._out(out, self.sizes["ncon"], "J v")
+        _check(lib().ocp_eval_jvp(self._h, zp, vp, op, self._stream()), "ocp_eval_jvp")
+        return out
+
+    def coef_grad(self, z, y):
+        """(dL/dA (n, n), dL/dB (n, m), dL/dgamma (n,)) as device tensors."""
+        torch = _torch()
+        n, m = self.n, self.m
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        f64 = dict(dtype=torch.float64, device=self.device)
+        gA, gB, gg = torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64)
+        _check(lib().ocp_eval_coef_grad(self._h, zp, yp, ctypes.c_void_p(gA.data_ptr()),
+                                        ctypes.c_void_p(gB.data_ptr()) if m else None,
+                                        ctypes.c_void_p(gg.data_ptr()), self._stream()),
+               "ocp_eval_coef_grad")
+        return gA, gB, gg
 
 
 def _autotune_cache_path() -> str:

@@ -1,0 +1,132 @@
+"""PyTorch autograd over the transcribed Lagrangian L(z, y) = sigma f(z) + y^T c(z).
+
+Forward and every derivative run in the library's HIP kernels (through the C
+ABI); PyTorch supplies the tensors, streams and the autograd graph.
+
+    L = lagrangian(prob, z, y, A, B, gamma, sigma)       # 0-dim tensor
+    L.backward()   # z.grad = grad_z L, y.grad = c(z), A.grad = dL/dA, ...
+
+Second order: grad_z L is itself differentiable in (z, y), so
+``torch.autograd.grad(L, z, create_graph=True)`` followed by a backward with a
+vector v gives the Hessian-vector product (Hessian of L) v for z and J v for y.
+Second derivatives that mix the coefficients (A, B, gamma) are not provided
+and raise.
+"""
+from __future__ import annotations
+
+import torch
+
+
+def _coefficients(prob, A, B, gamma):
+    prob.set_coefficients(A.detach(), B.detach(), gamma.detach())
+
+
+class _LagGrad(torch.autograd.Function):
+    """grad_z L as a function of (z, y, A, B, gamma); its backward gives
+    (Hessian of L) v for z and J v for y."""
+
+    @staticmethod
+    def forward(ctx, z, y, A, B, gamma, sigma, prob):
+        _coefficients(prob, A, B, gamma)
+        ctx.save_for_backward(z, y, A, B, gamma)
+        ctx.sigma, ctx.prob = sigma, prob
+        return prob.lag_grad(z.detach().contiguous(), y.detach().contiguous(), sigma)
+
+    @staticmethod
+    def backward(ctx, v):
+        z, y, A, B, gamma = ctx.saved_tensors
+        prob = ctx.prob
+        if any(ctx.needs_input_grad[2:5]):
+            raise NotImplementedError("second derivatives in the dynamics coefficients "
+                                      "(A, B, gamma) are not provided")
+        _coefficients(prob, A, B, gamma)
+        v = v.contiguous()
+        gz = gy = None
+        if ctx.needs_input_grad[0]:
+            gz = prob.hvp(z.detach().contiguous(), y.detach().contiguous(), v, ctx.sigma)
+        if ctx.needs_input_grad[1]:
+            gy = prob.jvp(z.detach().contiguous(), v)
+        return gz, gy, None, None, None, None, None
+
+
+class _Cons(torch.autograd.Function):
+    """c(z) as a function of (z, A, B, gamma); its backward is the
+    vector-Jacobian product: J^T w for z (grad_z of w^T c, i.e. grad_z L with
+    sigma = 0 and multipliers w) and the coefficient gradient of w^T c."""
+
+    @staticmethod
+    def forward(ctx, z, A, B, gamma, prob):
+        _coefficients(prob, A, B, gamma)
+        ctx.save_for_backward(z, A, B, gamma)
+        ctx.prob = prob
+        return prob.cons(z.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, w):
+        z, A, B, gamma = ctx.saved_tensors
+        prob = ctx.prob
+        if torch.is_grad_enabled() and (w.requires_grad or z.requires_grad):
+            raise NotImplementedError("third derivatives of the defects are not provided")
+        _coefficients(prob, A, B, gamma)
+        zd, w = z.detach().contiguous(), w.detach().contiguous()
+        gz = prob.lag_grad(zd, w, 0.0) if ctx.needs_input_grad[0] else None
+        gA = gB = gg = None
+        if any(ctx.needs_input_grad[1:4]):
+            gA, gB, gg = prob.coef_grad(zd, w)
+        return gz, gA, gB, gg, None
+
+
+class _CoefGrad(torch.autograd.Function):
+    """dL/d(A, B, gamma) as a function of (z, y); second derivatives raise."""
+
+    @staticmethod
+    def forward(ctx, z, y, A, B, gamma, prob):
+        _coefficients(prob, A, B, gamma)
+        return prob.coef_grad(z.detach().contiguous(), y.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, *grads):
+        raise NotImplementedError("second derivatives in the dynamics coefficients "
+                                  "(A, B, gamma) are not provided")
+
+
+class _Lagrangian(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z, y, A, B, gamma, sigma, prob):
+        _coefficients(prob, A, B, gamma)
+        ctx.save_for_backward(z, y, A, B, gamma)
+        ctx.sigma, ctx.prob = sigma, prob
+        return prob.lagrangian(z.detach().contiguous(), y.detach().contiguous(), sigma)[0]
+
+    @staticmethod
+    def backward(ctx, gL):
+        z, y, A, B, gamma = ctx.saved_tensors
+        prob, sigma = ctx.prob, ctx.sigma
+        gz = gy = gA = gB = gg = None
+        # each piece goes through a Function of its own so that a create_graph
+        # backward stays differentiable where it is defined
+        if ctx.needs_input_grad[0]:
+            gz = _LagGrad.apply(z, y, A, B, gamma, sigma, prob) * gL
+        if ctx.needs_input_grad[1]:
+            gy = _Cons.apply(z, A, B, gamma, prob) * gL
+        if any(ctx.needs_input_grad[2:5]):
+            dA, dB, dg = _CoefGrad.apply(z, y, A, B, gamma, prob)
+            gA, gB, gg = dA * gL, dB * gL, dg * gL
+        return gz, gy, gA, gB, gg, None, None
+
+
+def lagrangian(prob, z, y, A, B, gamma, sigma: float = 1.0):
+    """L(z, y) = sigma f(z) + y^T c(z) with differentiable z, y, A (n, n),
+    B (n, m) and gamma (n,) (float64 tensors on the problem's device);
+    sigma is a plain number."""
+    return _Lagrangian.apply(z, y, A, B, gamma, float(sigma), prob)
+
+
+def lagrangian_grad(prob, z, y, A, B, gamma, sigma: float = 1.0):
+    """grad_z L as a differentiable function of (z, y)."""
+    return _LagGrad.apply(z, y, A, B, gamma, float(sigma), prob)
+
+
+def constraints(prob, z, A, B, gamma):
+    """c(z) as a differentiable function of (z, A, B, gamma)."""
+    return _Cons.apply(z, A, B, gamma, prob)

@@ -53,6 +53,32 @@ __device__ __forceinline__ void st_nt2(double *p, dbl2 v)
     __builtin_nontemporal_store(v, reinterpret_cast<dbl2 *>(p));
 }
 
+// Fixed-shape sums: over a wavefront (cross-lane shuffles, tree of halving
+// offsets) and over a workgroup of BS lanes (wavefront sums, then the BS/64
+// wave totals in order).  The order of additions never depends on timing.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <int BS>
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double ws[BS / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) ws[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < BS / 64; i++) t += ws[i];
+    }
+    return t;  // valid in thread 0
+}
+
 // ---------------------------------------------------------------------------
 // Jacobian values of one column for NPT consecutive intervals k .. k+NPT-1
 // (the caller guarantees k + NPT <= N, and for NPT = 2 a 16-byte aligned
@@ -182,6 +208,59 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
     }
     const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
     for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
+}
+
+// ---------------------------------------------------------------------------
+// Dynamics at node k <= N: the node's states x[i] = X_ik and F_i(k) for every
+// i < n (NB >= n, entries beyond n are zero).  F_i sums j ascending, then l
+// ascending, then the bilinear term.
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__ z, int64_t k,
+                                         double (&x)[NB], double (&F)[NB])
+{
+    const int n = P.n, m = P.m;
+    const int64_t N1 = P.N1;
+    const double *U = z + (int64_t)n * N1;
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        x[i] = (i < n) ? z[i * N1 + k] : 0.0;
+        F[i] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        if (j < n) {
+            const double s = sin(x[j]);
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) F[i] += P.A[i * n + j] * s;
+        }
+    }
+    for (int l = 0; l < m; l++) {
+        const double u = U[l * N1 + k];
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) F[i] += P.B[i * m + l] * u;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        if (i < n) {
+            const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
+            F[i] += P.gam[i] * x[i] * xp;
+        }
+    }
+}
+
+// Entry n-1 of a register array (n is a run-time value <= NB), by selects so
+// the array stays in registers.
+template <int NB>
+__device__ __forceinline__ double last_of(const double (&a)[NB], int n)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+        if (i == n - 1) v = a[i];
+    return v;
 }
 
 // Host-side launchers of the single-instance Jacobian and Hessian kernels

@@ -1,0 +1,424 @@
+// Derivatives of the Lagrangian L(z, y) = sigma f(z) + y^T c(z) beyond the
+// interior-point evaluations: its value, grad_z L, Hessian-vector and
+// Jacobian-vector products, and the gradient with respect to the dynamics
+// coefficients (A, B, gamma) -- the pieces a differentiable-programming
+// wrapper needs (the paper names tighter integration with differentiable
+// programming as future work, Sec. 8).
+//
+// With the node multiplier yt_ik = y_{i,k-1}[k >= 1] + y_ik[k < N] (node k
+// closes interval k-1 and opens interval k):
+//   grad_z L at X_jk  = 2 sigma w_k q_j X_jk + y_{j,k-1} - y_jk
+//                       - hh (cos X_jk (A^T yt)_j + yt_j gamma_j X_{p(j)k}
+//                             + yt_{j-1} gamma_{j-1} X_{j-1,k})
+//   grad_z L at U_lk  = 2 sigma w_k r_l U_lk - hh (B^T yt)_l
+//   (H v) at node k   = diag_j v_j + P_j v_{p(j)} + P_{j-1} v_{j-1},
+//                       diag_j = 2 sigma w_k q_j + hh sin X_jk (A^T yt)_j,
+//                       P_i = -hh yt_i gamma_i;  controls 2 sigma w_k r_l v
+//   (J v)_ik          = (v_{i,k+1} - v_ik) - hh (D_i(k) + D_i(k+1)),
+//                       D_i = sum_j A_ij cos X_j v_j + sum_l B_il v_l
+//                             + gamma_i (X_p v_i + X_i v_p)
+//   dL/dA_ij = -hh sum_k yt_ik sin X_jk,  dL/dB_il = -hh sum_k yt_ik U_lk,
+//   dL/dgamma_i = -hh sum_k yt_ik X_ik X_{p(i)k}.
+// Every sum over nodes is a fixed-shape two-pass reduction (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "ocp_device.h"
+#include "ocp_internal.h"
+#include "ocp_problem.h"
+
+using namespace ocp;
+using namespace ocp::dev;
+
+namespace {
+
+constexpr int kCols = 8;  // coefficient-gradient columns per workgroup
+
+// Lagrangian value, pass 1.  Chunk c covers nodes [c (B-1), c (B-1) + B) and
+// closes the B-1 intervals starting there (one node of overlap, as in the
+// defect kernel); workgroups take chunks c = blockIdx.x, + gridDim.x, ...
+// A node's cost term is counted by the chunk that owns it (lane < B-1, or
+// the last node N).
+template <int NB>
+__global__ __launch_bounds__(kBlock) void lag_partial_kernel(KP P, const double *__restrict__ z,
+                                                             const double *__restrict__ y,
+                                                             double sigma, int nchunks,
+                                                             double *__restrict__ partials)
+{
+    __shared__ double Ms[NB][kBlock];
+    const int tid = threadIdx.x;
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1;
+    const double *U = z + (int64_t)n * N1;
+    double acc = 0.0;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t k = (int64_t)ch * (kBlock - 1) + tid;
+        double Pk[NB];
+        if (k <= N) {
+            double x[NB], F[NB];
+            dyn_node<NB>(P, z, k, x, F);
+#pragma unroll
+            for (int i = 0; i < NB; i++) {
+                if (i < n) {
+                    Ms[i][tid] = x[i] - P.hh * F[i];
+                    Pk[i] = x[i] + P.hh * F[i];
+                }
+            }
+            if (tid < kBlock - 1 || k == N) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < NB; i++)
+                    if (i < n) s += P.q[i] * x[i] * x[i];
+                for (int l = 0; l < m; l++) {
+                    const double u = U[l * N1 + k];
+                    s += P.r[l] * u * u;
+                }
+                acc += sigma * node_weight(P, (int)k) * s;
+            }
+        }
+        __syncthreads();
+        if (tid < kBlock - 1 && k < N) {
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) acc += y[i * N + k] * (Ms[i][tid + 1] - Pk[i]);
+        }
+        __syncthreads();
+    }
+    const double t = block_sum<kBlock>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double *__restrict__ partials,
+                                                              int count, double *__restrict__ out)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) acc += partials[i];
+    const double t = block_sum<kBlock>(acc);
+    if (threadIdx.x == 0) out[0] = t;
+}
+
+// Loads shared by grad_z L and H v at node k: states and node multipliers.
+template <int NB>
+__device__ __forceinline__ void node_x_yt(const KP &P, const double *__restrict__ z,
+                                          const double *__restrict__ y, int k, double (&x)[NB],
+                                          double (&yl)[NB], double (&yr)[NB])
+{
+    const int n = P.n;
+    const int64_t N = P.N, N1 = P.N1;
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        x[i] = yl[i] = yr[i] = 0.0;
+        if (i < n) {
+            x[i] = z[i * N1 + k];
+            const double *yi = y + i * N + k;
+            if (k >= 1) yl[i] = yi[-1];
+            if (k < P.N) yr[i] = yi[0];
+        }
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void lag_grad_kernel(KP P, const double *__restrict__ z,
+                                                          const double *__restrict__ y, double sigma,
+                                                          double *__restrict__ g)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    const int n = P.n, m = P.m;
+    const int64_t N1 = P.N1;
+    const double w = node_weight(P, k);
+    double x[NB], yl[NB], yr[NB], yt[NB];
+    node_x_yt<NB>(P, z, y, k, x, yl, yr);
+#pragma unroll
+    for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
+    const double x_last = last_of<NB>(x, n), yt_last = last_of<NB>(yt, n);
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        if (j < n) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) s += yt[i] * P.A[i * n + j];
+            const double xn = (j + 1 < n) ? x[(j + 1) % NB] : x[0];
+            const int jm = (j == 0) ? n - 1 : j - 1;
+            const double xm = (j == 0) ? x_last : x[(j + NB - 1) % NB];
+            const double ym = (j == 0) ? yt_last : yt[(j + NB - 1) % NB];
+            const double G = cos(x[j]) * s + yt[j] * P.gam[j] * xn + ym * P.gam[jm] * xm;
+            st_nt(g + j * N1 + k, 2.0 * sigma * w * P.q[j] * x[j] + (yl[j] - yr[j]) - P.hh * G);
+        }
+    }
+    const double *U = z + (int64_t)n * N1;
+    for (int l = 0; l < m; l++) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) s += yt[i] * P.B[i * m + l];
+        st_nt(g + (n + l) * N1 + k, 2.0 * sigma * w * P.r[l] * U[l * N1 + k] - P.hh * s);
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void hvp_kernel(KP P, const double *__restrict__ z,
+                                                     const double *__restrict__ y, double sigma,
+                                                     const double *__restrict__ v,
+                                                     double *__restrict__ out)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    const int n = P.n, m = P.m;
+    const int64_t N1 = P.N1;
+    const double w = node_weight(P, k);
+    double x[NB], yl[NB], yr[NB], vx[NB], pr[NB];
+    node_x_yt<NB>(P, z, y, k, x, yl, yr);
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        vx[i] = (i < n) ? v[i * N1 + k] : 0.0;
+        pr[i] = (i < n) ? -P.hh * (yl[i] + yr[i]) * P.gam[i] : 0.0;
+    }
+    const double v_last = last_of<NB>(vx, n), p_last = last_of<NB>(pr, n);
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        if (j < n) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) s += (yl[i] + yr[i]) * P.A[i * n + j];
+            const double d = 2.0 * sigma * w * P.q[j] + P.hh * sin(x[j]) * s;
+            const double vn = (j + 1 < n) ? vx[(j + 1) % NB] : vx[0];
+            const double vm = (j == 0) ? v_last : vx[(j + NB - 1) % NB];
+            const double pm = (j == 0) ? p_last : pr[(j + NB - 1) % NB];
+            st_nt(out + j * N1 + k, d * vx[j] + pr[j] * vn + pm * vm);
+        }
+    }
+    for (int l = 0; l < m; l++) {
+        const int64_t e = (int64_t)(n + l) * N1 + k;
+        st_nt(out + e, 2.0 * sigma * w * P.r[l] * v[e]);
+    }
+}
+
+// J v, laid out like the defects: lane k publishes v_ik - hh D_i(k) for lane
+// k-1 and keeps v_ik + hh D_i(k).
+template <int NB>
+__global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restrict__ z,
+                                                     const double *__restrict__ v,
+                                                     double *__restrict__ out)
+{
+    __shared__ double Ms[NB][kBlock];
+    const int tid = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1;
+    double Pk[NB];
+    if (k <= N) {
+        double x[NB], vx[NB], D[NB];
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            x[i] = (i < n) ? z[i * N1 + k] : 0.0;
+            vx[i] = (i < n) ? v[i * N1 + k] : 0.0;
+            D[i] = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            if (j < n) {
+                const double t = cos(x[j]) * vx[j];
+#pragma unroll
+                for (int i = 0; i < NB; i++)
+                    if (i < n) D[i] += P.A[i * n + j] * t;
+            }
+        }
+        for (int l = 0; l < m; l++) {
+            const double u = v[(n + l) * N1 + k];
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) D[i] += P.B[i * m + l] * u;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            if (i < n) {
+                const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
+                const double vp = (i + 1 < n) ? vx[(i + 1) % NB] : vx[0];
+                D[i] += P.gam[i] * (xp * vx[i] + x[i] * vp);
+                Ms[i][tid] = vx[i] - P.hh * D[i];
+                Pk[i] = vx[i] + P.hh * D[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < kBlock - 1 && k < N) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_nt(out + i * N + k, Ms[i][tid + 1] - Pk[i]);
+    }
+}
+
+// Coefficient gradient, pass 1.  Grid (G, n, ceil((n+m+1)/kCols)): row i,
+// columns c0 .. c0+kCols-1 of [A row i | B row i | gamma_i]; lanes take nodes
+// k = blockIdx.x * B + lane + s G B in order; each column's workgroup total
+// goes to cpart[(i (n+m+1) + col) G + blockIdx.x].
+__global__ __launch_bounds__(kBlock) void coef_partial_kernel(KP P, const double *__restrict__ z,
+                                                              const double *__restrict__ y, int G,
+                                                              double *__restrict__ cpart)
+{
+    __shared__ double ws[kCols][kBlock / 64];
+    const int n = P.n, m = P.m, ncol = n + m + 1;
+    const int i = blockIdx.y, c0 = blockIdx.z * kCols;
+    const int p = (i + 1 == n) ? 0 : i + 1;
+    const int64_t N = P.N, N1 = P.N1;
+    double acc[kCols];
+#pragma unroll
+    for (int c = 0; c < kCols; c++) acc[c] = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k <= N; k += (int64_t)G * kBlock) {
+        const double *yi = y + i * N + k;
+        const double yt = (k >= 1 ? yi[-1] : 0.0) + (k < N ? yi[0] : 0.0);
+#pragma unroll
+        for (int c = 0; c < kCols; c++) {
+            const int col = c0 + c;
+            if (col < n) acc[c] += yt * sin(z[col * N1 + k]);
+            else if (col < n + m) acc[c] += yt * z[col * N1 + k];
+            else if (col == n + m) acc[c] += yt * (z[i * N1 + k] * z[p * N1 + k]);
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kCols; c++) {
+        const double t = wave_sum(acc[c]);
+        if (lane == 0) ws[c][wid] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kCols) {
+        const int col = c0 + threadIdx.x;
+        if (col < ncol) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; w++) t += ws[threadIdx.x][w];
+            cpart[((int64_t)i * ncol + col) * G + blockIdx.x] = t;
+        }
+    }
+}
+
+// Pass 2: one workgroup per coefficient; lane b < G holds workgroup b's
+// partial and a fixed-shape tree adds them.
+__global__ __launch_bounds__(kBlock) void coef_final_kernel(KP P, const double *__restrict__ cpart,
+                                                            int G, double *__restrict__ gA,
+                                                            double *__restrict__ gB,
+                                                            double *__restrict__ gg)
+{
+    const int n = P.n, m = P.m, ncol = n + m + 1;
+    const int idx = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock) s += cpart[(int64_t)idx * G + b];
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x != 0) return;
+    const double val = -P.hh * s;
+    const int i = idx / ncol, col = idx - i * ncol;
+    if (col < n) gA[i * n + col] = val;
+    else if (col < n + m) gB[i * m + (col - n)] = val;
+    else gg[i] = val;
+}
+
+int nb_of(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
+
+}  // namespace
+
+#define OCP_DISPATCH_NB(n, KERNEL, grid, ...)                                                   \
+    do {                                                                                        \
+        switch (nb_of(n)) {                                                                     \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, grid, dim3(kBlock), 0, __VA_ARGS__); break;      \
+        case 8: hipLaunchKernelGGL(KERNEL<8>, grid, dim3(kBlock), 0, __VA_ARGS__); break;      \
+        case 16: hipLaunchKernelGGL(KERNEL<16>, grid, dim3(kBlock), 0, __VA_ARGS__); break;    \
+        default: hipLaunchKernelGGL(KERNEL<32>, grid, dim3(kBlock), 0, __VA_ARGS__); break;    \
+        }                                                                                       \
+    } while (0)
+
+extern "C" {
+
+int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const double *gamma,
+                         hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_set_coefficients")) return rc;
+    if (!A || !gamma || (p->d.m > 0 && !B)) return fail(OCP_ERR_ARG, "ocp_set_coefficients: NULL array");
+    const int n = p->d.n, m = p->d.m;
+    hipError_t e = hipMemcpyAsync(const_cast<double *>(p->kp.A), A, sizeof(double) * n * n,
+                                  hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && m)
+        e = hipMemcpyAsync(const_cast<double *>(p->kp.B), B, sizeof(double) * n * m,
+                           hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<double *>(p->kp.gam), gamma, sizeof(double) * n,
+                           hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail("ocp_set_coefficients", e);
+    return OCP_OK;
+}
+
+int ocp_eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma,
+                        double *L, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_lagrangian")) return rc;
+    if (!z || !y || !L) return fail(OCP_ERR_ARG, "ocp_eval_lagrangian: null array");
+    if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_lagrangian: sigma is not finite");
+    const int nchunks = (int)blocks_for(p->d.N, kBlock - 1);
+    const int g = std::min(nchunks, kObjBlocks);
+    OCP_DISPATCH_NB(p->d.n, lag_partial_kernel, dim3(g), stream, p->kp, z, y, sigma, nchunks, p->partials);
+    if (int rc = check_launch("ocp_eval_lagrangian")) return rc;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, g, L);
+    return check_launch("ocp_eval_lagrangian");
+}
+
+int ocp_eval_lag_grad(const ocp_problem *p, const double *z, const double *y, double sigma,
+                      double *g, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_lag_grad")) return rc;
+    if (!z || !y || !g) return fail(OCP_ERR_ARG, "ocp_eval_lag_grad: null array");
+    if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_lag_grad: sigma is not finite");
+    OCP_DISPATCH_NB(p->d.n, lag_grad_kernel, dim3(blocks_for(p->d.N1, kBlock)), stream, p->kp, z, y,
+                    sigma, g);
+    return check_launch("ocp_eval_lag_grad");
+}
+
+int ocp_eval_hvp(const ocp_problem *p, const double *z, const double *y, double sigma,
+                 const double *v, double *out, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_hvp")) return rc;
+    if (!z || !y || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_hvp: null array");
+    if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_hvp: sigma is not finite");
+    OCP_DISPATCH_NB(p->d.n, hvp_kernel, dim3(blocks_for(p->d.N1, kBlock)), stream, p->kp, z, y, sigma,
+                    v, out);
+    return check_launch("ocp_eval_hvp");
+}
+
+int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double *out,
+                 hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_jvp")) return rc;
+    if (!z || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_jvp: null array");
+    OCP_DISPATCH_NB(p->d.n, jvp_kernel, dim3(blocks_for(p->d.N, kBlock - 1)), stream, p->kp, z, v,
+                    out);
+    return check_launch("ocp_eval_jvp");
+}
+
+int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA,
+                       double *gB, double *ggamma, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_coef_grad")) return rc;
+    if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB))
+        return fail(OCP_ERR_ARG, "ocp_eval_coef_grad: null array");
+    const int n = p->d.n, m = p->d.m, ncol = n + m + 1;
+    const int G = (int)std::min<int64_t>(kCoefBlocks, blocks_for(p->d.N1, kBlock));
+    const dim3 grid(G, n, (ncol + kCols - 1) / kCols);
+    hipLaunchKernelGGL(coef_partial_kernel, grid, dim3(kBlock), 0, stream, p->kp, z, y, G, p->cpart);
+    if (int rc = check_launch("ocp_eval_coef_grad")) return rc;
+    hipLaunchKernelGGL(coef_final_kernel, dim3(n * ncol), dim3(kBlock), 0, stream, p->kp, p->cpart, G,
+                       gA, gB, ggamma);
+    return check_launch("ocp_eval_coef_grad");
+}
+
+}  // extern "C"

@@ -13,13 +13,12 @@
 
 #include "ocp_device.h"
 #include "ocp_internal.h"
+#include "ocp_problem.h"
 
 using namespace ocp;
 using namespace ocp::dev;
 
 namespace {
-
-constexpr int kObjBlocks = 4096;     // most partials of the objective sum
 
 // ---------------------------------------------------------------------------
 // Jacobian values.  2-D grid: blockIdx.x picks NPT intervals per lane,
@@ -64,37 +63,15 @@ __global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__rest
     __shared__ double Ms[NB][kBlock];
     const int tid = threadIdx.x;
     const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
-    const int n = P.n, m = P.m;
-    const int64_t N = P.N, N1 = P.N1;
-    const double *U = z + (int64_t)n * N1;
+    const int n = P.n;
+    const int64_t N = P.N;
     double Pk[NB];
     if (k <= N) {
         double x[NB], F[NB];
-#pragma unroll
-        for (int i = 0; i < NB; i++) {
-            x[i] = (i < n) ? z[i * N1 + k] : 0.0;
-            F[i] = 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-            if (j < n) {
-                const double s = sin(x[j]);
-#pragma unroll
-                for (int i = 0; i < NB; i++)
-                    if (i < n) F[i] += P.A[i * n + j] * s;
-            }
-        }
-        for (int l = 0; l < m; l++) {
-            const double u = U[l * N1 + k];
-#pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) F[i] += P.B[i * m + l] * u;
-        }
+        dyn_node<NB>(P, z, k, x, F);
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             if (i < n) {
-                const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
-                F[i] += P.gam[i] * x[i] * xp;
                 Ms[i][tid] = x[i] - P.hh * F[i];
                 Pk[i] = x[i] + P.hh * F[i];
             }
@@ -130,28 +107,6 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__rest
 // shuffles) and over the 4 waves; pass 2: one workgroup sums the partials in a
 // fixed order.  The grid depends only on N, so the result is reproducible.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-__device__ double block_sum(double v)
-{
-    __shared__ double ws[kBlock / 64];
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) ws[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kBlock / 64; i++) t += ws[i];
-    }
-    return t;  // valid in thread 0
-}
-
 __global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double *__restrict__ z,
                                                              double *__restrict__ partials)
 {
@@ -168,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double 
         }
         acc += node_weight(P, (int)k) * s;
     }
-    const double t = block_sum(acc);
+    const double t = block_sum<kBlock>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -177,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void obj_final_kernel(const double *__restr
 {
     double acc = 0.0;
     for (int i = threadIdx.x; i < count; i += kBlock) acc += partials[i];
-    const double t = block_sum(acc);
+    const double t = block_sum<kBlock>(acc);
     if (threadIdx.x == 0) obj[0] = t;
 }
 
@@ -340,37 +295,6 @@ hipError_t launch_hess(const KP &P, const double *z, const double *y, double sig
 }  // namespace dev
 }  // namespace ocp
 
-struct ocp_problem {
-    Dims d;
-    int device;
-    double *coef;      // device: A | B | gamma | q | r
-    double *partials;  // device: kObjBlocks doubles
-    KP kp;
-};
-
-static int hip_fail(const char *what, hipError_t e)
-{
-    return fail(OCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-static int check_launch(const char *what)
-{
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(what, e);
-    return OCP_OK;
-}
-
-static int check_handle(const ocp_problem *p, const char *what)
-{
-    if (!p) return fail(OCP_ERR_ARG, std::string(what) + ": problem handle is NULL");
-    return OCP_OK;
-}
-
-static unsigned blocks_for(int64_t count, int per_block)
-{
-    return (unsigned)((count + per_block - 1) / per_block);
-}
-
 extern "C" {
 
 int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B,
@@ -396,9 +320,10 @@ int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B
     e = hipMalloc(&p->coef, ncoef * sizeof(double));
     if (e != hipSuccess) { delete p; return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e)); }
     e = hipMalloc(&p->partials, kObjBlocks * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc(&p->cpart, (size_t)n * (n + m + 1) * kCoefBlocks * sizeof(double));
     if (e != hipSuccess) {
-        (void)hipFree(p->coef);
-        delete p;
+        ocp_destroy(p);
         return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e));
     }
     double *host = new (std::nothrow) double[ncoef];
@@ -438,6 +363,7 @@ void ocp_destroy(ocp_problem *p)
     if (!p) return;
     if (p->coef) (void)hipFree(p->coef);
     if (p->partials) (void)hipFree(p->partials);
+    if (p->cpart) (void)hipFree(p->cpart);
     delete p;
 }
 

@@ -1,0 +1,47 @@
+// The single-instance problem handle and host helpers shared by the
+// translation units that implement its entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "ocp_device.h"
+#include "ocp_internal.h"
+
+// Most partial sums of the one-pass-per-workgroup reductions (objective,
+// Lagrangian value), and workgroups per row of the coefficient-gradient sum.
+constexpr int kObjBlocks = 4096;
+constexpr int kCoefBlocks = 256;
+
+struct ocp_problem {
+    ocp::Dims d;
+    int device;
+    double *coef;       // device: A | B | gamma | q | r
+    double *partials;   // device: kObjBlocks doubles (objective and Lagrangian sums)
+    double *cpart;      // device: n (n+m+1) kCoefBlocks doubles (coefficient-gradient sums)
+    ocp::dev::KP kp;
+};
+
+static inline int hip_fail(const char *what, hipError_t e)
+{
+    return ocp::fail(OCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static inline int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(what, e);
+    return OCP_OK;
+}
+
+static inline int check_handle(const ocp_problem *p, const char *what)
+{
+    if (!p) return ocp::fail(OCP_ERR_ARG, std::string(what) + ": problem handle is NULL");
+    return OCP_OK;
+}
+
+static inline unsigned blocks_for(int64_t count, int per_block)
+{
+    return (unsigned)((count + per_block - 1) / per_block);
+}

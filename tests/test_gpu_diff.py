@@ -1,0 +1,228 @@
+"""GPU parity of the Lagrangian derivatives (L, grad_z L, H v, J v, dL/dtheta)
+against the CPU oracle, and of the autograd wrapper against finite differences
+(torch.autograd.gradcheck / gradgradcheck, and central differences at step
+1e-6 on the 2e5-interval differentiation workload)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import check_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SHAPES = [(1000, 4, 2), (777, 5, 3), (1, 1, 0), (1, 1, 1), (2, 2, 1), (3, 3, 0), (255, 2, 0),
+          (257, 16, 8), (513, 32, 32), (300, 9, 4)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ocp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_03932_amd as ocp
+    ocp.lib()
+    return ocp
+
+
+def _dev_inputs(inst, seed=0):
+    dev = torch.device("cuda", 0)
+    v = np.random.default_rng(seed).normal(size=len(inst.z))
+    return (dev, torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev),
+            v, torch.from_numpy(v).to(dev))
+
+
+def _check_all(ocp, inst, sigma, tag):
+    dev, z, y, v, vt = _dev_inputs(inst)
+    prob = ocp.Problem.from_instance(inst, dev)
+    L = prob.lagrangian(z, y, sigma).cpu().numpy()
+    g = prob.lag_grad(z, y, sigma).cpu().numpy()
+    hv = prob.hvp(z, y, vt, sigma).cpu().numpy()
+    jv = prob.jvp(z, vt).cpu().numpy()
+    gA, gB, gg = (t.cpu().numpy() for t in prob.coef_grad(z, y))
+    Lo, Lm = oracle.lagrangian(inst, sigma=sigma)
+    check_close(L, np.array([Lo]), np.array([Lm]), what=f"L {tag}")
+    want, mu = oracle.lag_grad(inst, sigma=sigma)
+    check_close(g, want, mu, what=f"grad_z L {tag}")
+    want, mu = oracle.hvp(inst, v, sigma=sigma)
+    check_close(hv, want, mu, what=f"H v {tag}")
+    want, mu = oracle.jvp(inst, v)
+    check_close(jv, want, mu, what=f"J v {tag}")
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_grad(inst)
+    check_close(gA, oA, mA, what=f"dL/dA {tag}")
+    check_close(gB, oB, mB, what=f"dL/dB {tag}")
+    check_close(gg, og, mg, what=f"dL/dgamma {tag}")
+    prob.close()
+
+
+@pytest.mark.parametrize("N,n,m", SHAPES)
+def test_derivatives_match_oracle(ocp, N, n, m):
+    _say(f"[diff] N={N} n={n} m={m}")
+    _check_all(ocp, synth.make_instance(N, n, m, seed=2), 1.3, f"{N},{n},{m}")
+
+
+def test_differentiation_workload_full_arrays(ocp):
+    N, n, m = synth.DIFF
+    _say(f"[diff] workload N={N} n={n} m={m}")
+    _check_all(ocp, synth.make_instance(N, n, m, seed=0), 1.0, "2e5")
+
+
+def test_deterministic(ocp):
+    inst = synth.make_instance(50_000, 8, 4, seed=3)
+    dev, z, y, v, vt = _dev_inputs(inst)
+    prob = ocp.Problem.from_instance(inst, dev)
+    for fn in (lambda: prob.lagrangian(z, y, 1.0), lambda: prob.lag_grad(z, y, 1.0),
+               lambda: prob.hvp(z, y, vt, 1.0), lambda: prob.jvp(z, vt),
+               lambda: torch.cat([t.ravel() for t in prob.coef_grad(z, y)])):
+        a, b = fn(), fn()
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+    prob.close()
+
+
+def test_set_coefficients(ocp):
+    """Coefficients pushed from device tensors replace the ones given at creation."""
+    inst = synth.make_instance(400, 5, 2, seed=4)
+    other = synth.make_instance(400, 5, 2, seed=5)
+    dev, z, y, v, vt = _dev_inputs(inst)
+    prob = ocp.Problem.from_instance(other, dev)
+    prob.set_coefficients(*(torch.from_numpy(a).to(dev) for a in (inst.A, inst.B, inst.gamma)))
+    got = prob.lag_grad(z, y, 1.0).cpu().numpy()
+    want, mu = oracle.lag_grad(inst)
+    check_close(got, want, mu, what="after set_coefficients")
+    c = prob.cons(z).cpu().numpy()
+    want, mu = oracle.cons(inst)
+    check_close(c, want, mu, what="cons after set_coefficients")
+    prob.close()
+
+
+def _leaf_inputs(inst, dev, coef_grad=True):
+    t = lambda a, rg=True: torch.from_numpy(np.array(a)).to(dev).requires_grad_(rg)
+    return (t(inst.z), t(inst.y), t(inst.A, coef_grad), t(inst.B, coef_grad), t(inst.gamma, coef_grad))
+
+
+def test_autograd_backward_matches_oracle(ocp):
+    from paper_2510_03932_amd.autograd import lagrangian
+    inst = synth.make_instance(2000, 6, 3, seed=6)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    L = lagrangian(prob, z, y, A, B, g, 0.9)
+    L.backward()
+    want, mu = oracle.lag_grad(inst, sigma=0.9)
+    check_close(z.grad.cpu().numpy(), want, mu, what="z.grad")
+    want, mu = oracle.cons(inst)
+    check_close(y.grad.cpu().numpy(), want, mu, what="y.grad")
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_grad(inst)
+    check_close(A.grad.cpu().numpy(), oA, mA, what="A.grad")
+    check_close(B.grad.cpu().numpy(), oB, mB, what="B.grad")
+    check_close(g.grad.cpu().numpy(), og, mg, what="gamma.grad")
+    Lo, Lm = oracle.lagrangian(inst, sigma=0.9)
+    assert abs(L.item() - Lo) <= 1e-12 * Lm
+    prob.close()
+
+
+@pytest.mark.parametrize("N,n,m", [(4, 3, 2), (3, 1, 1), (5, 2, 0)])
+def test_autograd_gradcheck(ocp, N, n, m):
+    from paper_2510_03932_amd.autograd import constraints, lagrangian, lagrangian_grad
+    inst = synth.make_instance(N, n, m, seed=7)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    if m == 0:  # an empty B takes no part in a gradient check
+        B = B.detach()
+        f = lambda z, y, A, g: lagrangian(prob, z, y, A, B, g, 1.2)
+        assert torch.autograd.gradcheck(f, (z, y, A, g), eps=1e-6, atol=1e-6, rtol=1e-5)
+    else:
+        f = lambda z, y, A, B, g: lagrangian(prob, z, y, A, B, g, 1.2)
+        assert torch.autograd.gradcheck(f, (z, y, A, B, g), eps=1e-6, atol=1e-6, rtol=1e-5)
+    z, y, A, B, g = _leaf_inputs(inst, dev, coef_grad=False)
+    f2 = lambda z, y: lagrangian(prob, z, y, A, B, g, 1.2)
+    assert torch.autograd.gradgradcheck(f2, (z, y), eps=1e-6, atol=1e-6, rtol=1e-5)
+    fg = lambda z, y: lagrangian_grad(prob, z, y, A, B, g, 1.2)
+    assert torch.autograd.gradcheck(fg, (z, y), eps=1e-6, atol=1e-6, rtol=1e-5)
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    if m == 0:
+        B = B.detach()
+        fc = lambda z, A, g: constraints(prob, z, A, B, g)
+        assert torch.autograd.gradcheck(fc, (z, A, g), eps=1e-6, atol=1e-6, rtol=1e-5)
+    else:
+        fc = lambda z, A, B, g: constraints(prob, z, A, B, g)
+        assert torch.autograd.gradcheck(fc, (z, A, B, g), eps=1e-6, atol=1e-6, rtol=1e-5)
+    prob.close()
+
+
+def test_second_order_in_coefficients_raises(ocp):
+    from paper_2510_03932_amd.autograd import lagrangian
+    inst = synth.make_instance(10, 3, 1, seed=8)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    L = lagrangian(prob, z, y, A, B, g)
+    (gz,) = torch.autograd.grad(L, z, create_graph=True)
+    with pytest.raises(NotImplementedError):
+        gz.sum().backward()
+    prob.close()
+
+
+def test_differentiation_workload_central_differences(ocp):
+    """On the 2e5-interval workload, with the GPU's own Lagrangian:
+    - central differences at step 1e-6 along sampled entries of z against
+      grad_z L (a local perturbation: the unchanged terms round identically
+      in both evaluations, so the difference resolves the derivative);
+    - central differences of grad_z L along v (step 1e-6) against H v;
+    - the coefficients: L is affine in (A, B, gamma), so a central difference
+      is exact at any step up to the rounding of L, which is eps * mu_L with
+      mu_L the sum of |terms| (2e6 here against |L| = 8.6).  Every coefficient
+      perturbs every term, so the step is 1.0 to keep that rounding far below
+      the derivative."""
+    N, n, m = synth.DIFF
+    inst = synth.make_instance(N, n, m, seed=0)
+    dev, z, y, v, vt = _dev_inputs(inst, seed=9)
+    prob = ocp.Problem.from_instance(inst, dev)
+    _, muL = oracle.lagrangian(inst)
+    eps = np.finfo(float).eps
+    step = 1e-6
+    g = prob.lag_grad(z, y, 1.0)
+    L0 = abs(prob.lagrangian(z, y, 1.0).item())
+    for e in np.random.default_rng(10).choice(len(inst.z), 24, replace=False).tolist() + [0, N, len(inst.z) - 1]:
+        zp, zm = z.clone(), z.clone()
+        zp[e] += step
+        zm[e] -= step
+        fd = (prob.lagrangian(zp, y, 1.0).item() - prob.lagrangian(zm, y, 1.0).item()) / (2 * step)
+        assert abs(fd - g[e].item()) <= 64 * eps * L0 / step + 1e-6 * abs(g[e].item()), e
+    hv = prob.hvp(z, y, vt, 1.0)
+    fd = (prob.lag_grad(z + step * vt, y, 1.0) - prob.lag_grad(z - step * vt, y, 1.0)) / (2 * step)
+    # the entries of grad_z L are O(1) while H v is O(h): the difference's
+    # rounding, eps * mu(grad_z L) / step per entry, bounds the comparison
+    _, mug = oracle.lag_grad(inst)
+    bound = 16 * eps * torch.from_numpy(mug).to(dev) / step + 1e-6 * hv.abs().max()
+    assert bool(((fd - hv).abs() <= bound).all())
+    gA, gB, gg = (t.cpu().numpy() for t in prob.coef_grad(z, y))
+    A0, B0, g0 = (torch.from_numpy(a).to(dev) for a in (inst.A, inst.B, inst.gamma))
+    cstep = 1.0
+    bound = 64 * eps * muL / cstep
+    for name, base, grad in (("A", A0, gA), ("B", B0, gB), ("gamma", g0, gg)):
+        flat = base.reshape(-1)
+        for idx in range(flat.numel()):
+            vals = []
+            for sgn in (1, -1):
+                pert = flat.clone()
+                pert[idx] += sgn * cstep
+                args = {"A": A0, "B": B0, "gamma": g0}
+                args[name] = pert.reshape(base.shape)
+                prob.set_coefficients(args["A"], args["B"], args["gamma"])
+                vals.append(prob.lagrangian(z, y, 1.0).item())
+            fd = (vals[0] - vals[1]) / (2 * cstep)
+            assert abs(fd - grad.reshape(-1)[idx]) <= bound, (name, idx, fd, grad.reshape(-1)[idx])
+    prob.set_coefficients(A0, B0, g0)
+    prob.close()
