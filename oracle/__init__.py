@@ -63,6 +63,16 @@ class Oracle:
                                   i64, i64, ptr, ptr]
             L.orc_jvp.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, i64, i64, ptr, ptr]
             L.orc_coef_grad.argtypes = [i64, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, ptr, ptr]
+            L.orc_sizes_ex.argtypes = [i64, i32, i32, i32, i32, ptr]
+            L.orc_obj_ex.argtypes = [i64, i32, i32, i32, i32, ptr, ptr, ptr, ptr]
+            L.orc_grad_ex.argtypes = [i64, i32, i32, i32, i32, ptr, ptr, ptr, ptr, ptr]
+            L.orc_cons_ex.argtypes = [i64, i32, i32, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr]
+            L.orc_pattern_ex.argtypes = [i64, i32, i32, i32, i32, ptr, ptr, ptr, ptr]
+            L.orc_jac_ex.argtypes = [i64, i32, i32, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr]
+            L.orc_hess_ex.argtypes = [i64, i32, i32, i32, i32, ptr, ptr, ptr, ptr, ptr, ptr, dbl,
+                                      ptr, ptr]
+            L.orc_kkt_generic.argtypes = [i64, i64, i64, i64, ptr, ptr, ptr, ptr, ptr, ptr, ptr,
+                                          ptr, ptr]
             L.orc_set_threads.argtypes = [i32]
             L.orc_set_threads.restype = None
             L.orc_get_threads.restype = i32
@@ -224,6 +234,71 @@ class Oracle:
                                     _p(mg)), "coef_grad")
         return (gA, gB, gg), (mA, mB, mg)
 
+    # ---- schemes (0 trapezoidal, 1 forward Euler) and boundary rows --------
+    def sizes_ex(self, N, n, m, scheme=0, bnd=0) -> dict:
+        out = np.zeros(10, np.int64)
+        _check(self.L.orc_sizes_ex(N, n, m, scheme, bnd, _p(out)), "sizes_ex")
+        keys = ["nvar", "ncon", "nnzj", "nnzh", "dim", "npair", "T", "S", "NU", "nb"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def obj_ex(self, inst, scheme=0, bnd=0):
+        out = np.zeros(2)
+        _check(self.L.orc_obj_ex(inst.N, inst.n, inst.m, scheme, bnd, _p(_d(inst.q)), _p(_d(inst.r)),
+                                 _p(_d(inst.z)), _p(out)), "obj_ex")
+        return float(out[0]), float(out[1])
+
+    def grad_ex(self, inst, scheme=0, bnd=0):
+        s = self.sizes_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        g, mu = np.empty(s["nvar"]), np.empty(s["nvar"])
+        _check(self.L.orc_grad_ex(inst.N, inst.n, inst.m, scheme, bnd, _p(_d(inst.q)),
+                                  _p(_d(inst.r)), _p(_d(inst.z)), _p(g), _p(mu)), "grad_ex")
+        return g, mu
+
+    def cons_ex(self, inst, scheme=0, bnd=0):
+        s = self.sizes_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        c, mu = np.empty(s["ncon"]), np.empty(s["ncon"])
+        _check(self.L.orc_cons_ex(inst.N, inst.n, inst.m, scheme, bnd, _p(_d(inst.A)), _p(_d(inst.B)),
+                                  _p(_d(inst.gamma)), _p(_d(inst.z)), _p(c), _p(mu)), "cons_ex")
+        return c, mu
+
+    def jac_ex(self, inst, scheme=0, bnd=0):
+        s = self.sizes_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        v, mu = np.empty(s["nnzj"]), np.empty(s["nnzj"])
+        _check(self.L.orc_jac_ex(inst.N, inst.n, inst.m, scheme, bnd, _p(_d(inst.A)), _p(_d(inst.B)),
+                                 _p(_d(inst.gamma)), _p(_d(inst.z)), _p(v), _p(mu)), "jac_ex")
+        return v, mu
+
+    def hess_ex(self, inst, scheme=0, bnd=0, sigma=None, y=None):
+        s = self.sizes_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        v, mu = np.empty(s["nnzh"]), np.empty(s["nnzh"])
+        sigma = inst.sigma if sigma is None else sigma
+        y = inst.y if y is None else y
+        _check(self.L.orc_hess_ex(inst.N, inst.n, inst.m, scheme, bnd, _p(_d(inst.A)),
+                                  _p(_d(inst.gamma)), _p(_d(inst.q)), _p(_d(inst.r)), _p(_d(inst.z)),
+                                  _p(_d(y)), float(sigma), _p(v), _p(mu)), "hess_ex")
+        return v, mu
+
+    def pattern_ex(self, N, n, m, scheme=0, bnd=0):
+        s = self.sizes_ex(N, n, m, scheme, bnd)
+        jr, jc = np.empty(s["nnzj"], np.int32), np.empty(s["nnzj"], np.int32)
+        hr, hc = np.empty(s["nnzh"], np.int32), np.empty(s["nnzh"], np.int32)
+        _check(self.L.orc_pattern_ex(N, n, m, scheme, bnd, _p(jr), _p(jc), _p(hr), _p(hc)),
+               "pattern_ex")
+        return jr, jc, hr, hc
+
+    def kkt_ex(self, N, n, m, scheme=0, bnd=0):
+        s = self.sizes_ex(N, n, m, scheme, bnd)
+        jr, jc, hr, hc = self.pattern_ex(N, n, m, scheme, bnd)
+        rowptr = np.empty(s["dim"] + 1, np.int32)
+        colind = np.empty(s["nnzh"] + s["nnzj"] + s["dim"], np.int32)
+        perm_j = np.empty(s["nnzj"], np.int32)
+        perm_h = np.empty(s["nnzh"], np.int32)
+        nnzk = np.zeros(1, np.int64)
+        _check(self.L.orc_kkt_generic(s["nvar"], s["ncon"], s["nnzj"], s["nnzh"], _p(jr), _p(jc),
+                                      _p(hr), _p(hc), _p(rowptr), _p(colind), _p(perm_j),
+                                      _p(perm_h), _p(nnzk)), "kkt_generic")
+        return rowptr, colind[: int(nnzk[0])].copy(), perm_j, perm_h
+
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
@@ -256,6 +331,14 @@ lag_grad = DEFAULT.lag_grad
 hvp = DEFAULT.hvp
 jvp = DEFAULT.jvp
 coef_grad = DEFAULT.coef_grad
+sizes_ex = DEFAULT.sizes_ex
+obj_ex = DEFAULT.obj_ex
+grad_ex = DEFAULT.grad_ex
+cons_ex = DEFAULT.cons_ex
+jac_ex = DEFAULT.jac_ex
+hess_ex = DEFAULT.hess_ex
+pattern_ex = DEFAULT.pattern_ex
+kkt_ex = DEFAULT.kkt_ex
 
 
 def build_variant(src_text: str, out_path: str) -> "Oracle":

@@ -89,3 +89,59 @@ def as_lists(inst):
     """Coefficients of a synth.Instance as nested Python lists."""
     return ([list(map(float, row)) for row in inst.A], [list(map(float, row)) for row in inst.B],
             list(map(float, inst.gamma)), list(map(float, inst.q)), list(map(float, inst.r)))
+
+
+# ---- forward Euler (paper Sec. 3) and boundary rows --------------------------
+
+def unpack_ex(z, N, n, m, scheme):
+    """Per-node states (N+1 nodes) and controls (N+1 nodes trapezoidal, N Euler)."""
+    NU = N + 1 if scheme == 0 else N
+    xs = [[z[j * (N + 1) + k] for j in range(n)] for k in range(N + 1)]
+    off = n * (N + 1)
+    us = [[z[off + l * NU + k] for l in range(m)] for k in range(NU)]
+    return xs, us
+
+
+def objective_ex(z, N, n, m, q, r, scheme, dt=None):
+    """Trapezoidal cost (scheme 0) or the forward-Euler Bolza-type sum
+    sum_{i<N} h f0(X_i, U_i) (scheme 1)."""
+    if scheme == 0:
+        return objective(z, N, n, m, q, r, dt)
+    dt = 1.0 / N if dt is None else dt
+    xs, us = unpack_ex(z, N, n, m, 1)
+    acc = 0
+    for k in range(N):
+        acc = acc + dt * running_cost(xs[k], us[k], q, r)
+    return acc
+
+
+def constraints_ex(z, N, n, m, A, B, gamma, scheme, bnd, sin=math.sin, dt=None):
+    """Defect rows (one generator per state component; trapezoidal, or forward
+    Euler X_{i+1} - X_i - h f(X_i, U_i)), then the boundary rows: the initial
+    state X_0 (bnd >= 1) and the final state X_N (bnd == 2), component by
+    component, as the paper's x(0) == x0 generator with lcon = ucon."""
+    dt_ = 1.0 / N if dt is None else dt
+    if scheme == 0:
+        c = constraints(z, N, n, m, A, B, gamma, sin, dt)
+    else:
+        xs, us = unpack_ex(z, N, n, m, 1)
+        c = []
+        for i in range(n):
+            for k in range(N):
+                f = rhs(xs[k], us[k], A, B, gamma, sin)
+                c.append(xs[k + 1][i] - xs[k][i] - dt_ * f[i])
+    xs, _ = unpack_ex(z, N, n, m, scheme)
+    if bnd >= 1:
+        c.extend(xs[0][i] for i in range(n))
+    if bnd == 2:
+        c.extend(xs[N][i] for i in range(n))
+    return c
+
+
+def lagrangian_ex(z, y, sigma, N, n, m, A, B, gamma, q, r, scheme, bnd, sin=math.sin, dt=None):
+    f = objective_ex(z, N, n, m, q, r, scheme, dt)
+    c = constraints_ex(z, N, n, m, A, B, gamma, scheme, bnd, sin, dt)
+    acc = sigma * f
+    for a, b in zip(y, c):
+        acc = acc + a * b
+    return acc

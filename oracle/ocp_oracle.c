@@ -796,3 +796,385 @@ int orc_coef_grad(int64_t N, int n, int m, const double *z, const double *y,
     free(part);
     return ORC_OK;
 }
+
+/* ---- schemes and boundary rows (the _ex family) --------------------------- */
+/*
+ * scheme 0: trapezoidal (everything above);
+ * scheme 1: forward Euler (paper Sec. 3): unknowns X_0..X_N and U_0..U_{N-1}
+ *   (controls on N nodes), defects c_ik = X_{i,k+1} - X_ik - h F_i(k), and the
+ *   Bolza-type cost sum_{k<N} h f0(X_k, U_k) (node N carries no cost).
+ * bnd 0: no boundary rows; 1: initial rows X_i0 (i < n); 2: initial and final
+ *   rows X_i0, X_iN.  As in the paper's generated code for x(0) == x0 (a
+ *   constraint generator over the components with lcon = ucon), the row's
+ *   value is the state itself; the target goes into the solver's bounds.
+ * Layout: vx(j,k) = j (N+1) + k; vu(l,k) = n (N+1) + l NU + k with NU = N+1
+ *   (trapezoidal) or N (Euler); defect rows i N + k, then the boundary rows.
+ *   Jacobian COO: the defect entries slot-major as before with T slots per
+ *   row (T = 2n+2m trapezoidal, n+1+m Euler, slots in ascending column
+ *   order), then one entry per boundary row.  Hessian COO: state and pair
+ *   slots s (N+1) + k as before, then control slots (n+npair)(N+1) + l NU + k.
+ */
+
+typedef struct {
+    int64_t N, NU, nvar, ncon, ndef, nb, nnzj_def, nnzj, nnzh, dim;
+    int n, m, npair, T, S, scheme, bnd;
+} exdims_t;
+
+static int ex_dims(int64_t N, int n, int m, int scheme, int bnd, exdims_t *d)
+{
+    if (bad_sizes(N, n, m) || scheme < 0 || scheme > 1 || bnd < 0 || bnd > 2) return ORC_BAD;
+    d->N = N; d->n = n; d->m = m; d->scheme = scheme; d->bnd = bnd;
+    d->NU = scheme == 0 ? N + 1 : N;
+    d->npair = npair_of(n);
+    d->T = scheme == 0 ? 2 * n + 2 * m : n + 1 + m;
+    d->S = n + d->npair + m;
+    d->nvar = (int64_t)n * (N + 1) + (int64_t)m * d->NU;
+    d->ndef = (int64_t)n * N;
+    d->nb = (int64_t)bnd * n;
+    d->ncon = d->ndef + d->nb;
+    d->nnzj_def = d->ndef * d->T;
+    d->nnzj = d->nnzj_def + d->nb;
+    d->nnzh = (int64_t)(n + d->npair) * (N + 1) + (int64_t)m * d->NU;
+    d->dim = d->nvar + d->ncon;
+    return ORC_OK;
+}
+
+/* out = {nvar, ncon, nnzj, nnzh, dim, npair, T, S, NU, nb} */
+int orc_sizes_ex(int64_t N, int n, int m, int scheme, int bnd, int64_t *out)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d) || !out) return ORC_BAD;
+    out[0] = d.nvar; out[1] = d.ncon; out[2] = d.nnzj; out[3] = d.nnzh; out[4] = d.dim;
+    out[5] = d.npair; out[6] = d.T; out[7] = d.S; out[8] = d.NU; out[9] = d.nb;
+    return ORC_OK;
+}
+
+/* Cost weight of node k under the scheme. */
+static double weight_ex(const exdims_t *d, int64_t k)
+{
+    double h = 1.0 / (double)d->N;
+    if (d->scheme == 0) return (k == 0 || k == d->N) ? 0.5 * h : h;
+    return k < d->N ? h : 0.0;
+}
+
+#define XV(z, d, j, k) ((z)[(int64_t)(j) * ((d)->N + 1) + (k)])
+#define UV(z, d, l, k) ((z)[(int64_t)(d)->n * ((d)->N + 1) + (int64_t)(l) * (d)->NU + (k)])
+
+/* F_i at node k with controls at node k (k < NU), and |F|. */
+static void dyn_ex(const exdims_t *d, const double *A, const double *B, const double *gam,
+                   const double *z, int64_t k, double *F, double *Fa)
+{
+    int n = d->n, m = d->m;
+    for (int i = 0; i < n; i++) {
+        double s = 0.0, sa = 0.0, t;
+        for (int j = 0; j < n; j++) { t = A[i * n + j] * sin(XV(z, d, j, k)); s += t; sa += fabs(t); }
+        for (int l = 0; l < m; l++) { t = B[i * m + l] * UV(z, d, l, k); s += t; sa += fabs(t); }
+        int p = (i + 1) % n;
+        t = gam[i] * XV(z, d, i, k) * XV(z, d, p, k);
+        s += t; sa += fabs(t);
+        F[i] = s;
+        if (Fa) Fa[i] = sa;
+    }
+}
+
+/* out = {f, mu}: sum over nodes of w_k (sum q X^2 + sum r U^2), U only where
+ * it exists (k < NU); compensated as orc_obj. */
+int orc_obj_ex(int64_t N, int n, int m, int scheme, int bnd, const double *q, const double *r,
+               const double *z, double *out)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !out) return ORC_BAD;
+    acc_t tot = {0.0, 0.0};
+    double mu = 0.0;
+    for (int64_t k = 0; k <= N; k++) {
+        double s = 0.0, sa = 0.0;
+        for (int j = 0; j < n; j++) { double x = XV(z, &d, j, k); s += q[j] * x * x; sa += fabs(q[j] * x * x); }
+        if (k < d.NU)
+            for (int l = 0; l < m; l++) { double u = UV(z, &d, l, k); s += r[l] * u * u; sa += fabs(r[l] * u * u); }
+        double w = weight_ex(&d, k);
+        acc_add(&tot, w * s);
+        mu += w * sa;
+    }
+    out[0] = tot.s + tot.c;
+    out[1] = mu;
+    return ORC_OK;
+}
+
+/* Full gradient of f (nvar entries, layout of z). */
+int orc_grad_ex(int64_t N, int n, int m, int scheme, int bnd, const double *q, const double *r,
+                const double *z, double *g, double *mu)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !g) return ORC_BAD;
+    for (int64_t k = 0; k <= N; k++) {
+        double w = weight_ex(&d, k);
+        for (int j = 0; j < n; j++) {
+            int64_t e = (int64_t)j * (N + 1) + k;
+            g[e] = 2.0 * w * q[j] * z[e];
+            if (mu) mu[e] = fabs(g[e]);
+        }
+        if (k < d.NU)
+            for (int l = 0; l < m; l++) {
+                int64_t e = (int64_t)n * (N + 1) + (int64_t)l * d.NU + k;
+                g[e] = 2.0 * w * r[l] * z[e];
+                if (mu) mu[e] = fabs(g[e]);
+            }
+    }
+    return ORC_OK;
+}
+
+/* All constraint rows (ncon): defects, then boundary rows. */
+int orc_cons_ex(int64_t N, int n, int m, int scheme, int bnd, const double *A, const double *B,
+                const double *gam, const double *z, double *c, double *mu)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !c) return ORC_BAD;
+    double h = 1.0 / (double)N, hh = 0.5 * h;
+    double *F0 = (double *)malloc(sizeof(double) * 4 * n);
+    double *F1 = F0 + n, *A0 = F0 + 2 * n, *A1 = F0 + 3 * n;
+    for (int64_t k = 0; k < N; k++) {
+        dyn_ex(&d, A, B, gam, z, k, F0, A0);
+        if (scheme == 0) dyn_ex(&d, A, B, gam, z, k + 1, F1, A1);
+        for (int i = 0; i < n; i++) {
+            double x0 = XV(z, &d, i, k), x1 = XV(z, &d, i, k + 1);
+            int64_t r0 = (int64_t)i * N + k;
+            if (scheme == 0) {
+                c[r0] = (x1 - x0) - hh * (F0[i] + F1[i]);
+                if (mu) mu[r0] = fabs(x1) + fabs(x0) + hh * (A0[i] + A1[i]);
+            } else {
+                c[r0] = (x1 - x0) - h * F0[i];
+                if (mu) mu[r0] = fabs(x1) + fabs(x0) + h * A0[i];
+            }
+        }
+    }
+    free(F0);
+    for (int64_t b = 0; b < d.nb; b++) {
+        int i = (int)(b % n);
+        int64_t node = b < n ? 0 : N;
+        c[d.ndef + b] = XV(z, &d, i, node);
+        if (mu) mu[d.ndef + b] = fabs(c[d.ndef + b]);
+    }
+    return ORC_OK;
+}
+
+/* Column (variable index) of Jacobian slot t of defect row (i, k). */
+static int64_t jac_col_ex(const exdims_t *d, int i, int t, int64_t k)
+{
+    int n = d->n;
+    int64_t NX = (int64_t)n * (d->N + 1);
+    if (d->scheme == 0) {
+        if (t < 2 * n) return (int64_t)(t / 2) * (d->N + 1) + k + (t % 2);
+        return NX + (int64_t)((t - 2 * n) / 2) * d->NU + k + ((t - 2 * n) % 2);
+    }
+    if (t <= i) return (int64_t)t * (d->N + 1) + k;               /* X_t at k */
+    if (t == i + 1) return (int64_t)i * (d->N + 1) + k + 1;      /* X_i at k+1 */
+    if (t <= n) return (int64_t)(t - 1) * (d->N + 1) + k;        /* X_{t-1} at k */
+    return NX + (int64_t)(t - n - 1) * d->NU + k;                /* U_{t-n-1} at k */
+}
+
+int orc_pattern_ex(int64_t N, int n, int m, int scheme, int bnd, int32_t *jrow, int32_t *jcol,
+                   int32_t *hrow, int32_t *hcol)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d)) return ORC_BAD;
+    if (d.dim + 1 > INT32_MAX || d.nnzj > INT32_MAX || d.nnzh > INT32_MAX) return ORC_BAD;
+    int64_t NX = (int64_t)n * (N + 1);
+    if (jrow && jcol) {
+        for (int i = 0; i < n; i++)
+            for (int t = 0; t < d.T; t++)
+                for (int64_t k = 0; k < N; k++) {
+                    int64_t e = ((int64_t)i * d.T + t) * N + k;
+                    jrow[e] = (int32_t)((int64_t)i * N + k);
+                    jcol[e] = (int32_t)jac_col_ex(&d, i, t, k);
+                }
+        for (int64_t b = 0; b < d.nb; b++) {
+            int64_t e = d.nnzj_def + b;
+            jrow[e] = (int32_t)(d.ndef + b);
+            jcol[e] = (int32_t)((int64_t)(b % n) * (N + 1) + (b < n ? 0 : N));
+        }
+    }
+    if (hrow && hcol) {
+        for (int64_t k = 0; k <= N; k++) {
+            for (int j = 0; j < n; j++) {
+                int64_t e = (int64_t)j * (N + 1) + k;
+                hrow[e] = hcol[e] = (int32_t)e;
+            }
+            for (int i = 0; i < d.npair; i++) {
+                int a = i, b = (i + 1) % n;
+                int hi = a > b ? a : b, lo = a < b ? a : b;
+                int64_t e = (int64_t)(n + i) * (N + 1) + k;
+                hrow[e] = (int32_t)((int64_t)hi * (N + 1) + k);
+                hcol[e] = (int32_t)((int64_t)lo * (N + 1) + k);
+            }
+        }
+        for (int l = 0; l < m; l++)
+            for (int64_t k = 0; k < d.NU; k++) {
+                int64_t e = (int64_t)(n + d.npair) * (N + 1) + (int64_t)l * d.NU + k;
+                hrow[e] = hcol[e] = (int32_t)(NX + (int64_t)l * d.NU + k);
+            }
+    }
+    return ORC_OK;
+}
+
+/* Jacobian values: defect entries (as orc_jac for the trapezoidal scheme; for
+ * Euler the slots of the o4-style table X_t at k: -delta - h G, X_i at k+1:
+ * +1, U_l at k: -h B), then 1.0 for every boundary row. */
+int orc_jac_ex(int64_t N, int n, int m, int scheme, int bnd, const double *A, const double *B,
+               const double *gam, const double *z, double *out, double *mu)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !out) return ORC_BAD;
+    double h = 1.0 / (double)N, hh = 0.5 * h;
+    const double *X = z;
+    for (int i = 0; i < n; i++)
+        for (int t = 0; t < d.T; t++)
+            for (int64_t k = 0; k < N; k++) {
+                int64_t e = ((int64_t)i * d.T + t) * N + k;
+                double v, va;
+                if (scheme == 0) {
+                    if (t < 2 * n) {
+                        int j = t / 2, right = t % 2;
+                        double dd = (i == j) ? 1.0 : 0.0, g, ga;
+                        dF_dx(N, n, A, gam, X, i, j, k + right, &g, &ga);
+                        v = (right ? dd : -dd) - hh * g;
+                        va = dd + hh * ga;
+                    } else {
+                        v = -hh * B[i * m + (t - 2 * n) / 2];
+                        va = fabs(v);
+                    }
+                } else {
+                    if (t == i + 1) {
+                        v = 1.0; va = 1.0;
+                    } else if (t <= n) {
+                        int j = t <= i ? t : t - 1;
+                        double dd = (i == j) ? 1.0 : 0.0, g, ga;
+                        dF_dx(N, n, A, gam, X, i, j, k, &g, &ga);
+                        v = -dd - h * g;
+                        va = dd + h * ga;
+                    } else {
+                        v = -h * B[i * m + (t - n - 1)];
+                        va = fabs(v);
+                    }
+                }
+                out[e] = v;
+                if (mu) mu[e] = va;
+            }
+    for (int64_t b = 0; b < d.nb; b++) {
+        out[d.nnzj_def + b] = 1.0;
+        if (mu) mu[d.nnzj_def + b] = 1.0;
+    }
+    return ORC_OK;
+}
+
+/* Hessian of L = sigma f + y^T c (boundary rows are linear and add nothing).
+ * Node multiplier and factor: trapezoidal yt = y_{k-1} + y_k, factor hh;
+ * Euler yt = y_k (k < N), factor h.  Layout as orc_pattern_ex. */
+int orc_hess_ex(int64_t N, int n, int m, int scheme, int bnd, const double *A, const double *gam,
+                const double *q, const double *r, const double *z, const double *y, double sigma,
+                double *out, double *mu)
+{
+    exdims_t d;
+    if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !y || !out) return ORC_BAD;
+    double h = 1.0 / (double)N;
+    double fac = scheme == 0 ? 0.5 * h : h;
+    double *yt = (double *)malloc(sizeof(double) * 2 * n), *ya = yt + n;
+    for (int64_t k = 0; k <= N; k++) {
+        double w = weight_ex(&d, k);
+        for (int i = 0; i < n; i++) {
+            double a = 0.0, aa = 0.0;
+            if (scheme == 0 && k >= 1) { a += y[(int64_t)i * N + k - 1]; aa += fabs(y[(int64_t)i * N + k - 1]); }
+            if (k <= N - 1) { a += y[(int64_t)i * N + k]; aa += fabs(y[(int64_t)i * N + k]); }
+            yt[i] = a; ya[i] = aa;
+        }
+        for (int j = 0; j < n; j++) {
+            double sx = sin(XV(z, &d, j, k)), s = 0.0, sa = 0.0;
+            for (int i = 0; i < n; i++) { s += yt[i] * A[i * n + j]; sa += ya[i] * fabs(A[i * n + j]); }
+            double v = 2.0 * sigma * w * q[j] + fac * sx * s;
+            double va = fabs(2.0 * sigma * w * q[j]) + fac * fabs(sx) * sa;
+            if (n == 1) { v += -2.0 * fac * yt[0] * gam[0]; va += 2.0 * fac * ya[0] * fabs(gam[0]); }
+            int64_t e = (int64_t)j * (N + 1) + k;
+            out[e] = v;
+            if (mu) mu[e] = va;
+        }
+        if (n >= 3) {
+            for (int i = 0; i < n; i++) {
+                int64_t e = (int64_t)(n + i) * (N + 1) + k;
+                out[e] = -fac * yt[i] * gam[i];
+                if (mu) mu[e] = fac * ya[i] * fabs(gam[i]);
+            }
+        } else if (n == 2) {
+            int64_t e = (int64_t)n * (N + 1) + k;
+            out[e] = -fac * (yt[0] * gam[0] + yt[1] * gam[1]);
+            if (mu) mu[e] = fac * (ya[0] * fabs(gam[0]) + ya[1] * fabs(gam[1]));
+        }
+        if (k < d.NU)
+            for (int l = 0; l < m; l++) {
+                int64_t e = (int64_t)(n + d.npair) * (N + 1) + (int64_t)l * d.NU + k;
+                out[e] = 2.0 * sigma * w * r[l];
+                if (mu) mu[e] = fabs(out[e]);
+            }
+    }
+    free(yt);
+    return ORC_OK;
+}
+
+/* Generic KKT build from explicit sizes and COO patterns (see orc_kkt). */
+int orc_kkt_generic(int64_t nvar, int64_t ncon, int64_t nnzj, int64_t nnzh,
+                    const int32_t *jrow, const int32_t *jcol, const int32_t *hrow,
+                    const int32_t *hcol, int32_t *rowptr, int32_t *colind, int32_t *perm_j,
+                    int32_t *perm_h, int64_t *nnzk)
+{
+    int64_t dim = nvar + ncon;
+    int64_t ntrip = nnzh + nnzj + dim;
+    if (dim + 1 > INT32_MAX || ntrip > INT32_MAX) return ORC_BAD;
+    int64_t *cnt = (int64_t *)calloc((size_t)dim + 1, sizeof(int64_t));
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)dim);
+    ent_t *ent = (ent_t *)malloc(sizeof(ent_t) * (size_t)ntrip);
+    if (!cnt || !pos || !ent) { free(cnt); free(pos); free(ent); return ORC_BAD; }
+    int rc = ORC_OK;
+    for (int64_t e = 0; e < nnzh; e++) cnt[hrow[e] + 1]++;
+    for (int64_t e = 0; e < nnzj; e++) cnt[nvar + jrow[e] + 1]++;
+    for (int64_t x = 0; x < dim; x++) cnt[x + 1]++;
+    for (int64_t x = 0; x < dim; x++) cnt[x + 1] += cnt[x];
+    memcpy(pos, cnt, sizeof(int64_t) * (size_t)dim);
+    for (int64_t e = 0; e < nnzh; e++) {
+        if (hcol[e] > hrow[e]) rc = ORC_BAD;
+        ent_t t = { hcol[e], 2 * e };
+        ent[pos[hrow[e]]++] = t;
+    }
+    for (int64_t e = 0; e < nnzj; e++) {
+        int64_t row = nvar + jrow[e];
+        if (jcol[e] > row) rc = ORC_BAD;
+        ent_t t = { jcol[e], 2 * e + 1 };
+        ent[pos[row]++] = t;
+    }
+    for (int64_t x = 0; x < dim; x++) {
+        ent_t t = { x, -1 };
+        ent[pos[x]++] = t;
+    }
+    free(pos);
+    int64_t slot = -1;
+    rowptr[0] = 0;
+    for (int64_t x = 0; x < dim; x++) {
+        int64_t b = cnt[x], en = cnt[x + 1];
+        qsort(ent + b, (size_t)(en - b), sizeof(ent_t), ent_cmp);
+        int64_t prev = -1;
+        for (int64_t u = b; u < en; u++) {
+            if (u == b || ent[u].col != prev) {
+                slot++;
+                colind[slot] = (int32_t)ent[u].col;
+                prev = ent[u].col;
+            }
+            int64_t sr = ent[u].src;
+            if (sr >= 0) {
+                if (sr % 2 == 0) perm_h[sr / 2] = (int32_t)slot;
+                else perm_j[sr / 2] = (int32_t)slot;
+            }
+        }
+        rowptr[x + 1] = (int32_t)(slot + 1);
+    }
+    *nnzk = slot + 1;
+    free(cnt);
+    free(ent);
+    return rc;
+}

@@ -37,8 +37,14 @@ class Instance:
     q: np.ndarray      # (n,)
     r: np.ndarray      # (m,)
     z: np.ndarray      # (nvar,) = [X (n, N+1) | U (m, N+1)], row-major blocks
-    y: np.ndarray      # (n*N,) multipliers, row (i, k) at i*N + k
+    y: np.ndarray      # (ncon,) multipliers, row (i, k) at i*N + k, then boundary rows
     sigma: float
+    scheme: int = 0    # 0 trapezoidal (controls on N+1 nodes), 1 forward Euler (N nodes)
+    bnd: int = 0       # boundary rows: 0 none, 1 initial state, 2 initial and final state
+
+    @property
+    def NU(self) -> int:
+        return self.N + 1 if self.scheme == 0 else self.N
 
     @property
     def X(self) -> np.ndarray:
@@ -46,7 +52,7 @@ class Instance:
 
     @property
     def U(self) -> np.ndarray:
-        return self.z[self.n * (self.N + 1):].reshape(self.m, self.N + 1)
+        return self.z[self.n * (self.N + 1):].reshape(self.m, self.NU)
 
 
 def coefficients(rng: np.random.Generator, n: int, m: int):
@@ -65,16 +71,22 @@ def point(rng: np.random.Generator, N: int, n: int, m: int):
     return X, U, y
 
 
-def make_instance(N: int, n: int, m: int, seed=0) -> Instance:
-    """One instance of the workload family; ``seed`` may be an int or a list."""
+def make_instance(N: int, n: int, m: int, seed=0, scheme: int = 0, bnd: int = 0) -> Instance:
+    """One instance of the workload family; ``seed`` may be an int or a list.
+    Under the forward-Euler scheme the controls live on N nodes; boundary rows
+    add n (initial) or 2n (initial and final) multipliers, drawn after the
+    defect multipliers."""
     rng = np.random.default_rng(seed)
     A, B, gamma = coefficients(rng, n, m)
-    X, U, y = point(rng, N, n, m)
+    NU = N + 1 if scheme == 0 else N
+    X = rng.normal(0.0, 1.0, (n, N + 1))
+    U = rng.uniform(-1.0, 1.0, (m, NU))
+    y = rng.normal(0.0, 1.0, n * N + bnd * n)
     z = np.concatenate([X.ravel(), U.ravel()])
     return Instance(N=N, n=n, m=m, A=np.ascontiguousarray(A), B=np.ascontiguousarray(B),
                     gamma=gamma, q=np.ones(n), r=np.full(m, 0.1),
-                    z=np.ascontiguousarray(z), y=np.ascontiguousarray(y.ravel()),
-                    sigma=1.0)
+                    z=np.ascontiguousarray(z), y=np.ascontiguousarray(y),
+                    sigma=1.0, scheme=scheme, bnd=bnd)
 
 
 # Named workloads: (N, n, m).

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_diff_pins as D
+from tests import test_oracle_ex_pins as E
 from tests import test_oracle_pins as P
 
 # (name, text in ocp_oracle.c, replacement)
@@ -52,6 +53,16 @@ MUTATIONS = [
      "d = -hh * (sin(X[(int64_t)idx * (N + 1) + k]) + sin(X[(int64_t)idx * (N + 1) + k]));"),
     ("coef grad gamma partner", "d = -hh * (X[(int64_t)i * (N + 1) + k] * X[(int64_t)p * (N + 1) + k]",
      "d = -hh * (X[(int64_t)i * (N + 1) + k] * X[(int64_t)i * (N + 1) + k]"),
+    ("euler defect factor", "c[r0] = (x1 - x0) - h * F0[i];", "c[r0] = (x1 - x0) - hh * F0[i];"),
+    ("euler cost at last node", "return k < d->N ? h : 0.0;", "return k <= d->N ? h : 0.0;"),
+    ("euler next-node entry", "v = 1.0; va = 1.0;", "v = -1.0; va = 1.0;"),
+    ("euler column order", "if (t <= i) return (int64_t)t * (d->N + 1) + k;",
+     "if (t < i) return (int64_t)t * (d->N + 1) + k;"),
+    ("euler state slot", "int j = t <= i ? t : t - 1;", "int j = t < i ? t : t - 1;"),
+    ("euler multiplier of node", "if (scheme == 0 && k >= 1) { a += y", "if (k >= 1) { a += y"),
+    ("euler hessian factor", "double fac = scheme == 0 ? 0.5 * h : h;", "double fac = 0.5 * h;"),
+    ("final boundary node", "int64_t node = b < n ? 0 : N;", "int64_t node = 0;"),
+    ("final boundary column", "(b % n) * (N + 1) + (b < n ? 0 : N));", "(b % n) * (N + 1) + (b < n ? 0 : N - 1));"),
 ]
 
 # Pins run against each mutant: (test function, arguments after the oracle).
@@ -78,6 +89,15 @@ PINS = [
     (D.test_hvp_mixed_difference, (3, 1, 0)),
     (D.test_jvp_complex_step, (5, 4, 2)),
     (D.test_coef_grad_complex_step_and_central_difference, (5, 3, 2)),
+    (E.test_golden_euler_and_boundary, ()),
+    (E.test_euler_defects_of_exact_trajectory_are_second_order, (4, 2)),
+    (E.test_jacobian_complex_step_and_pattern, (3, 3, 1, 1, 2)),
+    (E.test_jacobian_complex_step_and_pattern, (4, 1, 1, 1, 1)),
+    (E.test_hessian_mixed_difference, (3, 3, 1, 1, 1)),
+    (E.test_hessian_mixed_difference, (2, 1, 1, 1, 0)),
+    (E.test_kkt_generic_matches_scipy, (5, 3, 2, 1, 2)),
+    (E.test_euler_linear_quadratic_case, (2,)),
+    (E.test_trapezoidal_branch_equals_pinned_functions, (9, 2, 1)),
 ]
 
 
