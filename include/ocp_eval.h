@@ -91,6 +91,30 @@ typedef struct ocp_sizes_t {
 
 typedef struct ocp_problem ocp_problem;
 
+/* Transcription options (the *_ex entry points; NULL means the defaults). */
+#define OCP_SCHEME_TRAPEZOIDAL 0   /* default: the trapezoidal scheme above */
+#define OCP_SCHEME_EULER 1         /* forward Euler (paper Sec. 3), see below */
+#define OCP_BOUNDARY_NONE 0        /* default: defect rows only */
+#define OCP_BOUNDARY_INITIAL 1     /* n rows X_i0 after the defects */
+#define OCP_BOUNDARY_INITIAL_FINAL 2  /* n rows X_i0, then n rows X_iN */
+
+/* Forward Euler (paper Sec. 3): controls on the N nodes 0..N-1 (vu(l,k) =
+ * n (N+1) + l N + k, nvar = n (N+1) + m N); defects c_ik = X_{i,k+1} - X_ik
+ * - h F_i(k); cost sum_{k<N} h (sum q X_k^2 + sum r U_k^2).  Jacobian rows
+ * have T = n + 1 + m slots in ascending column order: X_0..X_i at k, X_i at
+ * k+1, X_{i+1}..X_{n-1} at k, then U_0..U_{m-1} at k.  Hessian: state and
+ * pair slots as above (node N carries zeros), control slots
+ * (n+npair)(N+1) + l N + k.
+ * Boundary rows (either scheme), after the n N defect rows: their value is
+ * the state itself (X_i0, then X_iN), as in the paper's generated code for
+ * x(0) == x0 (Sec. 5), whose target enters the solver as lcon = ucon.  Each
+ * adds one Jacobian entry (1.0) after the defect entries and no Hessian
+ * entry. */
+typedef struct ocp_options {
+    int32_t scheme;    /* OCP_SCHEME_* */
+    int32_t boundary;  /* OCP_BOUNDARY_* */
+} ocp_options;
+
 /* Sizes of the transcribed NLP (paper Sec. 3, trapezoidal scheme of Sec. 5).
  * Host only; no HIP call.  Errors: OCP_ERR_ARG, OCP_ERR_OVERFLOW. */
 int ocp_sizes(int64_t N, int32_t n, int32_t m, ocp_sizes_t *out);
@@ -113,6 +137,18 @@ int ocp_build_pattern(int64_t N, int32_t n, int32_t m, int32_t *jrow, int32_t *j
 int ocp_build_kkt(int64_t N, int32_t n, int32_t m, int32_t *rowptr, int32_t *colind,
                   int32_t *perm_j, int32_t *perm_h);
 
+/* ocp_sizes with transcription options (NULL = defaults).  Errors: as
+ * ocp_sizes, plus OCP_ERR_ARG for an unknown scheme or boundary value. */
+int ocp_sizes_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, ocp_sizes_t *out);
+
+/* ocp_build_pattern with transcription options (NULL = defaults). */
+int ocp_build_pattern_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, int32_t *jrow,
+                         int32_t *jcol, int32_t *hrow, int32_t *hcol);
+
+/* ocp_build_kkt with transcription options (NULL = defaults). */
+int ocp_build_kkt_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, int32_t *rowptr,
+                     int32_t *colind, int32_t *perm_j, int32_t *perm_h);
+
 /* Create a problem handle on the current HIP device.  A: n x n row-major,
  * B: n x m row-major, gamma: n, q: n, r: m (host pointers; B and r may be
  * NULL when m = 0).  Copies them to the device.
@@ -120,6 +156,14 @@ int ocp_build_kkt(int64_t N, int32_t n, int32_t m, int32_t *rowptr, int32_t *col
  * OCP_ERR_ALLOC, OCP_ERR_HIP. */
 int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B,
                const double *gamma, const double *q, const double *r, ocp_problem **out);
+
+/* ocp_create with transcription options (NULL = defaults).  Every evaluation
+ * and the assembly follow the handle's options; the batched and the
+ * Lagrangian-derivative entry points accept only the defaults (OCP_ERR_ARG
+ * otherwise). */
+int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const double *A,
+                  const double *B, const double *gamma, const double *q, const double *r,
+                  ocp_problem **out);
 
 /* Release a handle and its device memory.  NULL-safe.  The caller must make
  * sure no work using the handle is still in flight. */

@@ -930,24 +930,28 @@ int orc_cons_ex(int64_t N, int n, int m, int scheme, int bnd, const double *A, c
     exdims_t d;
     if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !c) return ORC_BAD;
     double h = 1.0 / (double)N, hh = 0.5 * h;
-    double *F0 = (double *)malloc(sizeof(double) * 4 * n);
-    double *F1 = F0 + n, *A0 = F0 + 2 * n, *A1 = F0 + 3 * n;
-    for (int64_t k = 0; k < N; k++) {
-        dyn_ex(&d, A, B, gam, z, k, F0, A0);
-        if (scheme == 0) dyn_ex(&d, A, B, gam, z, k + 1, F1, A1);
-        for (int i = 0; i < n; i++) {
-            double x0 = XV(z, &d, i, k), x1 = XV(z, &d, i, k + 1);
-            int64_t r0 = (int64_t)i * N + k;
-            if (scheme == 0) {
-                c[r0] = (x1 - x0) - hh * (F0[i] + F1[i]);
-                if (mu) mu[r0] = fabs(x1) + fabs(x0) + hh * (A0[i] + A1[i]);
-            } else {
-                c[r0] = (x1 - x0) - h * F0[i];
-                if (mu) mu[r0] = fabs(x1) + fabs(x0) + h * A0[i];
+    #pragma omp parallel
+    {
+        double *F0 = (double *)malloc(sizeof(double) * 4 * n);
+        double *F1 = F0 + n, *A0 = F0 + 2 * n, *A1 = F0 + 3 * n;
+        #pragma omp for schedule(static)
+        for (int64_t k = 0; k < N; k++) {
+            dyn_ex(&d, A, B, gam, z, k, F0, A0);
+            if (scheme == 0) dyn_ex(&d, A, B, gam, z, k + 1, F1, A1);
+            for (int i = 0; i < n; i++) {
+                double x0 = XV(z, &d, i, k), x1 = XV(z, &d, i, k + 1);
+                int64_t r0 = (int64_t)i * N + k;
+                if (scheme == 0) {
+                    c[r0] = (x1 - x0) - hh * (F0[i] + F1[i]);
+                    if (mu) mu[r0] = fabs(x1) + fabs(x0) + hh * (A0[i] + A1[i]);
+                } else {
+                    c[r0] = (x1 - x0) - h * F0[i];
+                    if (mu) mu[r0] = fabs(x1) + fabs(x0) + h * A0[i];
+                }
             }
         }
+        free(F0);
     }
-    free(F0);
     for (int64_t b = 0; b < d.nb; b++) {
         int i = (int)(b % n);
         int64_t node = b < n ? 0 : N;
@@ -1026,6 +1030,7 @@ int orc_jac_ex(int64_t N, int n, int m, int scheme, int bnd, const double *A, co
     if (ex_dims(N, n, m, scheme, bnd, &d) || !z || !out) return ORC_BAD;
     double h = 1.0 / (double)N, hh = 0.5 * h;
     const double *X = z;
+    #pragma omp parallel for collapse(2) schedule(static)
     for (int i = 0; i < n; i++)
         for (int t = 0; t < d.T; t++)
             for (int64_t k = 0; k < N; k++) {

@@ -44,6 +44,20 @@ class Sizes(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class Options(ctypes.Structure):
+    """Transcription options: scheme 0 trapezoidal / 1 forward Euler; boundary
+    0 none / 1 initial-state rows / 2 initial- and final-state rows."""
+    _fields_ = [("scheme", ctypes.c_int32), ("boundary", ctypes.c_int32)]
+
+
+SCHEMES = {"trapezoidal": 0, "euler": 1}
+
+
+def _opts(scheme=0, boundary=0):
+    scheme = SCHEMES.get(scheme, scheme) if isinstance(scheme, str) else scheme
+    return Options(int(scheme), int(boundary))
+
+
 class BatchConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("pair", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("order", ctypes.c_int32)]
@@ -70,6 +84,11 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         L.ocp_sizes.argtypes = [i64, i32, i32, ctypes.POINTER(Sizes)]
+        L.ocp_sizes_ex.argtypes = [i64, i32, i32, ctypes.POINTER(Options), ctypes.POINTER(Sizes)]
+        L.ocp_build_pattern_ex.argtypes = [i64, i32, i32, ctypes.POINTER(Options), vp, vp, vp, vp]
+        L.ocp_build_kkt_ex.argtypes = [i64, i32, i32, ctypes.POINTER(Options), vp, vp, vp, vp]
+        L.ocp_create_ex.argtypes = [i64, i32, i32, ctypes.POINTER(Options), vp, vp, vp, vp, vp,
+                                    ctypes.POINTER(vp)]
         L.ocp_build_pattern.argtypes = [i64, i32, i32, vp, vp, vp, vp]
         L.ocp_build_kkt.argtypes = [i64, i32, i32, vp, vp, vp, vp]
         L.ocp_create.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -126,32 +145,37 @@ def _hp(a: np.ndarray | None):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
-def sizes(N: int, n: int, m: int) -> dict:
+def sizes(N: int, n: int, m: int, scheme=0, boundary=0) -> dict:
     s = Sizes()
-    _check(lib().ocp_sizes(N, n, m, ctypes.byref(s)), "ocp_sizes")
+    o = _opts(scheme, boundary)
+    _check(lib().ocp_sizes_ex(N, n, m, ctypes.byref(o), ctypes.byref(s)), "ocp_sizes")
     return s.as_dict()
 
 
-def pattern(N: int, n: int, m: int, jac: bool = True, hess: bool = True):
+def pattern(N: int, n: int, m: int, jac: bool = True, hess: bool = True, scheme=0, boundary=0):
     """Host COO patterns (jrow, jcol, hrow, hcol), int32; skipped parts are None."""
-    s = sizes(N, n, m)
+    s = sizes(N, n, m, scheme, boundary)
     jrow = np.empty(s["nnzj"], np.int32) if jac else None
     jcol = np.empty(s["nnzj"], np.int32) if jac else None
     hrow = np.empty(s["nnzh"], np.int32) if hess else None
     hcol = np.empty(s["nnzh"], np.int32) if hess else None
-    _check(lib().ocp_build_pattern(N, n, m, _hp(jrow), _hp(jcol), _hp(hrow), _hp(hcol)),
-           "ocp_build_pattern")
+    o = _opts(scheme, boundary)
+    _check(lib().ocp_build_pattern_ex(N, n, m, ctypes.byref(o), _hp(jrow), _hp(jcol), _hp(hrow),
+                                      _hp(hcol)), "ocp_build_pattern")
     return jrow, jcol, hrow, hcol
 
 
-def kkt_pattern(N: int, n: int, m: int, rowptr=True, colind=True, perm_j=True, perm_h=True):
+def kkt_pattern(N: int, n: int, m: int, rowptr=True, colind=True, perm_j=True, perm_h=True,
+                scheme=0, boundary=0):
     """Host KKT structure (rowptr, colind, perm_j, perm_h), int32; skipped parts are None."""
-    s = sizes(N, n, m)
+    s = sizes(N, n, m, scheme, boundary)
     rp = np.empty(s["dim"] + 1, np.int32) if rowptr else None
     ci = np.empty(s["nnzk"], np.int32) if colind else None
     pj = np.empty(s["nnzj"], np.int32) if perm_j else None
     ph = np.empty(s["nnzh"], np.int32) if perm_h else None
-    _check(lib().ocp_build_kkt(N, n, m, _hp(rp), _hp(ci), _hp(pj), _hp(ph)), "ocp_build_kkt")
+    o = _opts(scheme, boundary)
+    _check(lib().ocp_build_kkt_ex(N, n, m, ctypes.byref(o), _hp(rp), _hp(ci), _hp(pj), _hp(ph)),
+           "ocp_build_kkt")
     return rp, ci, pj, ph
 
 
@@ -163,11 +187,12 @@ def _torch():
 class Problem:
     """One transcribed OCP instance bound to a GPU (the current torch device)."""
 
-    def __init__(self, N, n, m, A, B, gamma, q, r, device=None):
+    def __init__(self, N, n, m, A, B, gamma, q, r, device=None, scheme=0, boundary=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise OcpError(OCP_ERR_HIP, "no GPU visible: this library runs only on gfx950 devices")
         self.N, self.n, self.m = int(N), int(n), int(m)
+        self.options = _opts(scheme, boundary)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         f64 = lambda a, shape: np.ascontiguousarray(np.asarray(a, np.float64).reshape(shape))
@@ -177,9 +202,9 @@ class Problem:
         r = f64(r, (m,)) if m else np.zeros(0)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib().ocp_create(self.N, self.n, self.m, _hp(A), _hp(B) if m else None,
-                                    _hp(gamma), _hp(q), _hp(r) if m else None, ctypes.byref(h)),
-                   "ocp_create")
+            _check(lib().ocp_create_ex(self.N, self.n, self.m, ctypes.byref(self.options), _hp(A),
+                                       _hp(B) if m else None, _hp(gamma), _hp(q),
+                                       _hp(r) if m else None, ctypes.byref(h)), "ocp_create")
         self._h = h
         s = Sizes()
         _check(lib().ocp_problem_sizes(self._h, ctypes.byref(s)), "ocp_problem_sizes")
@@ -187,7 +212,8 @@ class Problem:
 
     @classmethod
     def from_instance(cls, inst, device=None):
-        return cls(inst.N, inst.n, inst.m, inst.A, inst.B, inst.gamma, inst.q, inst.r, device)
+        return cls(inst.N, inst.n, inst.m, inst.A, inst.B, inst.gamma, inst.q, inst.r, device,
+                   scheme=getattr(inst, "scheme", 0), boundary=getattr(inst, "bnd", 0))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -70,6 +70,9 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, const InstDesc *__rest
         P.T = bp.T;
         P.S = bp.S;
         P.nnzk = 0;
+        P.NU = id.N + 1;
+        P.scheme = 0;
+        P.nb = 0;
         P.h = id.h;
         P.hh = id.hh;
         P.A = bp.A + (int64_t)td.b * bp.n * bp.n;
@@ -238,6 +241,9 @@ static int batch_launch(const ocp_batch *b, const TileDesc *tiles, int32_t what,
         P.T = b->bp.T;
         P.S = b->bp.S;
         P.nnzk = 0;
+        P.NU = P.N1;
+        P.scheme = 0;
+        P.nb = 0;
         P.h = 1.0 / (double)P.N;
         P.hh = 0.5 * P.h;
         P.A = b->bp.A + (int64_t)i * b->n * b->n;

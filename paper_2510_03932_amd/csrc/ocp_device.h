@@ -34,6 +34,9 @@ struct KP {
     int N1;        // nodes = N + 1
     int n, m, npair, T, S;
     int nnzk;      // KKT entries
+    int NU;        // control nodes: N + 1 (trapezoidal) or N (forward Euler)
+    int scheme;    // 0 trapezoidal, 1 forward Euler
+    int nb;        // boundary rows after the n N defect rows
     double h, hh;
     const double *A;    // n x n row-major
     const double *B;    // n x m row-major
@@ -42,8 +45,11 @@ struct KP {
     const double *r;    // m
 };
 
+// Cost weight of node k: trapezoidal rule (end nodes h/2), or the forward
+// Euler sum over nodes 0..N-1 (weight h, none at node N).
 __device__ __forceinline__ double node_weight(const KP &P, int k)
 {
+    if (P.scheme) return k < P.N ? P.h : 0.0;
     return (k == 0 || k == P.N) ? P.hh : P.h;
 }
 
@@ -237,7 +243,7 @@ __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__
         }
     }
     for (int l = 0; l < m; l++) {
-        const double u = U[l * N1 + k];
+        const double u = U[(int64_t)l * P.NU + k];
 #pragma unroll
         for (int i = 0; i < NB; i++)
             if (i < n) F[i] += P.B[i * m + l] * u;
@@ -261,6 +267,119 @@ __device__ __forceinline__ double last_of(const double (&a)[NB], int n)
     for (int i = 0; i < NB; i++)
         if (i == n - 1) v = a[i];
     return v;
+}
+
+// ---------------------------------------------------------------------------
+// Forward Euler (paper Sec. 3): Jacobian values of one column for NPT
+// consecutive intervals k .. k+NPT-1 (k + NPT <= N; NPT = 2 needs N even and a
+// 16-byte aligned output).  Row i's slots, in ascending column order, are
+// X_0..X_i at k (slots 0..i), X_i at k+1 (slot i+1), X_{i+1}..X_{n-1} at k
+// (slots i+2..n), U_l at k (slot n+1+l).  State column j writes slot
+// (j <= i ? j : j+1) of every row i, -delta_ij - h dF_i/dX_j(k), and the +1
+// at slot j+1 of row j; control column l writes -h B_il at slot n+1+l.
+// ---------------------------------------------------------------------------
+template <int NPT>
+__device__ __forceinline__ void jac_column_euler(const KP &P, const double *__restrict__ z,
+                                                 double *__restrict__ jac, int64_t k, int col)
+{
+    const int n = P.n, T = P.T;
+    const int64_t N = P.N, N1 = P.N1;
+    const double h = P.h;
+    auto put = [&](int64_t i, int t, const double (&v)[NPT]) {
+        double *o = jac + ((int64_t)i * T + t) * N + k;
+        if constexpr (NPT == 2) st_nt2(o, dbl2{v[0], v[1]});
+        else st_nt(o, v[0]);
+    };
+    if (col < n) {
+        const int j = col;
+        const int jn = (j + 1 == n) ? 0 : j + 1;
+        const int jp = (j == 0) ? n - 1 : j - 1;
+        const double *xj = z + j * N1 + k;
+        const double *xn = z + jn * N1 + k;
+        const double *xp = z + jp * N1 + k;
+        double cs[NPT], dg[NPT], lo[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; u++) {
+            cs[u] = cos(xj[u]);
+            dg[u] = -h * P.gam[j] * xn[u];   // row i = j: gamma_j X_{j+1}
+            lo[u] = -h * P.gam[jp] * xp[u];  // row i = j-1: gamma_{j-1} X_{j-1}
+        }
+        for (int i = 0; i < n; i++) {
+            const double a = -h * P.A[i * n + j];
+            double v[NPT];
+#pragma unroll
+            for (int u = 0; u < NPT; u++) v[u] = a * cs[u];
+            if (i == j) {
+#pragma unroll
+                for (int u = 0; u < NPT; u++) v[u] += dg[u] - 1.0;
+            }
+            if (i == jp) {
+#pragma unroll
+                for (int u = 0; u < NPT; u++) v[u] += lo[u];
+            }
+            put(i, j <= i ? j : j + 1, v);
+        }
+        double one[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; u++) one[u] = 1.0;
+        put(j, j + 1, one);
+    } else {
+        const int l = col - n, m = P.m;
+        for (int i = 0; i < n; i++) {
+            double v[NPT];
+#pragma unroll
+            for (int u = 0; u < NPT; u++) v[u] = -h * P.B[i * m + l];
+            put(i, n + 1 + l, v);
+        }
+    }
+}
+
+// Forward Euler Hessian-of-Lagrangian values at node k <= N: node k enters
+// only the defect of interval k (multiplier y_k, factor h); node N enters no
+// defect and carries no cost, so its entries are zero.  Control slots exist
+// for k < N only, at (n+npair)(N+1) + l N + k.
+template <int NB>
+__device__ __forceinline__ void hess_node_euler(const KP &P, const double *__restrict__ z,
+                                                const double *__restrict__ y, double sigma,
+                                                double *__restrict__ hv, int k)
+{
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1;
+    const double w = node_weight(P, k);
+    const double h = P.h;
+    double x[NB], yt[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        x[i] = yt[i] = 0.0;
+        if (i < n) {
+            x[i] = z[i * N1 + k];
+            if (k < P.N) yt[i] = y[i * N + k];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        if (j < n) {
+            const double sx = sin(x[j]);
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                if (i < n) s += yt[i] * P.A[i * n + j];
+            double v = 2.0 * sigma * w * P.q[j] + h * sx * s;
+            if (n == 1) v -= 2.0 * h * yt[0] * P.gam[0];
+            st_nt(hv + j * N1 + k, v);
+        }
+    }
+    if (n >= 3) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_nt(hv + (n + i) * N1 + k, -h * yt[i] * P.gam[i]);
+    } else if (n == 2) {
+        st_nt(hv + 2 * N1 + k, -h * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+    }
+    if (k < P.NU) {
+        const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
+        for (int l = 0; l < m; l++) st_nt(hv + ub + (int64_t)l * P.NU, 2.0 * sigma * w * P.r[l]);
+    }
 }
 
 // Host-side launchers of the single-instance Jacobian and Hessian kernels

@@ -33,6 +33,16 @@
 using namespace ocp;
 using namespace ocp::dev;
 
+// The derivative kernels implement the trapezoidal transcription without
+// boundary rows.
+static int check_default_options(const ocp_problem *p, const char *what)
+{
+    if (p->d.scheme != OCP_SCHEME_TRAPEZOIDAL || p->d.nb != 0)
+        return fail(OCP_ERR_ARG, std::string(what) +
+                                     ": supports the trapezoidal scheme without boundary rows only");
+    return OCP_OK;
+}
+
 namespace {
 
 constexpr int kCols = 8;  // coefficient-gradient columns per workgroup
@@ -359,6 +369,7 @@ int ocp_eval_lagrangian(const ocp_problem *p, const double *z, const double *y, 
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_lagrangian")) return rc;
+    if (int rc = check_default_options(p, "ocp_eval_lagrangian")) return rc;
     if (!z || !y || !L) return fail(OCP_ERR_ARG, "ocp_eval_lagrangian: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_lagrangian: sigma is not finite");
     const int nchunks = (int)blocks_for(p->d.N, kBlock - 1);
@@ -374,6 +385,7 @@ int ocp_eval_lag_grad(const ocp_problem *p, const double *z, const double *y, do
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_lag_grad")) return rc;
+    if (int rc = check_default_options(p, "ocp_eval_lag_grad")) return rc;
     if (!z || !y || !g) return fail(OCP_ERR_ARG, "ocp_eval_lag_grad: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_lag_grad: sigma is not finite");
     OCP_DISPATCH_NB(p->d.n, lag_grad_kernel, dim3(blocks_for(p->d.N1, kBlock)), stream, p->kp, z, y,
@@ -386,6 +398,7 @@ int ocp_eval_hvp(const ocp_problem *p, const double *z, const double *y, double 
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_hvp")) return rc;
+    if (int rc = check_default_options(p, "ocp_eval_hvp")) return rc;
     if (!z || !y || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_hvp: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_hvp: sigma is not finite");
     OCP_DISPATCH_NB(p->d.n, hvp_kernel, dim3(blocks_for(p->d.N1, kBlock)), stream, p->kp, z, y, sigma,
@@ -398,6 +411,7 @@ int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double 
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_jvp")) return rc;
+    if (int rc = check_default_options(p, "ocp_eval_jvp")) return rc;
     if (!z || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_jvp: null array");
     OCP_DISPATCH_NB(p->d.n, jvp_kernel, dim3(blocks_for(p->d.N, kBlock - 1)), stream, p->kp, z, v,
                     out);
@@ -409,6 +423,7 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_coef_grad")) return rc;
+    if (int rc = check_default_options(p, "ocp_eval_coef_grad")) return rc;
     if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_grad: null array");
     const int n = p->d.n, m = p->d.m, ncol = n + m + 1;

@@ -86,6 +86,64 @@ __global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Forward-Euler defects: one lane per interval k < N,
+//   c_ik = (X_{i,k+1} - X_ik) - h F_i(k)  (paper Sec. 3).
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(kBlock) void cons_euler_kernel(KP P, const double *__restrict__ z,
+                                                            double *__restrict__ c)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= P.N) return;
+    const int n = P.n;
+    const int64_t N = P.N, N1 = P.N1;
+    double x[NB], F[NB];
+    dyn_node<NB>(P, z, k, x, F);
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+        if (i < n) st_nt(c + i * N + k, (z[i * N1 + k + 1] - x[i]) - P.h * F[i]);
+}
+
+// Boundary rows after the n N defect rows: row b holds X_{b mod n} at node 0
+// (b < n) or node N; its single Jacobian entry (1.0) follows the defect
+// entries.
+__global__ __launch_bounds__(kBlock) void bnd_cons_kernel(KP P, const double *__restrict__ z,
+                                                          double *__restrict__ c)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= P.nb) return;
+    const int i = b % P.n;
+    const int64_t node = b < P.n ? 0 : P.N;
+    c[(int64_t)P.n * P.N + b] = z[(int64_t)i * P.N1 + node];
+}
+
+__global__ __launch_bounds__(kBlock) void bnd_jac_kernel(KP P, double *__restrict__ jac)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= P.nb) return;
+    jac[(int64_t)P.n * P.N * P.T + b] = 1.0;
+}
+
+template <int NPT>
+__global__ __launch_bounds__(kBlock) void jac_euler_kernel(KP P, const double *__restrict__ z,
+                                                           double *__restrict__ jac)
+{
+    const int64_t k = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPT;
+    if (k >= P.N) return;
+    jac_column_euler<NPT>(P, z, jac, k, blockIdx.y);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void hess_euler_kernel(KP P, const double *__restrict__ z,
+                                                            const double *__restrict__ y,
+                                                            double sigma, double *__restrict__ hv)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    hess_node_euler<NB>(P, z, y, sigma, hv, k);
+}
+
+// ---------------------------------------------------------------------------
 // Gradient: g = 2 w_k q_j X_jk, 2 w_k r_l U_lk.  blockIdx.y = component.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__restrict__ z,
@@ -93,9 +151,10 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__rest
 {
     const int comp = blockIdx.y;
     const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k > P.N) return;
+    if (k > P.N || (comp >= P.n && k >= P.NU)) return;
     const double coef = comp < P.n ? P.q[comp] : P.r[comp - P.n];
-    const int64_t e = (int64_t)comp * P.N1 + k;
+    const int64_t e = comp < P.n ? (int64_t)comp * P.N1 + k
+                                 : (int64_t)P.n * P.N1 + (int64_t)(comp - P.n) * P.NU + k;
     const double w = node_weight(P, k);
     st_nt(g + e, 2.0 * w * coef * z[e]);
 }
@@ -118,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double 
         double s = 0.0;
 #pragma unroll 8
         for (int c = 0; c < nc; c++) {
-            const double v = z[c * N1 + k];
+            if (c >= n && k >= P.NU) continue;  // controls exist on NU nodes
+            const double v = c < n ? z[c * N1 + k] : z[n * N1 + (c - n) * (int64_t)P.NU + k];
             s += (c < n ? P.q[c] : P.r[c - n]) * v * v;
         }
         acc += node_weight(P, (int)k) * s;
@@ -156,14 +216,14 @@ __global__ __launch_bounds__(kBlock) void obj_final_kernel(const double *__restr
 // reg on the variable diagonals in the same IEEE add.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void assemble_kernel(
-    KP P, int gj, int KT, bool vec_ok, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
+    KP P, int gj, int gh, int KT, bool vec_ok, const int32_t *__restrict__ perm_j, const int32_t *__restrict__ perm_h,
     const int32_t *__restrict__ rowptr, const double *__restrict__ jv,
     const double *__restrict__ hv, const double *__restrict__ reg, double *__restrict__ kkt)
 {
     extern __shared__ double tile[];
     __shared__ int filled;
     const int64_t N = P.N, N1 = P.N1;
-    const int64_t nvar = (int64_t)(P.n + P.m) * N1;
+    const int64_t nvar = (int64_t)P.n * N1 + (int64_t)P.m * P.NU;
     const uint32_t nnzk = (uint32_t)P.nnzk;  // slots outside [0, nnzk) are skipped
     const int T = P.T;
     if ((int)blockIdx.x < gj) {
@@ -240,20 +300,36 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
                 if ((uint32_t)q < nnzk) kkt[q] = reg ? reg[d] : 0.0;
             }
         }
-    } else {
+    } else if ((int)blockIdx.x < gj + gh) {
         const int64_t k = (int64_t)(blockIdx.x - gj) * kBlock + threadIdx.x;
         if (k >= N1) return;
         const int n = P.n, np = P.npair, S = P.S;
         for (int s = 0; s < S; s++) {
-            const int64_t e = (int64_t)s * N1 + k;
-            double v = hv[e];
-            if (reg && (s < n || s >= n + np)) {
-                const int64_t row = (s < n) ? (int64_t)s * N1 + k : (int64_t)(s - np) * N1 + k;
-                v += reg[row];
+            int64_t e, row = -1;  // COO entry; KKT row of a diagonal entry
+            if (s < n + np) {
+                e = (int64_t)s * N1 + k;
+                if (s < n) row = e;
+            } else {
+                if (k >= P.NU) break;  // control slots exist on NU nodes
+                const int64_t l = s - n - np;
+                e = (int64_t)(n + np) * N1 + l * P.NU + k;
+                row = (int64_t)n * N1 + l * P.NU + k;
             }
+            double v = hv[e];
+            if (reg && row >= 0) v += reg[row];
             const uint32_t q = (uint32_t)perm_h[e];
             if (q < nnzk) kkt[q] = v;
         }
+    } else {
+        // boundary rows: their Jacobian entry and their diagonal
+        const int b = (blockIdx.x - gj - gh) * kBlock + threadIdx.x;
+        if (b >= P.nb) return;
+        const int64_t e = (int64_t)P.n * N * T + b;
+        const uint32_t q = (uint32_t)perm_j[e];
+        if (q < nnzk) kkt[q] = jv[e];
+        const int64_t d = nvar + (int64_t)P.n * N + b;
+        const uint32_t dq = (uint32_t)(rowptr[d + 1] - 1);
+        if (dq < nnzk) kkt[dq] = reg ? reg[d] : 0.0;
     }
 }
 
@@ -271,24 +347,38 @@ hipError_t launch_jac(const KP &P, const double *z, double *jac, bool pair_ok, h
     // Paired 16-byte stores need every slot row 16-byte aligned: N even and
     // the output 16-byte aligned.
     const unsigned cols = (unsigned)(P.n + P.m);
-    if (pair_ok && P.N % 2 == 0) {
-        hipLaunchKernelGGL(jac_kernel<2>, dim3((unsigned)((P.N / 2 + kBlock - 1) / kBlock), cols),
-                           dim3(kBlock), 0, stream, P, z, jac);
+    const bool pair = pair_ok && P.N % 2 == 0;
+    const dim3 g2((unsigned)((P.N / 2 + kBlock - 1) / kBlock), cols);
+    const dim3 g1((unsigned)((P.N + kBlock - 1) / kBlock), cols);
+    if (P.scheme == 0) {
+        if (pair) hipLaunchKernelGGL(jac_kernel<2>, g2, dim3(kBlock), 0, stream, P, z, jac);
+        else hipLaunchKernelGGL(jac_kernel<1>, g1, dim3(kBlock), 0, stream, P, z, jac);
     } else {
-        hipLaunchKernelGGL(jac_kernel<1>, dim3((unsigned)((P.N + kBlock - 1) / kBlock), cols),
-                           dim3(kBlock), 0, stream, P, z, jac);
+        if (pair) hipLaunchKernelGGL(jac_euler_kernel<2>, g2, dim3(kBlock), 0, stream, P, z, jac);
+        else hipLaunchKernelGGL(jac_euler_kernel<1>, g1, dim3(kBlock), 0, stream, P, z, jac);
     }
+    if (P.nb > 0)
+        hipLaunchKernelGGL(bnd_jac_kernel, dim3((P.nb + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                           P, jac);
     return hipGetLastError();
+}
+
+template <int NB>
+static void launch_hess_nb(const KP &P, const double *z, const double *y, double sigma, double *hv,
+                           hipStream_t stream)
+{
+    const dim3 g((unsigned)((P.N1 + kBlock - 1) / kBlock));
+    if (P.scheme == 0) hipLaunchKernelGGL(hess_kernel<NB>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
+    else hipLaunchKernelGGL(hess_euler_kernel<NB>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
 }
 
 hipError_t launch_hess(const KP &P, const double *z, const double *y, double sigma, double *hv,
                        hipStream_t stream)
 {
-    const dim3 g((unsigned)((P.N1 + kBlock - 1) / kBlock));
-    if (P.n <= 4) hipLaunchKernelGGL(hess_kernel<4>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
-    else if (P.n <= 8) hipLaunchKernelGGL(hess_kernel<8>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
-    else if (P.n <= 16) hipLaunchKernelGGL(hess_kernel<16>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
-    else hipLaunchKernelGGL(hess_kernel<32>, g, dim3(kBlock), 0, stream, P, z, y, sigma, hv);
+    if (P.n <= 4) launch_hess_nb<4>(P, z, y, sigma, hv, stream);
+    else if (P.n <= 8) launch_hess_nb<8>(P, z, y, sigma, hv, stream);
+    else if (P.n <= 16) launch_hess_nb<16>(P, z, y, sigma, hv, stream);
+    else launch_hess_nb<32>(P, z, y, sigma, hv, stream);
     return hipGetLastError();
 }
 
@@ -300,11 +390,19 @@ extern "C" {
 int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B,
                const double *gamma, const double *q, const double *r, ocp_problem **out)
 {
+    return ocp_create_ex(N, n, m, nullptr, A, B, gamma, q, r, out);
+}
+
+int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const double *A,
+                  const double *B, const double *gamma, const double *q, const double *r,
+                  ocp_problem **out)
+{
     clear_error();
     if (!out) return fail(OCP_ERR_ARG, "ocp_create: out is NULL");
     *out = nullptr;
     Dims d;
-    int rc = make_dims(N, n, m, &d);
+    int rc = make_dims_ex(N, n, m, opt ? opt->scheme : OCP_SCHEME_TRAPEZOIDAL,
+                          opt ? opt->boundary : OCP_BOUNDARY_NONE, &d);
     if (rc) return rc;
     if (!A || !gamma || !q || (m > 0 && (!B || !r)))
         return fail(OCP_ERR_ARG, "ocp_create: coefficient pointer is NULL");
@@ -347,6 +445,9 @@ int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B
     kp.T = d.T;
     kp.S = d.S;
     kp.nnzk = (int)d.nnzk;
+    kp.NU = (int)d.NU;
+    kp.scheme = d.scheme;
+    kp.nb = (int)d.nb;
     kp.h = 1.0 / (double)d.N;
     kp.hh = 0.5 * kp.h;
     kp.A = p->coef;
@@ -403,12 +504,23 @@ int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t 
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_cons")) return rc;
     if (!z || !c) return fail(OCP_ERR_ARG, "ocp_eval_cons: null array");
-    const unsigned g = blocks_for(p->d.N, kBlock - 1);
     const int n = p->d.n;
-    if (n <= 4) hipLaunchKernelGGL(cons_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-    else if (n <= 8) hipLaunchKernelGGL(cons_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-    else if (n <= 16) hipLaunchKernelGGL(cons_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-    else hipLaunchKernelGGL(cons_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    if (p->d.scheme == OCP_SCHEME_TRAPEZOIDAL) {
+        const unsigned g = blocks_for(p->d.N, kBlock - 1);
+        if (n <= 4) hipLaunchKernelGGL(cons_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+        else if (n <= 8) hipLaunchKernelGGL(cons_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+        else if (n <= 16) hipLaunchKernelGGL(cons_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+        else hipLaunchKernelGGL(cons_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    } else {
+        const unsigned g = blocks_for(p->d.N, kBlock);
+        if (n <= 4) hipLaunchKernelGGL(cons_euler_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+        else if (n <= 8) hipLaunchKernelGGL(cons_euler_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+        else if (n <= 16) hipLaunchKernelGGL(cons_euler_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+        else hipLaunchKernelGGL(cons_euler_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
+    }
+    if (p->d.nb > 0)
+        hipLaunchKernelGGL(bnd_cons_kernel, dim3(blocks_for(p->d.nb, kBlock)), dim3(kBlock), 0, stream,
+                           p->kp, z, c);
     return check_launch("ocp_eval_cons");
 }
 
@@ -448,11 +560,12 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
     const unsigned tiles_per_i = (unsigned)((p->d.N + KT - 1) / KT);
     const unsigned gj = tiles_per_i * (unsigned)p->d.n;
     const unsigned gh = blocks_for(p->d.N1, kBlock);
+    const unsigned gb = blocks_for(p->d.nb, kBlock);
     const size_t lds = (size_t)KT * (p->d.T + 1) * sizeof(double);
     // paired loads need 16-byte aligned values and 8-byte aligned slots
     const bool vec_ok = ((uintptr_t)jvals % 16 == 0) && ((uintptr_t)perm_j % 8 == 0);
-    hipLaunchKernelGGL(assemble_kernel, dim3(gj + gh), dim3(kBlock), lds, stream, p->kp, (int)gj,
-                       KT, vec_ok, perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
+    hipLaunchKernelGGL(assemble_kernel, dim3(gj + gh + gb), dim3(kBlock), lds, stream, p->kp, (int)gj,
+                       (int)gh, KT, vec_ok, perm_j, perm_h, rowptr, jvals, hvals, reg, kkt);
     return check_launch("ocp_assemble_kkt");
 }
 

@@ -19,7 +19,7 @@ GRID = [(1, 1, 0), (1, 1, 1), (2, 1, 0), (3, 2, 0), (2, 2, 1), (5, 3, 0), (4, 3,
 def test_library_exports_every_declared_symbol():
     L = ocp.lib()
     names = ocp.exported_names()
-    assert len(names) == 29, names
+    assert len(names) == 33, names
     for name in names:
         assert hasattr(L, name), name
     text = open(ocp.HEADER).read()
@@ -145,3 +145,29 @@ def test_batch_create_rejects_bad_arguments_before_any_hip_call():
     assert L.ocp_graph_launch(None, None) == ocp.OCP_ERR_ARG
     L.ocp_batch_destroy(None)
     L.ocp_graph_destroy(None)
+
+
+EX_GRID = [(1, 1, 0), (2, 1, 1), (3, 2, 0), (4, 3, 1), (7, 5, 3), (1, 16, 8), (33, 16, 8),
+           (17, 32, 32), (1000, 4, 2), (999, 8, 4)]
+
+
+@pytest.mark.parametrize("scheme,bnd", [(s, b) for s in (0, 1) for b in (0, 1, 2)])
+@pytest.mark.parametrize("N,n,m", EX_GRID)
+def test_ex_sizes_patterns_kkt_bit_exact(orc, N, n, m, scheme, bnd):
+    s = ocp.sizes(N, n, m, scheme, bnd)
+    o = orc.sizes_ex(N, n, m, scheme, bnd)
+    for k in ("nvar", "ncon", "nnzj", "nnzh", "dim", "npair", "T", "S"):
+        assert s[k] == o[k], k
+    for g, w in zip(ocp.pattern(N, n, m, scheme=scheme, boundary=bnd), orc.pattern_ex(N, n, m, scheme, bnd)):
+        assert np.array_equal(g, w)
+    got = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd)
+    want = orc.kkt_ex(N, n, m, scheme, bnd)
+    for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h"), got, want):
+        assert np.array_equal(g, w), name
+
+
+def test_ex_rejects_unknown_options():
+    for scheme, bnd in ((2, 0), (-1, 0), (0, 3), (0, -1)):
+        with pytest.raises(ocp.OcpError) as e:
+            ocp.sizes(10, 3, 1, scheme, bnd)
+        assert e.value.code == ocp.OCP_ERR_ARG
