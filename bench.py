@@ -1,6 +1,6 @@
 """Benchmark of the evaluation path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler]
 
 Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
 controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
@@ -255,6 +255,52 @@ def differentiation(torch, ocp, synth, reps=20):
     return out
 
 
+def euler(torch, ocp, synth, reps=10):
+    """Forward-Euler transcription with initial- and final-state rows, at the
+    large shape (N = 1e6, n = 16, m = 8): cons, jac, hess and assemble_kkt
+    timed with HIP events, against their algorithmic bytes."""
+    N, n, m = synth.LARGE
+    dev = torch.device("cuda", 0)
+    inst = synth.make_instance(N, n, m, seed=0, scheme=1, bnd=2)
+    prob = ocp.Problem.from_instance(inst, dev)
+    s = prob.sizes
+    z = torch.from_numpy(inst.z).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    rowptr, _, perm_j, perm_h = ocp.kkt_pattern(N, n, m, colind=False, scheme=1, boundary=2)
+    pj = torch.from_numpy(perm_j).to(dev)
+    del perm_j
+    ph, rp = torch.from_numpy(perm_h).to(dev), torch.from_numpy(rowptr).to(dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    c, jv, hv = torch.empty(s["ncon"], **f64), torch.empty(s["nnzj"], **f64), torch.empty(s["nnzh"], **f64)
+    kkt = torch.empty(s["nnzk"], **f64)
+    nx = n * (N + 1)
+    calls = {
+        "eval_cons": (lambda: prob.cons(z, out=c), 8 * s["nvar"] + 8 * s["ncon"]),
+        "eval_jac": (lambda: prob.jac(z, out=jv), 8 * s["nnzj"] + 8 * nx),
+        "eval_hess": (lambda: prob.hess(z, y, 1.0, out=hv), 8 * s["nnzh"] + 8 * nx + 8 * n * N),
+        "assemble_kkt": (lambda: prob.assemble_kkt(pj, ph, rp, jv, hv, None, out=kkt),
+                         12 * (s["nnzj"] + s["nnzh"]) + 8 * s["nnzk"] + 4 * s["ncon"]),
+    }
+    out = {"workload": f"forward Euler, initial+final state rows, N={N} n={n} m={m}, seed 0",
+           "nnzj": s["nnzj"], "nnzh": s["nnzh"]}
+    for name, (fn, nbytes) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "bytes": nbytes,
+                     "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+    t = (out["eval_jac"]["ms"] + out["eval_hess"]["ms"]) * 1e-3
+    out["jac_hess_nnz_per_s"] = (s["nnzj"] + s["nnzh"]) / t
+    prob.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +311,8 @@ def main():
                     help="run only the 512-instance batched measurement (profiling runs)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-instance batched measurement (profiling runs)")
+    ap.add_argument("--no-euler", action="store_true",
+                    help="skip the forward-Euler measurement (profiling runs)")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the N=2e5 differentiation measurement (profiling runs)")
     ap.add_argument("--no-ipm-loop", action="store_true",
@@ -440,6 +488,9 @@ def main():
     if not args.no_ipm_loop:
         log("[bench] interior-point loop workload")
         out["ipm_loop"] = ipm_loop(torch, ocp, synth)
+    if not args.no_euler:
+        log("[bench] forward-Euler workload")
+        out["euler"] = euler(torch, ocp, synth)
     if not args.no_diff:
         log("[bench] differentiation workload")
         out["differentiation"] = differentiation(torch, ocp, synth)
