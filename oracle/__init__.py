@@ -73,6 +73,13 @@ class Oracle:
                                       ptr, ptr]
             L.orc_kkt_generic.argtypes = [i64, i64, i64, i64, ptr, ptr, ptr, ptr, ptr, ptr, ptr,
                                           ptr, ptr]
+            L.orc_quad_sizes.argtypes = [i64, i32, ptr]
+            L.orc_quad_pattern.argtypes = [i64, i32, ptr, ptr, ptr, ptr]
+            L.orc_quad_obj.argtypes = [i64, dbl, ptr, ptr]
+            L.orc_quad_grad.argtypes = [i64, dbl, ptr, ptr, ptr]
+            L.orc_quad_cons.argtypes = [i64, i32, dbl, ptr, ptr, ptr]
+            L.orc_quad_jac.argtypes = [i64, i32, ptr, ptr, ptr]
+            L.orc_quad_hess.argtypes = [i64, dbl, ptr, ptr, dbl, ptr, ptr]
             L.orc_set_threads.argtypes = [i32]
             L.orc_set_threads.restype = None
             L.orc_get_threads.restype = i32
@@ -299,6 +306,64 @@ class Oracle:
                                       _p(perm_h), _p(nnzk)), "kkt_generic")
         return rowptr, colind[: int(nnzk[0])].copy(), perm_j, perm_h
 
+    # ---- quadrotor model (q: a synth.QuadInstance) ----
+
+    def quad_sizes(self, N, bnd=1) -> dict:
+        out = np.zeros(5, np.int64)
+        _check(self.L.orc_quad_sizes(N, bnd, _p(out)), "quad_sizes")
+        return {k: int(v) for k, v in zip(["nvar", "ncon", "nnzj", "nnzh", "dim"], out)}
+
+    def quad_pattern(self, N, bnd=1):
+        s = self.quad_sizes(N, bnd)
+        jr, jc = np.empty(s["nnzj"], np.int32), np.empty(s["nnzj"], np.int32)
+        hr, hc = np.empty(s["nnzh"], np.int32), np.empty(s["nnzh"], np.int32)
+        _check(self.L.orc_quad_pattern(N, bnd, _p(jr), _p(jc), _p(hr), _p(hc)), "quad_pattern")
+        return jr, jc, hr, hc
+
+    def quad_kkt(self, N, bnd=1):
+        s = self.quad_sizes(N, bnd)
+        jr, jc, hr, hc = self.quad_pattern(N, bnd)
+        rowptr = np.empty(s["dim"] + 1, np.int32)
+        colind = np.empty(s["nnzh"] + s["nnzj"] + s["dim"], np.int32)
+        perm_j = np.empty(s["nnzj"], np.int32)
+        perm_h = np.empty(s["nnzh"], np.int32)
+        nnzk = np.zeros(1, np.int64)
+        _check(self.L.orc_kkt_generic(s["nvar"], s["ncon"], s["nnzj"], s["nnzh"], _p(jr), _p(jc),
+                                      _p(hr), _p(hc), _p(rowptr), _p(colind), _p(perm_j),
+                                      _p(perm_h), _p(nnzk)), "kkt_generic")
+        return rowptr, colind[: int(nnzk[0])].copy(), perm_j, perm_h
+
+    def quad_obj(self, q):
+        out = np.zeros(2)
+        _check(self.L.orc_quad_obj(q.N, q.r, _p(_d(q.z)), _p(out)), "quad_obj")
+        return float(out[0]), float(out[1])
+
+    def quad_grad(self, q):
+        g, mu = np.empty(len(q.z)), np.empty(len(q.z))
+        _check(self.L.orc_quad_grad(q.N, q.r, _p(_d(q.z)), _p(g), _p(mu)), "quad_grad")
+        return g, mu
+
+    def quad_cons(self, q):
+        s = self.quad_sizes(q.N, q.bnd)
+        c, mu = np.empty(s["ncon"]), np.empty(s["ncon"])
+        _check(self.L.orc_quad_cons(q.N, q.bnd, q.g, _p(_d(q.z)), _p(c), _p(mu)), "quad_cons")
+        return c, mu
+
+    def quad_jac(self, q):
+        s = self.quad_sizes(q.N, q.bnd)
+        v, mu = np.empty(s["nnzj"]), np.empty(s["nnzj"])
+        _check(self.L.orc_quad_jac(q.N, q.bnd, _p(_d(q.z)), _p(v), _p(mu)), "quad_jac")
+        return v, mu
+
+    def quad_hess(self, q, sigma=None, y=None):
+        s = self.quad_sizes(q.N, q.bnd)
+        v, mu = np.empty(s["nnzh"]), np.empty(s["nnzh"])
+        sigma = q.sigma if sigma is None else sigma
+        y = q.y if y is None else y
+        _check(self.L.orc_quad_hess(q.N, q.r, _p(_d(q.z)), _p(_d(y)), float(sigma), _p(v), _p(mu)),
+               "quad_hess")
+        return v, mu
+
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
@@ -339,6 +404,14 @@ jac_ex = DEFAULT.jac_ex
 hess_ex = DEFAULT.hess_ex
 pattern_ex = DEFAULT.pattern_ex
 kkt_ex = DEFAULT.kkt_ex
+quad_sizes = DEFAULT.quad_sizes
+quad_pattern = DEFAULT.quad_pattern
+quad_kkt = DEFAULT.quad_kkt
+quad_obj = DEFAULT.quad_obj
+quad_grad = DEFAULT.quad_grad
+quad_cons = DEFAULT.quad_cons
+quad_jac = DEFAULT.quad_jac
+quad_hess = DEFAULT.quad_hess
 
 
 def build_variant(src_text: str, out_path: str) -> "Oracle":

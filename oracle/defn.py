@@ -145,3 +145,87 @@ def lagrangian_ex(z, y, sigma, N, n, m, A, B, gamma, q, r, scheme, bnd, sin=math
     for a, b in zip(y, c):
         acc = acc + a * b
     return acc
+
+
+# ---- the quadrotor model (paper Appendix A) -----------------------------------
+#
+# States x1..x9 are indices 0..8 (positions x1, x3, x5; velocities x2, x4, x6;
+# Euler angles x7, x8, x9), controls u1..u4 are indices 0..3.  Transcribed with
+# the trapezoidal scheme of Sec. 5 on t in [0, 1]; the cost is one half of the
+# integral of the tracking error of x1, x3, x5 against sin(2 pi t),
+# 2 sin(4 pi t) and 2 t, plus the squared angles and r times the squared
+# controls.  ``fn`` supplies sin, cos, tan and pi (math, cmath, mpmath or sympy).
+
+def quad_unpack(z, N):
+    xs = [[z[j * (N + 1) + k] for j in range(9)] for k in range(N + 1)]
+    off = 9 * (N + 1)
+    us = [[z[off + l * (N + 1) + k] for l in range(4)] for k in range(N + 1)]
+    return xs, us
+
+
+def quad_rhs(x, u, g, fn=math):
+    """The nine right-hand sides of the quadrotor ODE, as the paper states them."""
+    s7, c7 = fn.sin(x[6]), fn.cos(x[6])
+    s8, c8, t8 = fn.sin(x[7]), fn.cos(x[7]), fn.tan(x[7])
+    s9, c9 = fn.sin(x[8]), fn.cos(x[8])
+    return [
+        x[1],
+        u[0] * c7 * s8 * c9 + u[0] * s7 * s9,
+        x[3],
+        u[0] * c7 * s8 * s9 - u[0] * s7 * c9,
+        x[5],
+        u[0] * c7 * c8 - g,
+        u[1] * c7 / c8 + u[2] * s7 / c8,
+        -u[1] * s7 + u[2] * c7,
+        u[1] * c7 * t8 + u[2] * s7 * t8 + u[3],
+    ]
+
+
+def quad_running_cost(t, x, u, r, fn=math):
+    """Integrand of the quadrotor cost, including its factor one half."""
+    d1 = fn.sin(2 * fn.pi * t)
+    d3 = 2 * fn.sin(4 * fn.pi * t)
+    d5 = 2 * t
+    acc = (x[0] - d1) ** 2 + (x[2] - d3) ** 2 + (x[4] - d5) ** 2
+    acc = acc + x[6] ** 2 + x[7] ** 2 + x[8] ** 2
+    acc = acc + r * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2 + u[3] ** 2)
+    return acc / 2
+
+
+def quad_objective(z, N, r, fn=math, dt=None):
+    """Trapezoidal cost: end nodes weighted dt/2, interior nodes dt; t_k = k dt."""
+    dt = 1.0 / N if dt is None else dt
+    xs, us = quad_unpack(z, N)
+    ends = 0
+    for k in (0, N):
+        ends = ends + dt * quad_running_cost(k * dt, xs[k], us[k], r, fn) / 2
+    inner = 0
+    for k in range(1, N):
+        inner = inner + dt * quad_running_cost(k * dt, xs[k], us[k], r, fn)
+    return ends + inner
+
+
+def quad_constraints(z, N, g, bnd, fn=math, dt=None):
+    """Trapezoidal defects (row i N + k), then the boundary rows X_i0 (bnd >= 1)
+    and X_iN (bnd == 2)."""
+    dt = 1.0 / N if dt is None else dt
+    xs, us = quad_unpack(z, N)
+    fs = [quad_rhs(xs[k], us[k], g, fn) for k in range(N + 1)]
+    c = []
+    for i in range(9):
+        for k in range(N):
+            c.append((xs[k + 1][i] - xs[k][i]) - dt * (fs[k][i] + fs[k + 1][i]) / 2)
+    if bnd >= 1:
+        c.extend(xs[0][i] for i in range(9))
+    if bnd == 2:
+        c.extend(xs[N][i] for i in range(9))
+    return c
+
+
+def quad_lagrangian(z, y, sigma, N, g, r, bnd, fn=math, dt=None):
+    f = quad_objective(z, N, r, fn, dt)
+    c = quad_constraints(z, N, g, bnd, fn, dt)
+    acc = sigma * f
+    for a, b in zip(y, c):
+        acc = acc + a * b
+    return acc

@@ -1183,3 +1183,449 @@ int orc_kkt_generic(int64_t nvar, int64_t ncon, int64_t nnzj, int64_t nnzh,
     free(ent);
     return rc;
 }
+
+/* ===========================================================================
+ * The quadrotor model (paper Appendix A), trapezoidal transcription (Sec. 5).
+ *
+ * Node-local variables v = 0..12: states x1..x9 are v = 0..8, controls
+ * u1..u4 are v = 9..12; every variable lives on the N+1 nodes, so the global
+ * index of v at node k is v (N+1) + k.  Defect row (i, k) is i N + k; the
+ * boundary rows X_i0 (bnd >= 1) and X_iN (bnd == 2) follow the 9 N defects.
+ *
+ * Dynamics, as the paper writes them (phi = x7, theta = x8, psi = x9):
+ *   F1 = x2, F3 = x4, F5 = x6,
+ *   F2 = u1 c7 s8 c9 + u1 s7 s9,      F4 = u1 c7 s8 s9 - u1 s7 c9,
+ *   F6 = u1 c7 c8 - g,
+ *   F7 = u2 c7 / c8 + u3 s7 / c8,     F8 = -u2 s7 + u3 c7,
+ *   F9 = u2 c7 t8 + u3 s7 t8 + u4.
+ * Cost: 1/2 integral of (x1 - sin 2 pi t)^2 + (x3 - 2 sin 4 pi t)^2
+ *   + (x5 - 2t)^2 + x7^2 + x8^2 + x9^2 + r (u1^2 + u2^2 + u3^2 + u4^2),
+ *   with the trapezoidal weights w_k and t_k = k h.
+ *
+ * Patterns (structural support of the model):
+ *   Jacobian row i holds, in ascending column order, for each variable v of
+ *   its support (x_i itself and the variables F_i depends on) the two
+ *   entries (v at node k, v at node k+1).  COO position of entry
+ *   (i, p-th support variable, side s) of interval k: (off_i + 2p + s) N + k,
+ *   off_i = 2 (support sizes of rows 0..i-1).  Boundary entries follow.
+ *   Hessian: 23 lower-triangle entries per node, in (row, col) order, at
+ *   COO position s (N+1) + k.  Every variable diagonal is listed (the KKT
+ *   needs it), including those of x2, x4, x6, whose value is zero.
+ * ======================================================================== */
+
+#define QN 9
+#define QV 13
+
+static const int q_sup_len[QN] = { 2, 5, 2, 5, 2, 4, 4, 4, 6 };
+static const int q_sup[QN][6] = {
+    { 0, 1 },                /* F1 = x2 */
+    { 1, 6, 7, 8, 9 },       /* F2(x7, x8, x9, u1) */
+    { 2, 3 },                /* F3 = x4 */
+    { 3, 6, 7, 8, 9 },       /* F4(x7, x8, x9, u1) */
+    { 4, 5 },                /* F5 = x6 */
+    { 5, 6, 7, 9 },          /* F6(x7, x8, u1) */
+    { 6, 7, 10, 11 },        /* F7(x7, x8, u2, u3) */
+    { 6, 7, 10, 11 },        /* F8(x7, u2, u3); x8 is the row's own state */
+    { 6, 7, 8, 10, 11, 12 }, /* F9(x7, x8, u2, u3, u4); x9 own state */
+};
+#define Q_NNZH_NODE 23
+static const int q_hpat[Q_NNZH_NODE][2] = {
+    { 0, 0 }, { 1, 1 }, { 2, 2 }, { 3, 3 }, { 4, 4 }, { 5, 5 }, { 6, 6 },
+    { 7, 6 }, { 7, 7 }, { 8, 6 }, { 8, 7 }, { 8, 8 },
+    { 9, 6 }, { 9, 7 }, { 9, 8 }, { 9, 9 },
+    { 10, 6 }, { 10, 7 }, { 10, 10 },
+    { 11, 6 }, { 11, 7 }, { 11, 11 },
+    { 12, 12 },
+};
+
+static int q_slots_per_interval(void)
+{
+    int t = 0;
+    for (int i = 0; i < QN; i++) t += 2 * q_sup_len[i];
+    return t;
+}
+
+/* out = {nvar, ncon, nnzj, nnzh, dim} */
+int orc_quad_sizes(int64_t N, int bnd, int64_t *out)
+{
+    if (N < 1 || bnd < 0 || bnd > 2 || !out) return ORC_BAD;
+    out[0] = (int64_t)QV * (N + 1);
+    out[1] = (int64_t)QN * N + (int64_t)QN * bnd;
+    out[2] = (int64_t)q_slots_per_interval() * N + (int64_t)QN * bnd;
+    out[3] = (int64_t)Q_NNZH_NODE * (N + 1);
+    out[4] = out[0] + out[1];
+    return ORC_OK;
+}
+
+int orc_quad_pattern(int64_t N, int bnd, int32_t *jrow, int32_t *jcol, int32_t *hrow, int32_t *hcol)
+{
+    if (N < 1 || bnd < 0 || bnd > 2) return ORC_BAD;
+    int64_t N1 = N + 1;
+    if (jrow && jcol) {
+        int64_t off = 0;
+        for (int i = 0; i < QN; i++) {
+            for (int p = 0; p < q_sup_len[i]; p++)
+                for (int s = 0; s < 2; s++) {
+                    int64_t slot = off + 2 * p + s;
+                    for (int64_t k = 0; k < N; k++) {
+                        jrow[slot * N + k] = (int32_t)((int64_t)i * N + k);
+                        jcol[slot * N + k] = (int32_t)((int64_t)q_sup[i][p] * N1 + k + s);
+                    }
+                }
+            off += 2 * q_sup_len[i];
+        }
+        int64_t e0 = off * N;
+        for (int b = 0; b < QN * bnd; b++) {
+            jrow[e0 + b] = (int32_t)((int64_t)QN * N + b);
+            jcol[e0 + b] = (int32_t)((int64_t)(b % QN) * N1 + (b < QN ? 0 : N));
+        }
+    }
+    if (hrow && hcol)
+        for (int s = 0; s < Q_NNZH_NODE; s++)
+            for (int64_t k = 0; k < N1; k++) {
+                hrow[s * N1 + k] = (int32_t)((int64_t)q_hpat[s][0] * N1 + k);
+                hcol[s * N1 + k] = (int32_t)((int64_t)q_hpat[s][1] * N1 + k);
+            }
+    return ORC_OK;
+}
+
+static void q_node(int64_t N, const double *z, int64_t k, double *x, double *u)
+{
+    for (int j = 0; j < 9; j++) x[j] = z[(int64_t)j * (N + 1) + k];
+    for (int l = 0; l < 4; l++) u[l] = z[(int64_t)(9 + l) * (N + 1) + k];
+}
+
+typedef struct { double s7, c7, s8, c8, t8, s9, c9; } qtrig_t;
+
+static qtrig_t q_trig(const double *x)
+{
+    qtrig_t t = { sin(x[6]), cos(x[6]), sin(x[7]), cos(x[7]), tan(x[7]), sin(x[8]), cos(x[8]) };
+    return t;
+}
+
+/* F (9 values) and the magnitude of each (sum of |terms|). */
+static void q_rhs(const double *x, const double *u, double g, double *F, double *Fa)
+{
+    qtrig_t t = q_trig(x);
+    double a, b;
+    F[0] = x[1];
+    Fa[0] = fabs(x[1]);
+    a = u[0] * t.c7 * t.s8 * t.c9; b = u[0] * t.s7 * t.s9;
+    F[1] = a + b; Fa[1] = fabs(a) + fabs(b);
+    F[2] = x[3];
+    Fa[2] = fabs(x[3]);
+    a = u[0] * t.c7 * t.s8 * t.s9; b = u[0] * t.s7 * t.c9;
+    F[3] = a - b; Fa[3] = fabs(a) + fabs(b);
+    F[4] = x[5];
+    Fa[4] = fabs(x[5]);
+    a = u[0] * t.c7 * t.c8;
+    F[5] = a - g; Fa[5] = fabs(a) + fabs(g);
+    a = u[1] * t.c7 / t.c8; b = u[2] * t.s7 / t.c8;
+    F[6] = a + b; Fa[6] = fabs(a) + fabs(b);
+    a = -u[1] * t.s7; b = u[2] * t.c7;
+    F[7] = a + b; Fa[7] = fabs(a) + fabs(b);
+    double c;
+    a = u[1] * t.c7 * t.t8; b = u[2] * t.s7 * t.t8; c = u[3];
+    F[8] = a + b + c; Fa[8] = fabs(a) + fabs(b) + fabs(c);
+}
+
+/* Dense first partials D[i][v] = dF_i/dv, each differentiated term by term
+ * from the expressions above, and their magnitudes. */
+static void q_d1(const double *x, const double *u, double D[QN][QV], double Da[QN][QV])
+{
+    qtrig_t t = q_trig(x);
+    double sec2 = 1.0 / (t.c8 * t.c8);
+    memset(D, 0, sizeof(double) * QN * QV);
+    memset(Da, 0, sizeof(double) * QN * QV);
+#define SET1(i, v, A) do { D[i][v] = (A); Da[i][v] = fabs(A); } while (0)
+#define SET2(i, v, A, B) do { double a_ = (A), b_ = (B); D[i][v] = a_ + b_; Da[i][v] = fabs(a_) + fabs(b_); } while (0)
+    SET1(0, 1, 1.0);
+    /* F2 = u1 c7 s8 c9 + u1 s7 s9 */
+    SET2(1, 6, -u[0] * t.s7 * t.s8 * t.c9, u[0] * t.c7 * t.s9);
+    SET1(1, 7, u[0] * t.c7 * t.c8 * t.c9);
+    SET2(1, 8, -u[0] * t.c7 * t.s8 * t.s9, u[0] * t.s7 * t.c9);
+    SET2(1, 9, t.c7 * t.s8 * t.c9, t.s7 * t.s9);
+    SET1(2, 3, 1.0);
+    /* F4 = u1 c7 s8 s9 - u1 s7 c9 */
+    SET2(3, 6, -u[0] * t.s7 * t.s8 * t.s9, -u[0] * t.c7 * t.c9);
+    SET1(3, 7, u[0] * t.c7 * t.c8 * t.s9);
+    SET2(3, 8, u[0] * t.c7 * t.s8 * t.c9, u[0] * t.s7 * t.s9);
+    SET2(3, 9, t.c7 * t.s8 * t.s9, -t.s7 * t.c9);
+    SET1(4, 5, 1.0);
+    /* F6 = u1 c7 c8 - g */
+    SET1(5, 6, -u[0] * t.s7 * t.c8);
+    SET1(5, 7, -u[0] * t.c7 * t.s8);
+    SET1(5, 9, t.c7 * t.c8);
+    /* F7 = u2 c7 / c8 + u3 s7 / c8;  d(1/c8)/dx8 = s8 / c8^2 */
+    SET2(6, 6, -u[1] * t.s7 / t.c8, u[2] * t.c7 / t.c8);
+    SET2(6, 7, u[1] * t.c7 * t.s8 * sec2, u[2] * t.s7 * t.s8 * sec2);
+    SET1(6, 10, t.c7 / t.c8);
+    SET1(6, 11, t.s7 / t.c8);
+    /* F8 = -u2 s7 + u3 c7 */
+    SET2(7, 6, -u[1] * t.c7, -u[2] * t.s7);
+    SET1(7, 10, -t.s7);
+    SET1(7, 11, t.c7);
+    /* F9 = u2 c7 t8 + u3 s7 t8 + u4;  d(t8)/dx8 = 1 / c8^2 */
+    SET2(8, 6, -u[1] * t.s7 * t.t8, u[2] * t.c7 * t.t8);
+    SET2(8, 7, u[1] * t.c7 * sec2, u[2] * t.s7 * sec2);
+    SET1(8, 10, t.c7 * t.t8);
+    SET1(8, 11, t.s7 * t.t8);
+    SET1(8, 12, 1.0);
+#undef SET1
+#undef SET2
+}
+
+/* Dense second partials W[i][a][b] (both triangles) and magnitudes. */
+static void q_d2(const double *x, const double *u, double W[QN][QV][QV], double Wa[QN][QV][QV])
+{
+    qtrig_t t = q_trig(x);
+    double c8 = t.c8, s8 = t.s8;
+    double sec2 = 1.0 / (c8 * c8);
+    /* d^2(1/c8)/dx8^2 = (1 + s8^2) / c8^3,  d^2(t8)/dx8^2 = 2 s8 / c8^3 */
+    double dsec2 = (1.0 + s8 * s8) / (c8 * c8 * c8);
+    double dtan2 = 2.0 * s8 / (c8 * c8 * c8);
+    memset(W, 0, sizeof(double) * QN * QV * QV);
+    memset(Wa, 0, sizeof(double) * QN * QV * QV);
+#define S1(i, a, b, A) do { double v_ = (A); W[i][a][b] = v_; W[i][b][a] = v_; \
+        Wa[i][a][b] = fabs(v_); Wa[i][b][a] = fabs(v_); } while (0)
+#define S2(i, a, b, A, B) do { double a_ = (A), b_ = (B); W[i][a][b] = a_ + b_; W[i][b][a] = a_ + b_; \
+        Wa[i][a][b] = fabs(a_) + fabs(b_); Wa[i][b][a] = fabs(a_) + fabs(b_); } while (0)
+    /* F2 = u1 c7 s8 c9 + u1 s7 s9 */
+    S2(1, 6, 6, -u[0] * t.c7 * t.s8 * t.c9, -u[0] * t.s7 * t.s9);
+    S1(1, 6, 7, -u[0] * t.s7 * t.c8 * t.c9);
+    S2(1, 6, 8, u[0] * t.s7 * t.s8 * t.s9, u[0] * t.c7 * t.c9);
+    S1(1, 7, 7, -u[0] * t.c7 * t.s8 * t.c9);
+    S1(1, 7, 8, -u[0] * t.c7 * t.c8 * t.s9);
+    S2(1, 8, 8, -u[0] * t.c7 * t.s8 * t.c9, -u[0] * t.s7 * t.s9);
+    S2(1, 9, 6, -t.s7 * t.s8 * t.c9, t.c7 * t.s9);
+    S1(1, 9, 7, t.c7 * t.c8 * t.c9);
+    S2(1, 9, 8, -t.c7 * t.s8 * t.s9, t.s7 * t.c9);
+    /* F4 = u1 c7 s8 s9 - u1 s7 c9 */
+    S2(3, 6, 6, -u[0] * t.c7 * t.s8 * t.s9, u[0] * t.s7 * t.c9);
+    S1(3, 6, 7, -u[0] * t.s7 * t.c8 * t.s9);
+    S2(3, 6, 8, -u[0] * t.s7 * t.s8 * t.c9, u[0] * t.c7 * t.s9);
+    S1(3, 7, 7, -u[0] * t.c7 * t.s8 * t.s9);
+    S1(3, 7, 8, u[0] * t.c7 * t.c8 * t.c9);
+    S2(3, 8, 8, -u[0] * t.c7 * t.s8 * t.s9, u[0] * t.s7 * t.c9);
+    S2(3, 9, 6, -t.s7 * t.s8 * t.s9, -t.c7 * t.c9);
+    S1(3, 9, 7, t.c7 * t.c8 * t.s9);
+    S2(3, 9, 8, t.c7 * t.s8 * t.c9, t.s7 * t.s9);
+    /* F6 = u1 c7 c8 - g */
+    S1(5, 6, 6, -u[0] * t.c7 * t.c8);
+    S1(5, 6, 7, u[0] * t.s7 * t.s8);
+    S1(5, 7, 7, -u[0] * t.c7 * t.c8);
+    S1(5, 9, 6, -t.s7 * t.c8);
+    S1(5, 9, 7, -t.c7 * t.s8);
+    /* F7 = u2 c7 / c8 + u3 s7 / c8 */
+    S2(6, 6, 6, -u[1] * t.c7 / c8, -u[2] * t.s7 / c8);
+    S2(6, 6, 7, -u[1] * t.s7 * s8 * sec2, u[2] * t.c7 * s8 * sec2);
+    S2(6, 7, 7, u[1] * t.c7 * dsec2, u[2] * t.s7 * dsec2);
+    S1(6, 10, 6, -t.s7 / c8);
+    S1(6, 10, 7, t.c7 * s8 * sec2);
+    S1(6, 11, 6, t.c7 / c8);
+    S1(6, 11, 7, t.s7 * s8 * sec2);
+    /* F8 = -u2 s7 + u3 c7 */
+    S2(7, 6, 6, u[1] * t.s7, -u[2] * t.c7);
+    S1(7, 10, 6, -t.c7);
+    S1(7, 11, 6, -t.s7);
+    /* F9 = u2 c7 t8 + u3 s7 t8 + u4 */
+    S2(8, 6, 6, -u[1] * t.c7 * t.t8, -u[2] * t.s7 * t.t8);
+    S2(8, 6, 7, -u[1] * t.s7 * sec2, u[2] * t.c7 * sec2);
+    S2(8, 7, 7, u[1] * t.c7 * dtan2, u[2] * t.s7 * dtan2);
+    S1(8, 10, 6, -t.s7 * t.t8);
+    S1(8, 10, 7, t.c7 * sec2);
+    S1(8, 11, 6, t.c7 * t.t8);
+    S1(8, 11, 7, t.s7 * sec2);
+#undef S1
+#undef S2
+}
+
+/* Reference trajectory of the tracked states at time t: (x1, x3, x5) targets. */
+#define Q_PI 3.14159265358979323846
+
+static void q_refs(double t, double *d)
+{
+    d[0] = sin(2.0 * Q_PI * t);
+    d[1] = 2.0 * sin(4.0 * Q_PI * t);
+    d[2] = 2.0 * t;
+}
+
+/* out[0] = f, out[1] = mu(f); compensated sums in fixed chunks (as orc_obj). */
+int orc_quad_obj(int64_t N, double r, const double *z, double *out)
+{
+    if (N < 1 || !z || !out) return ORC_BAD;
+    int64_t N1 = N + 1;
+    double h = 1.0 / (double)N;
+    int64_t nch = (N1 + OBJ_CHUNK - 1) / OBJ_CHUNK;
+    acc_t *part = (acc_t *)calloc((size_t)nch, sizeof(acc_t));
+    double *pmu = (double *)calloc((size_t)nch, sizeof(double));
+    if (!part || !pmu) { free(part); free(pmu); return ORC_BAD; }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nch; c++) {
+        acc_t a = { 0.0, 0.0 };
+        double mu = 0.0;
+        int64_t k1 = (c + 1) * OBJ_CHUNK < N1 ? (c + 1) * OBJ_CHUNK : N1;
+        for (int64_t k = c * OBJ_CHUNK; k < k1; k++) {
+            double x[9], u[4], d[3];
+            q_node(N, z, k, x, u);
+            q_refs((double)k * h, d);
+            double e0 = x[0] - d[0], e2 = x[2] - d[1], e4 = x[4] - d[2];
+            double L = e0 * e0 + e2 * e2 + e4 * e4 + x[6] * x[6] + x[7] * x[7] + x[8] * x[8]
+                       + r * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
+            double La = (fabs(x[0]) + fabs(d[0])) * (fabs(x[0]) + fabs(d[0]))
+                        + (fabs(x[2]) + fabs(d[1])) * (fabs(x[2]) + fabs(d[1]))
+                        + (fabs(x[4]) + fabs(d[2])) * (fabs(x[4]) + fabs(d[2]))
+                        + x[6] * x[6] + x[7] * x[7] + x[8] * x[8]
+                        + fabs(r) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
+            double w = weight(N, k);
+            acc_add(&a, w * (0.5 * L));
+            mu += w * 0.5 * La;
+        }
+        part[c] = a;
+        pmu[c] = mu;
+    }
+    acc_t tot = { 0.0, 0.0 };
+    double mu = 0.0;
+    for (int64_t c = 0; c < nch; c++) {
+        acc_add(&tot, part[c].s);
+        acc_add(&tot, part[c].c);
+        mu += pmu[c];
+    }
+    out[0] = tot.s + tot.c;
+    out[1] = mu;
+    free(part);
+    free(pmu);
+    return ORC_OK;
+}
+
+/* Gradient of the cost: w_k (x - target) for x1, x3, x5; w_k x for x7..x9;
+ * w_k r u for the controls; zero for x2, x4, x6. */
+int orc_quad_grad(int64_t N, double r, const double *z, double *g, double *mu)
+{
+    if (N < 1 || !z || !g || !mu) return ORC_BAD;
+    int64_t N1 = N + 1;
+    double h = 1.0 / (double)N;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < N1; k++) {
+        double x[9], u[4], d[3];
+        q_node(N, z, k, x, u);
+        q_refs((double)k * h, d);
+        double w = weight(N, k);
+        for (int v = 0; v < QV; v++) { g[v * N1 + k] = 0.0; mu[v * N1 + k] = 0.0; }
+        for (int q = 0; q < 3; q++) {
+            int v = 2 * q;
+            g[v * N1 + k] = w * (x[v] - d[q]);
+            mu[v * N1 + k] = w * (fabs(x[v]) + fabs(d[q]));
+        }
+        for (int v = 6; v < 9; v++) {
+            g[v * N1 + k] = w * x[v];
+            mu[v * N1 + k] = fabs(w * x[v]);
+        }
+        for (int l = 0; l < 4; l++) {
+            g[(9 + l) * N1 + k] = w * r * u[l];
+            mu[(9 + l) * N1 + k] = fabs(w * r * u[l]);
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_quad_cons(int64_t N, int bnd, double g, const double *z, double *c, double *mu)
+{
+    if (N < 1 || bnd < 0 || bnd > 2 || !z || !c || !mu) return ORC_BAD;
+    double hh = 0.5 * (1.0 / (double)N);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < N; k++) {
+        double x0[9], u0[4], x1[9], u1[4], F0[9], Fa0[9], F1[9], Fa1[9];
+        q_node(N, z, k, x0, u0);
+        q_node(N, z, k + 1, x1, u1);
+        q_rhs(x0, u0, g, F0, Fa0);
+        q_rhs(x1, u1, g, F1, Fa1);
+        for (int i = 0; i < QN; i++) {
+            c[(int64_t)i * N + k] = (x1[i] - x0[i]) - hh * (F0[i] + F1[i]);
+            mu[(int64_t)i * N + k] = fabs(x1[i]) + fabs(x0[i]) + hh * (Fa0[i] + Fa1[i]);
+        }
+    }
+    for (int b = 0; b < QN * bnd; b++) {
+        double v = z[(int64_t)(b % QN) * (N + 1) + (b < QN ? 0 : N)];
+        c[(int64_t)QN * N + b] = v;
+        mu[(int64_t)QN * N + b] = fabs(v);
+    }
+    return ORC_OK;
+}
+
+int orc_quad_jac(int64_t N, int bnd, const double *z, double *jac, double *mu)
+{
+    if (N < 1 || bnd < 0 || bnd > 2 || !z || !jac || !mu) return ORC_BAD;
+    double hh = 0.5 * (1.0 / (double)N);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < N; k++) {
+        double x[2][9], u[2][4];
+        double D[2][QN][QV], Da[2][QN][QV];
+        for (int s = 0; s < 2; s++) {
+            q_node(N, z, k + s, x[s], u[s]);
+            q_d1(x[s], u[s], D[s], Da[s]);
+        }
+        int64_t off = 0;
+        for (int i = 0; i < QN; i++) {
+            for (int p = 0; p < q_sup_len[i]; p++) {
+                int v = q_sup[i][p];
+                for (int s = 0; s < 2; s++) {
+                    double id = v == i ? (s ? 1.0 : -1.0) : 0.0;
+                    int64_t e = (off + 2 * p + s) * N + k;
+                    jac[e] = id - hh * D[s][i][v];
+                    mu[e] = fabs(id) + hh * Da[s][i][v];
+                }
+            }
+            off += 2 * q_sup_len[i];
+        }
+    }
+    int64_t e0 = (int64_t)q_slots_per_interval() * N;
+    for (int b = 0; b < QN * bnd; b++) {
+        jac[e0 + b] = 1.0;
+        mu[e0 + b] = 1.0;
+    }
+    return ORC_OK;
+}
+
+/* Hessian of L = sigma f + y^T c on the 23-entry node pattern:
+ * sigma w_k C_ab - hh sum_i ytilde_ik d2F_i/(da db), where C is the cost's
+ * constant second derivative (1 for x1, x3, x5, x7, x8, x9; r for controls)
+ * and ytilde_ik = y_{i,k-1} [k >= 1] + y_{ik} [k < N].  Boundary rows are
+ * linear and add nothing. */
+int orc_quad_hess(int64_t N, double r, const double *z, const double *y, double sigma,
+                  double *hess, double *mu)
+{
+    if (N < 1 || !z || !y || !hess || !mu) return ORC_BAD;
+    int64_t N1 = N + 1;
+    double hh = 0.5 * (1.0 / (double)N);
+    static const int tracked[QV] = { 1, 0, 1, 0, 1, 0, 1, 1, 1, 0, 0, 0, 0 };
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < N1; k++) {
+        double x[9], u[4], yt[QN];
+        double (*W)[QV][QV] = malloc(sizeof(double) * QN * QV * QV);
+        double (*Wa)[QV][QV] = malloc(sizeof(double) * QN * QV * QV);
+        q_node(N, z, k, x, u);
+        q_d2(x, u, W, Wa);
+        for (int i = 0; i < QN; i++) {
+            yt[i] = 0.0;
+            if (k >= 1) yt[i] += y[(int64_t)i * N + k - 1];
+            if (k < N) yt[i] += y[(int64_t)i * N + k];
+        }
+        double w = weight(N, k);
+        for (int s = 0; s < Q_NNZH_NODE; s++) {
+            int a = q_hpat[s][0], b = q_hpat[s][1];
+            double cst = 0.0;
+            if (a == b) cst = a < 9 ? (tracked[a] ? 1.0 : 0.0) : r;
+            double v = sigma * w * cst, m = fabs(sigma * w * cst);
+            for (int i = 0; i < QN; i++) {
+                v += -hh * yt[i] * W[i][a][b];
+                m += hh * fabs(yt[i]) * Wa[i][a][b];
+            }
+            hess[s * N1 + k] = v;
+            mu[s * N1 + k] = m;
+        }
+        free(W);
+        free(Wa);
+    }
+    return ORC_OK;
+}

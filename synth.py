@@ -125,3 +125,57 @@ def make_batch(count: int = 512, n: int = 6, m: int = 3, seed: int = 0, Ns=None)
 def pack(insts):
     """Packed z and y of a list of instances (instance after instance)."""
     return (np.concatenate([i.z for i in insts]), np.concatenate([i.y for i in insts]))
+
+
+# ---- quadrotor-shaped workload ------------------------------------------------
+#
+# The paper's quadrotor benchmark (Appendix A): 9 states (positions x1, x3, x5,
+# velocities x2, x4, x6, Euler angles x7, x8, x9), 4 controls (thrust u1, body
+# rates u2, u3, u4), on t in [0, 1] with g = 9.8 and control weight r = 0.1,
+# and the initial state fixed.  Only the evaluation point is drawn here:
+#     positions and velocities ~ N(0, 1), shape (6, N + 1)
+#     angles ~ U(-0.5, 0.5) rad, shape (3, N + 1)   (|x8| < pi/2 keeps 1/cos finite)
+#     thrust ~ U(5, 15), shape (1, N + 1)           (around hover, u1 = g)
+#     rates ~ U(-1, 1), shape (3, N + 1)
+#     y ~ N(0, 1), 9 N defect multipliers then 9 per boundary group
+# drawn in that order from ``default_rng(seed)``; sigma = 1.
+
+QUAD_N, QUAD_M = 9, 4
+QUAD_G, QUAD_R = 9.8, 0.1
+
+
+@dataclass
+class QuadInstance:
+    N: int
+    z: np.ndarray    # [X (9, N+1) | U (4, N+1)], row-major blocks
+    y: np.ndarray    # 9 N defect multipliers, then 9 per boundary group
+    sigma: float
+    g: float = QUAD_G
+    r: float = QUAD_R
+    bnd: int = 1     # boundary rows: 0 none, 1 initial state (the paper's model), 2 initial and final
+    n: int = QUAD_N
+    m: int = QUAD_M
+
+    @property
+    def X(self) -> np.ndarray:
+        return self.z[: 9 * (self.N + 1)].reshape(9, self.N + 1)
+
+    @property
+    def U(self) -> np.ndarray:
+        return self.z[9 * (self.N + 1):].reshape(4, self.N + 1)
+
+
+def make_quadrotor(N: int, seed=0, bnd: int = 1) -> QuadInstance:
+    """One evaluation point of the quadrotor-shaped workload (draw order above)."""
+    rng = np.random.default_rng(seed)
+    pv = rng.normal(0.0, 1.0, (6, N + 1))
+    ang = rng.uniform(-0.5, 0.5, (3, N + 1))
+    thrust = rng.uniform(5.0, 15.0, (1, N + 1))
+    rates = rng.uniform(-1.0, 1.0, (3, N + 1))
+    y = rng.normal(0.0, 1.0, 9 * N + 9 * bnd)
+    z = np.concatenate([pv.ravel(), ang.ravel(), thrust.ravel(), rates.ravel()])
+    return QuadInstance(N=N, z=np.ascontiguousarray(z), y=np.ascontiguousarray(y), sigma=1.0, bnd=bnd)
+
+
+QUAD_LARGE = 1_000_000   # quadrotor roofline workload
+QUAD_PAPER = 200_000     # the paper's largest quadrotor grid

@@ -11,6 +11,7 @@ import oracle
 from tests import test_oracle_diff_pins as D
 from tests import test_oracle_ex_pins as E
 from tests import test_oracle_pins as P
+from tests import test_oracle_quad_pins as Q
 
 # (name, text in ocp_oracle.c, replacement)
 MUTATIONS = [
@@ -63,6 +64,24 @@ MUTATIONS = [
     ("euler hessian factor", "double fac = scheme == 0 ? 0.5 * h : h;", "double fac = 0.5 * h;"),
     ("final boundary node", "int64_t node = b < n ? 0 : N;", "int64_t node = 0;"),
     ("final boundary column", "(b % n) * (N + 1) + (b < n ? 0 : N));", "(b % n) * (N + 1) + (b < n ? 0 : N - 1));"),
+    ("quad F4 sign", "F[3] = a - b;", "F[3] = a + b;"),
+    ("quad F7 roll term", "a = u[1] * t.c7 / t.c8; b = u[2] * t.s7 / t.c8;", "a = u[1] * t.c7 / t.c8; b = u[2] * t.s7 * t.c8;"),
+    ("quad gravity sign", "F[5] = a - g;", "F[5] = a + g;"),
+    ("quad yaw rate partner", "a = u[1] * t.c7 * t.t8; b = u[2] * t.s7 * t.t8; c = u[3];", "a = u[1] * t.c7 * t.t8; b = u[2] * t.s7 * t.t8; c = u[2];"),
+    ("quad jac pitch partial", "SET1(1, 7, u[0] * t.c7 * t.c8 * t.c9);", "SET1(1, 7, u[0] * t.c7 * t.c8 * t.s9);"),
+    ("quad jac sec^2", "SET2(8, 7, u[1] * t.c7 * sec2, u[2] * t.s7 * sec2);", "SET2(8, 7, u[1] * t.c7 / t.c8, u[2] * t.s7 * sec2);"),
+    ("quad jac thrust column", "SET2(3, 9, t.c7 * t.s8 * t.s9, -t.s7 * t.c9);", "SET2(3, 9, t.c7 * t.s8 * t.s9, t.s7 * t.c9);"),
+    ("quad support of F8", "{ 6, 7, 10, 11 },        /* F8", "{ 6, 7, 9, 11 },        /* F8"),
+    ("quad jac identity side", "double id = v == i ? (s ? 1.0 : -1.0) : 0.0;", "double id = v == i ? (s ? -1.0 : 1.0) : 0.0;"),
+    ("quad hess second of 1/cos", "double dsec2 = (1.0 + s8 * s8) / (c8 * c8 * c8);", "double dsec2 = (1.0 - s8 * s8) / (c8 * c8 * c8);"),
+    ("quad hess cross term sign", "S1(5, 6, 7, u[0] * t.s7 * t.s8);", "S1(5, 6, 7, -u[0] * t.s7 * t.s8);"),
+    ("quad hess node multiplier", "if (k >= 1) yt[i] += y[(int64_t)i * N + k - 1];", "if (k >= 1) yt[i] += y[(int64_t)i * N + k];"),
+    ("quad hess pattern entry", "{ 10, 6 }, { 10, 7 }, { 10, 10 },", "{ 10, 6 }, { 10, 8 }, { 10, 10 },"),
+    ("quad tracked states", "{ 1, 0, 1, 0, 1, 0, 1, 1, 1, 0, 0, 0, 0 }", "{ 1, 1, 0, 0, 1, 0, 1, 1, 1, 0, 0, 0, 0 }"),
+    ("quad reference amplitude", "d[1] = 2.0 * sin(4.0 * Q_PI * t);", "d[1] = sin(4.0 * Q_PI * t);"),
+    ("quad reference ramp", "d[2] = 2.0 * t;", "d[2] = t;"),
+    ("quad cost half", "acc_add(&a, w * (0.5 * L));", "acc_add(&a, w * L);"),
+    ("quad boundary node", "double v = z[(int64_t)(b % QN) * (N + 1) + (b < QN ? 0 : N)];", "double v = z[(int64_t)(b % QN) * (N + 1) + (b < QN ? 0 : N - 1)];"),
 ]
 
 # Pins run against each mutant: (test function, arguments after the oracle).
@@ -98,6 +117,16 @@ PINS = [
     (E.test_kkt_generic_matches_scipy, (5, 3, 2, 1, 2)),
     (E.test_euler_linear_quadratic_case, (2,)),
     (E.test_trapezoidal_branch_equals_pinned_functions, (9, 2, 1)),
+    (Q.test_sizes_and_pattern, ()),
+    (Q.test_hover_has_zero_defects_exactly, ()),
+    (Q.test_defects_of_exact_trajectory_are_third_order, ()),
+    (Q.test_objective_closed_form_at_zero, (7,)),
+    (Q.test_objective_exact_tracking, ()),
+    (Q.test_constraints_match_definition, ()),
+    (Q.test_jacobian_complex_step_and_pattern, (3, 2)),
+    (Q.test_gradient_complex_step, ()),
+    (Q.test_hessian_mixed_difference, (1, 1, 1.3)),
+    (Q.test_kkt_matches_scipy, (3, 1)),
 ]
 
 
