@@ -1,6 +1,6 @@
 """Benchmark of the evaluation path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler] [--no-quad] [--only-quad]
 
 Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
 controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
@@ -301,6 +301,62 @@ def euler(torch, ocp, synth, reps=10):
     return out
 
 
+def quadrotor(torch, ocp, synth, reps=10):
+    """The quadrotor model (68 Jacobian and 23 Hessian entries per node) with
+    the initial-state rows: a full step (obj, grad, cons, jac, hess,
+    assemble_kkt) at N = 1e6, and the same at the paper's largest grid
+    N = 2e5, each call timed with HIP events against its algorithmic bytes."""
+    out = {}
+    for tag, N in (("N1e6", synth.QUAD_LARGE), ("N2e5", synth.QUAD_PAPER)):
+        dev = torch.device("cuda", 0)
+        q = synth.make_quadrotor(N, seed=0, bnd=1)
+        prob = ocp.QuadrotorProblem.from_instance(q, dev)
+        s = prob.sizes
+        z = torch.from_numpy(q.z).to(dev)
+        y = torch.from_numpy(q.y).to(dev)
+        rowptr, _, perm_j, perm_h = ocp.quad_kkt_pattern(N, 1, colind=False)
+        pj, ph, rp = (torch.from_numpy(a).to(dev) for a in (perm_j, perm_h, rowptr))
+        f64 = dict(dtype=torch.float64, device=dev)
+        o = torch.empty(1, **f64)
+        g = torch.empty(s["nvar"], **f64)
+        c, jv, hv = torch.empty(s["ncon"], **f64), torch.empty(s["nnzj"], **f64), torch.empty(s["nnzh"], **f64)
+        kkt = torch.empty(s["nnzk"], **f64)
+        N1 = N + 1
+        # algorithmic bytes: the attitude and controls (7 per node) feed the
+        # derivatives; the Hessian also reads the six nonlinear rows' y
+        calls = {
+            "eval_obj": (lambda: prob.obj(z, out=o), 8 * 10 * N1),
+            "eval_grad": (lambda: prob.grad(z, out=g), 8 * 10 * N1 + 8 * s["nvar"]),
+            "eval_cons": (lambda: prob.cons(z, out=c), 8 * s["nvar"] + 8 * s["ncon"]),
+            "eval_jac": (lambda: prob.jac(z, out=jv), 8 * s["nnzj"] + 8 * 7 * N1),
+            "eval_hess": (lambda: prob.hess(z, y, 1.0, out=hv), 8 * s["nnzh"] + 8 * 7 * N1 + 8 * 6 * N),
+            "assemble_kkt": (lambda: prob.assemble_kkt(pj, ph, rp, jv, hv, None, out=kkt),
+                             12 * (s["nnzj"] + s["nnzh"]) + 8 * s["nnzk"] + 4 * s["ncon"]),
+        }
+        r = {"workload": f"quadrotor (paper Appendix A), trapezoidal, x(0) rows, N={N}, seed 0",
+             "nnzj": s["nnzj"], "nnzh": s["nnzh"], "nnzk": s["nnzk"]}
+        for name, (fn, nbytes) in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            r[name] = {"ms": round(ms, 4), "bytes": nbytes,
+                       "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+        r["step_ms"] = round(sum(r[k]["ms"] for k in calls), 4)
+        t = (r["eval_jac"]["ms"] + r["eval_hess"]["ms"]) * 1e-3
+        r["jac_hess_nnz_per_s"] = (s["nnzj"] + s["nnzh"]) / t
+        prob.close()
+        del pj, ph, rp, jv, hv, kkt
+        torch.cuda.empty_cache()
+        out[tag] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +369,10 @@ def main():
                     help="skip the 512-instance batched measurement (profiling runs)")
     ap.add_argument("--no-euler", action="store_true",
                     help="skip the forward-Euler measurement (profiling runs)")
+    ap.add_argument("--no-quad", action="store_true",
+                    help="skip the quadrotor measurement (profiling runs)")
+    ap.add_argument("--only-quad", action="store_true",
+                    help="run only the quadrotor measurement (profiling runs)")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the N=2e5 differentiation measurement (profiling runs)")
     ap.add_argument("--no-ipm-loop", action="store_true",
@@ -334,6 +394,10 @@ def main():
         torch.cuda.set_device(0)
         log("[bench] batched workload only")
         print(json.dumps({"batched": batched(torch, ocp, synth)}), flush=True)
+        return
+    if args.only_quad:
+        log("[bench] quadrotor workload only")
+        print(json.dumps({"quadrotor": quadrotor(torch, ocp, synth)}), flush=True)
         return
 
     N, n, m = synth.LARGE
@@ -491,6 +555,9 @@ def main():
     if not args.no_euler:
         log("[bench] forward-Euler workload")
         out["euler"] = euler(torch, ocp, synth)
+    if not args.no_quad:
+        log("[bench] quadrotor workload")
+        out["quadrotor"] = quadrotor(torch, ocp, synth)
     if not args.no_diff:
         log("[bench] differentiation workload")
         out["differentiation"] = differentiation(torch, ocp, synth)

@@ -247,6 +247,65 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
                        double *gB, double *ggamma, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * The quadrotor model of the paper's benchmark set (Appendix A), transcribed
+ * with the trapezoidal scheme (Sec. 5) on t in [0, 1], h = 1/N.
+ *
+ * States x1..x9 (node-local v = 0..8: positions x1, x3, x5, velocities x2,
+ * x4, x6, Euler angles x7, x8, x9) and controls u1..u4 (v = 9..12) all live
+ * on the N+1 nodes: z[v (N+1) + k], nvar = 13 (N+1).  Dynamics:
+ *   x1' = x2, x3' = x4, x5' = x6,
+ *   x2' = u1 (c7 s8 c9 + s7 s9), x4' = u1 (c7 s8 s9 - s7 c9), x6' = u1 c7 c8 - g,
+ *   x7' = (u2 c7 + u3 s7) / c8, x8' = -u2 s7 + u3 c7, x9' = (u2 c7 + u3 s7) t8 + u4
+ * (cj, sj, tj: cos, sin, tan of xj).  Cost: the trapezoidal sum of one half
+ * of (x1 - sin 2 pi t)^2 + (x3 - 2 sin 4 pi t)^2 + (x5 - 2t)^2 + x7^2 + x8^2
+ * + x9^2 + r |u|^2 at t_k = k h.  Defect rows i N + k as above; with
+ * `boundary` = OCP_BOUNDARY_INITIAL the 9 rows X_i0 follow (the paper fixes
+ * x(0) = 0; the target enters the solver as lcon = ucon), with
+ * OCP_BOUNDARY_INITIAL_FINAL also the 9 rows X_iN.
+ *
+ * Patterns (the structural support of the model, not a dense block):
+ *   Jacobian: row i holds two entries (node k, node k+1) per variable of its
+ *   support -- its own state and the variables its right-hand side depends
+ *   on -- in ascending column order; 68 entries per interval, slot-major:
+ *   entry t of the interval's 68 (rows 0..8 in order) sits at t N + k.
+ *   Supports: x1:{x1,x2}  x2:{x2,x7,x8,x9,u1}  x3:{x3,x4}  x4:{x4,x7,x8,x9,u1}
+ *   x5:{x5,x6}  x6:{x6,x7,x8,u1}  x7,x8:{x7,x8,u2,u3}  x9:{x7,x8,x9,u2,u3,u4}.
+ *   Boundary entries (1.0) follow at 68 N + b.
+ *   Hessian: 23 lower entries per node, sorted by (row, col) in node-local
+ *   numbering, at s (N+1) + k: the 13 diagonals (those of x2, x4, x6 are
+ *   zero, kept so every KKT diagonal is a Hessian entry), (x8,x7), (x9,x7),
+ *   (x9,x8), (u1,x7), (u1,x8), (u1,x9), (u2,x7), (u2,x8), (u3,x7), (u3,x8).
+ *   ocp_sizes_t reports T = 68 (entries per interval), S = 23, npair = 0.
+ *
+ * A handle from ocp_quad_create works with ocp_problem_sizes, ocp_eval_obj,
+ * ocp_eval_grad, ocp_eval_cons, ocp_eval_jac, ocp_eval_hess,
+ * ocp_assemble_kkt and ocp_destroy, with the arrays and layouts above.  The
+ * Lagrangian-derivative entry points and ocp_set_coefficients reject it
+ * (OCP_ERR_ARG).
+ * ------------------------------------------------------------------------- */
+
+/* Sizes of the quadrotor NLP.  Host only.  Errors: OCP_ERR_ARG (N < 1,
+ * unknown boundary), OCP_ERR_OVERFLOW. */
+int ocp_quad_sizes(int64_t N, int32_t boundary, ocp_sizes_t *out);
+
+/* Jacobian and Hessian COO patterns of the quadrotor NLP into caller-owned
+ * host arrays (nnzj, nnzh int32 each; any may be NULL to skip it). */
+int ocp_quad_pattern(int64_t N, int32_t boundary, int32_t *jrow, int32_t *jcol, int32_t *hrow,
+                     int32_t *hcol);
+
+/* Lower CSR of the quadrotor KKT matrix and the slot maps (Sec. 6 one-time
+ * host step), into caller-owned host arrays: rowptr dim+1, colind nnzk,
+ * perm_j nnzj, perm_h nnzh (any may be NULL). */
+int ocp_quad_kkt(int64_t N, int32_t boundary, int32_t *rowptr, int32_t *colind, int32_t *perm_j,
+                 int32_t *perm_h);
+
+/* Create a quadrotor handle on the current HIP device with gravity g and
+ * control weight r (the paper uses g = 9.8, r = 0.1).  Allocates only the
+ * objective's reduction workspace.  Errors: OCP_ERR_ARG (also for non-finite
+ * g or r), OCP_ERR_OVERFLOW, OCP_ERR_ALLOC, OCP_ERR_HIP. */
+int ocp_quad_create(int64_t N, int32_t boundary, double g, double r, ocp_problem **out);
+
+/* ---------------------------------------------------------------------------
  * Batches: many independent instances with their own N_b and coefficients
  * (shared n, m), evaluated together.  The paper motivates data parallelism
  * across grid nodes (Sec. 3) and real-time use; a batch extends the same

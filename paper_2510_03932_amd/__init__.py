@@ -102,6 +102,10 @@ def lib():
         L.ocp_eval_hess.argtypes = [vp, vp, vp, dbl, vp, vp]
         L.ocp_assemble_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_last_error.restype = ctypes.c_char_p
+        L.ocp_quad_sizes.argtypes = [i64, i32, ctypes.POINTER(Sizes)]
+        L.ocp_quad_pattern.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.ocp_quad_kkt.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.ocp_quad_create.argtypes = [i64, i32, dbl, dbl, ctypes.POINTER(vp)]
         L.ocp_set_coefficients.argtypes = [vp, vp, vp, vp, vp]
         L.ocp_eval_lagrangian.argtypes = [vp, vp, vp, dbl, vp, vp]
         L.ocp_eval_lag_grad.argtypes = [vp, vp, vp, dbl, vp, vp]
@@ -176,6 +180,41 @@ def kkt_pattern(N: int, n: int, m: int, rowptr=True, colind=True, perm_j=True, p
     o = _opts(scheme, boundary)
     _check(lib().ocp_build_kkt_ex(N, n, m, ctypes.byref(o), _hp(rp), _hp(ci), _hp(pj), _hp(ph)),
            "ocp_build_kkt")
+    return rp, ci, pj, ph
+
+
+# ---- the quadrotor model (paper Appendix A) ----------------------------------
+
+QUAD_G, QUAD_R = 9.8, 0.1  # the paper's gravity and control weight
+
+
+def quad_sizes(N: int, boundary: int = 1) -> dict:
+    out = Sizes()
+    _check(lib().ocp_quad_sizes(int(N), int(boundary), ctypes.byref(out)), "ocp_quad_sizes")
+    return out.as_dict()
+
+
+def quad_pattern(N: int, boundary: int = 1, jac: bool = True, hess: bool = True):
+    """Host COO patterns (jrow, jcol, hrow, hcol) of the quadrotor NLP, int32."""
+    s = quad_sizes(N, boundary)
+    jr = np.empty(s["nnzj"], np.int32) if jac else None
+    jc = np.empty(s["nnzj"], np.int32) if jac else None
+    hr = np.empty(s["nnzh"], np.int32) if hess else None
+    hc = np.empty(s["nnzh"], np.int32) if hess else None
+    _check(lib().ocp_quad_pattern(int(N), int(boundary), _hp(jr), _hp(jc), _hp(hr), _hp(hc)),
+           "ocp_quad_pattern")
+    return jr, jc, hr, hc
+
+
+def quad_kkt_pattern(N: int, boundary: int = 1, rowptr=True, colind=True, perm_j=True, perm_h=True):
+    """Host KKT structure (rowptr, colind, perm_j, perm_h) of the quadrotor NLP."""
+    s = quad_sizes(N, boundary)
+    rp = np.empty(s["dim"] + 1, np.int32) if rowptr else None
+    ci = np.empty(s["nnzk"], np.int32) if colind else None
+    pj = np.empty(s["nnzj"], np.int32) if perm_j else None
+    ph = np.empty(s["nnzh"], np.int32) if perm_h else None
+    _check(lib().ocp_quad_kkt(int(N), int(boundary), _hp(rp), _hp(ci), _hp(pj), _hp(ph)),
+           "ocp_quad_kkt")
     return rp, ci, pj, ph
 
 
@@ -362,6 +401,32 @@ class Problem:
                                         ctypes.c_void_p(gg.data_ptr()), self._stream()),
                "ocp_eval_coef_grad")
         return gA, gB, gg
+
+
+class QuadrotorProblem(Problem):
+    """The quadrotor model on a GPU: the evaluations and the assembly of
+    Problem, with the quadrotor's layouts (see ``quad_sizes``)."""
+
+    def __init__(self, N, boundary=1, g=QUAD_G, r=QUAD_R, device=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise OcpError(OCP_ERR_HIP, "no GPU visible: this library runs only on gfx950 devices")
+        self.N, self.n, self.m = int(N), 9, 4
+        self.boundary = int(boundary)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().ocp_quad_create(self.N, self.boundary, float(g), float(r), ctypes.byref(h)),
+                   "ocp_quad_create")
+        self._h = h
+        s = Sizes()
+        _check(lib().ocp_problem_sizes(self._h, ctypes.byref(s)), "ocp_problem_sizes")
+        self.sizes = s.as_dict()
+
+    @classmethod
+    def from_instance(cls, q, device=None):
+        return cls(q.N, q.bnd, q.g, q.r, device)
 
 
 def _autotune_cache_path() -> str:

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libocpeval.so")
 SOURCES = [os.path.join(CSRC, "ocp_eval.hip"), os.path.join(CSRC, "ocp_batch.hip"),
-           os.path.join(CSRC, "ocp_diff.hip"), os.path.join(CSRC, "ocp_host.cpp")]
+           os.path.join(CSRC, "ocp_diff.hip"), os.path.join(CSRC, "ocp_host.cpp"),
+           os.path.join(CSRC, "ocp_quad.hip"), os.path.join(CSRC, "ocp_quad_host.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

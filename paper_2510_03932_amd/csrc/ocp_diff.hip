@@ -37,6 +37,8 @@ using namespace ocp::dev;
 // boundary rows.
 static int check_default_options(const ocp_problem *p, const char *what)
 {
+    if (p->model != 0)
+        return fail(OCP_ERR_ARG, std::string(what) + ": supports the synthetic dynamics family only");
     if (p->d.scheme != OCP_SCHEME_TRAPEZOIDAL || p->d.nb != 0)
         return fail(OCP_ERR_ARG, std::string(what) +
                                      ": supports the trapezoidal scheme without boundary rows only");
@@ -350,6 +352,8 @@ int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_set_coefficients")) return rc;
+    if (p->model != 0)
+        return fail(OCP_ERR_ARG, "ocp_set_coefficients: the handle's model has no coefficients");
     if (!A || !gamma || (p->d.m > 0 && !B)) return fail(OCP_ERR_ARG, "ocp_set_coefficients: NULL array");
     const int n = p->d.n, m = p->d.m;
     hipError_t e = hipMemcpyAsync(const_cast<double *>(p->kp.A), A, sizeof(double) * n * n,

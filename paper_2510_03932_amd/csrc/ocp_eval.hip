@@ -14,6 +14,7 @@
 #include "ocp_device.h"
 #include "ocp_internal.h"
 #include "ocp_problem.h"
+#include "ocp_quad.h"
 
 using namespace ocp;
 using namespace ocp::dev;
@@ -235,7 +236,9 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
         const int32_t base = rowptr[r0];
         const int32_t ext = (int32_t)((uint32_t)rowptr[r0 + kn] - (uint32_t)base);
         const int cap = KT * (T + 1);
-        const bool staged = ext >= 0 && ext <= cap;
+        // stage only a range inside [0, nnzk) (a corrupt rowptr falls back
+        // to bounds-checked direct stores)
+        const bool staged = ext >= 0 && ext <= cap && base >= 0 && (int64_t)base + ext <= (int64_t)nnzk;
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (threadIdx.x == 0) filled = 0;
         if (staged)
@@ -482,6 +485,7 @@ int ocp_eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_obj")) return rc;
     if (!z || !obj) return fail(OCP_ERR_ARG, "ocp_eval_obj: null array");
+    if (p->model == quad::kModel) return quad::eval_obj(p, z, obj, stream);
     const unsigned g = (unsigned)std::min<int64_t>(kObjBlocks, blocks_for(p->d.N1, kBlock));
     hipLaunchKernelGGL(obj_partial_kernel, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
     if (int rc = check_launch("ocp_eval_obj")) return rc;
@@ -494,6 +498,7 @@ int ocp_eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t 
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_grad")) return rc;
     if (!z || !g) return fail(OCP_ERR_ARG, "ocp_eval_grad: null array");
+    if (p->model == quad::kModel) return quad::eval_grad(p, z, g, stream);
     dim3 grid(blocks_for(p->d.N1, kBlock), p->d.n + p->d.m);
     hipLaunchKernelGGL(grad_kernel, grid, dim3(kBlock), 0, stream, p->kp, z, g);
     return check_launch("ocp_eval_grad");
@@ -504,6 +509,7 @@ int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t 
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_cons")) return rc;
     if (!z || !c) return fail(OCP_ERR_ARG, "ocp_eval_cons: null array");
+    if (p->model == quad::kModel) return quad::eval_cons(p, z, c, stream);
     const int n = p->d.n;
     if (p->d.scheme == OCP_SCHEME_TRAPEZOIDAL) {
         const unsigned g = blocks_for(p->d.N, kBlock - 1);
@@ -529,6 +535,7 @@ int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_jac")) return rc;
     if (!z || !jvals) return fail(OCP_ERR_ARG, "ocp_eval_jac: null array");
+    if (p->model == quad::kModel) return quad::eval_jac(p, z, jvals, stream);
     const hipError_t e = launch_jac(p->kp, z, jvals, (uintptr_t)jvals % 16 == 0, stream);
     if (e != hipSuccess) return hip_fail("ocp_eval_jac", e);
     return OCP_OK;
@@ -541,6 +548,7 @@ int ocp_eval_hess(const ocp_problem *p, const double *z, const double *y, double
     if (int rc = check_handle(p, "ocp_eval_hess")) return rc;
     if (!z || !y || !hvals) return fail(OCP_ERR_ARG, "ocp_eval_hess: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_hess: sigma is not finite");
+    if (p->model == quad::kModel) return quad::eval_hess(p, z, y, sigma, hvals, stream);
     const hipError_t e = launch_hess(p->kp, z, y, sigma, hvals, stream);
     if (e != hipSuccess) return hip_fail("ocp_eval_hess", e);
     return OCP_OK;
@@ -554,6 +562,8 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
     if (int rc = check_handle(p, "ocp_assemble_kkt")) return rc;
     if (!perm_j || !perm_h || !rowptr || !jvals || !hvals || !kkt)
         return fail(OCP_ERR_ARG, "ocp_assemble_kkt: null array");
+    if (p->model == quad::kModel)
+        return quad::assemble_kkt(p, perm_j, perm_h, rowptr, jvals, hvals, reg, kkt, stream);
     // Tile height: 64 constraint rows (one per lane) while the staged CSR
     // range fits in 64 KiB of LDS, else 32.
     const int KT = (64 * (p->d.T + 1) * 8 <= 64 * 1024) ? 64 : 32;

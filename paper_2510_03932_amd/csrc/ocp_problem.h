@@ -21,6 +21,9 @@ struct ocp_problem {
     double *partials;   // device: kObjBlocks doubles (objective and Lagrangian sums)
     double *cpart;      // device: n (n+m+1) kCoefBlocks doubles (coefficient-gradient sums)
     ocp::dev::KP kp;
+    int model = 0;        // 0: the synthetic dynamics family; ocp::quad::kModel: the quadrotor
+    double quad_g = 0.0;  // quadrotor gravity and control weight
+    double quad_r = 0.0;
 };
 
 static inline int hip_fail(const char *what, hipError_t e)

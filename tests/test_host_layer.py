@@ -19,7 +19,7 @@ GRID = [(1, 1, 0), (1, 1, 1), (2, 1, 0), (3, 2, 0), (2, 2, 1), (5, 3, 0), (4, 3,
 def test_library_exports_every_declared_symbol():
     L = ocp.lib()
     names = ocp.exported_names()
-    assert len(names) == 33, names
+    assert len(names) == 37, names
     for name in names:
         assert hasattr(L, name), name
     text = open(ocp.HEADER).read()
@@ -171,3 +171,56 @@ def test_ex_rejects_unknown_options():
         with pytest.raises(ocp.OcpError) as e:
             ocp.sizes(10, 3, 1, scheme, bnd)
         assert e.value.code == ocp.OCP_ERR_ARG
+
+
+# ---- the quadrotor model -------------------------------------------------------
+
+@pytest.mark.parametrize("bnd", [0, 1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3, 64, 255, 1000, 4097])
+def test_quad_sizes_patterns_kkt_bit_exact(orc, N, bnd):
+    s = ocp.quad_sizes(N, bnd)
+    o = orc.quad_sizes(N, bnd)
+    for k in ("nvar", "ncon", "nnzj", "nnzh", "dim"):
+        assert s[k] == o[k], k
+    assert s["nnzk"] == s["nnzh"] + s["nnzj"] + s["ncon"]
+    assert (s["T"], s["S"], s["npair"]) == (68, 23, 0)
+    for g, w in zip(ocp.quad_pattern(N, bnd), orc.quad_pattern(N, bnd)):
+        assert np.array_equal(g, w)
+    got = ocp.quad_kkt_pattern(N, bnd)
+    want = orc.quad_kkt(N, bnd)
+    for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h"), got, want):
+        assert np.array_equal(g, w), name
+
+
+def test_quad_kkt_bit_exact_paper_grid(orc):
+    """The paper's largest quadrotor grid, N = 2e5, with the initial-state rows."""
+    got = ocp.quad_kkt_pattern(200_000, 1)
+    want = orc.quad_kkt(200_000, 1)
+    for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h"), got, want):
+        assert np.array_equal(g, w), name
+
+
+def test_quad_partial_outputs():
+    full = ocp.quad_kkt_pattern(50, 2)
+    part = ocp.quad_kkt_pattern(50, 2, rowptr=False, perm_h=False)
+    assert part[0] is None and part[3] is None
+    assert np.array_equal(part[1], full[1]) and np.array_equal(part[2], full[2])
+    jr, jc, hr, hc = ocp.quad_pattern(50, 2, hess=False)
+    assert hr is None and np.array_equal(jc, ocp.quad_pattern(50, 2)[1])
+
+
+def test_quad_rejects_bad_arguments_before_any_hip_call():
+    L = ocp.lib()
+    h = ctypes.c_void_p()
+    for N, bnd in ((0, 1), (-5, 0), (10, 3), (10, -1)):
+        with pytest.raises(ocp.OcpError) as e:
+            ocp.quad_sizes(N, bnd)
+        assert e.value.code == ocp.OCP_ERR_ARG
+        assert L.ocp_quad_create(N, bnd, 9.8, 0.1, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_quad_create(10, 1, float("nan"), 0.1, ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_quad_create(10, 1, 9.8, float("inf"), ctypes.byref(h)) == ocp.OCP_ERR_ARG
+    assert L.ocp_quad_create(10, 1, 9.8, 0.1, None) == ocp.OCP_ERR_ARG
+    assert h.value is None
+    with pytest.raises(ocp.OcpError) as e:
+        ocp.quad_sizes(400_000_000, 1)
+    assert e.value.code == ocp.OCP_ERR_OVERFLOW
