@@ -80,6 +80,9 @@ class Oracle:
             L.orc_quad_cons.argtypes = [i64, i32, dbl, ptr, ptr, ptr]
             L.orc_quad_jac.argtypes = [i64, i32, ptr, ptr, ptr]
             L.orc_quad_hess.argtypes = [i64, dbl, ptr, ptr, dbl, ptr, ptr]
+            L.orc_kkt_permute.argtypes = [i64, ptr, ptr, i64, ptr, i64, ptr, ptr, ptr, ptr, ptr, ptr,
+                                           ptr]
+            L.orc_assemble_mapped.argtypes = [i64, i64, ptr, i64, ptr, ptr, i64, ptr, ptr, ptr, ptr]
             L.orc_set_threads.argtypes = [i32]
             L.orc_set_threads.restype = None
             L.orc_get_threads.restype = i32
@@ -306,6 +309,33 @@ class Oracle:
                                       _p(perm_h), _p(nnzk)), "kkt_generic")
         return rowptr, colind[: int(nnzk[0])].copy(), perm_j, perm_h
 
+    # ---- symmetric reordering of the KKT matrix ----
+
+    def kkt_permute(self, rowptr, colind, perm_j, perm_h, order):
+        """Lower CSR of P K P^T for order[new] = old, with the slot maps
+        carried over: (rowptr2, colind2, perm_j2, perm_h2, diag2)."""
+        dim = len(rowptr) - 1
+        nnzk = int(rowptr[-1])
+        rp2 = np.empty(dim + 1, np.int32)
+        ci2 = np.empty(nnzk, np.int32)
+        pj2 = np.empty(len(perm_j), np.int32)
+        ph2 = np.empty(len(perm_h), np.int32)
+        dg2 = np.empty(dim, np.int32)
+        rowptr, colind, perm_j, perm_h, order = (_i32(a) for a in (rowptr, colind, perm_j, perm_h, order))
+        _check(self.L.orc_kkt_permute(dim, _p(rowptr), _p(colind), len(perm_j), _p(perm_j),
+                                      len(perm_h), _p(perm_h), _p(order), _p(rp2), _p(ci2),
+                                      _p(pj2), _p(ph2), _p(dg2)), "kkt_permute")
+        return rp2, ci2, pj2, ph2, dg2
+
+    def assemble_mapped(self, nnzk, diag, perm_j, jvals, perm_h, hvals, reg=None):
+        out = np.empty(int(nnzk))
+        regp = None if reg is None else _d(reg)
+        diag, perm_j, perm_h = _i32(diag), _i32(perm_j), _i32(perm_h)
+        _check(self.L.orc_assemble_mapped(int(nnzk), len(diag), _p(diag), len(perm_j), _p(perm_j),
+                                          _p(_d(jvals)), len(perm_h), _p(perm_h), _p(_d(hvals)),
+                                          _p(regp), _p(out)), "assemble_mapped")
+        return out
+
     # ---- quadrotor model (q: a synth.QuadInstance) ----
 
     def quad_sizes(self, N, bnd=1) -> dict:
@@ -365,6 +395,10 @@ class Oracle:
         return v, mu
 
 
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
 def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
@@ -404,6 +438,8 @@ jac_ex = DEFAULT.jac_ex
 hess_ex = DEFAULT.hess_ex
 pattern_ex = DEFAULT.pattern_ex
 kkt_ex = DEFAULT.kkt_ex
+kkt_permute = DEFAULT.kkt_permute
+assemble_mapped = DEFAULT.assemble_mapped
 quad_sizes = DEFAULT.quad_sizes
 quad_pattern = DEFAULT.quad_pattern
 quad_kkt = DEFAULT.quad_kkt

@@ -1629,3 +1629,83 @@ int orc_quad_hess(int64_t N, double r, const double *z, const double *y, double 
     }
     return ORC_OK;
 }
+
+/* ===========================================================================
+ * Symmetric reordering of the KKT matrix (paper Sec. 6: the one-time host
+ * analysis reorders the matrix to reduce fill before LDL^T).
+ *
+ * Given the lower CSR of K (any of the builds above) and an ordering
+ * order[new] = old, the lower CSR of P K P^T (entry (pos[r], pos[c]) for each
+ * stored (r, c), pos = order^-1, mirrored into the lower triangle) is built
+ * generically -- triplets -> counting sort by new row -> sort by new column --
+ * and every old slot is mapped to its new slot: perm_j2 = map o perm_j,
+ * perm_h2 = map o perm_h, and diag2[d] = map(diagonal slot of old row d).
+ * ======================================================================== */
+int orc_kkt_permute(int64_t dim, const int32_t *rowptr, const int32_t *colind,
+                    int64_t nnzj, const int32_t *perm_j, int64_t nnzh, const int32_t *perm_h,
+                    const int32_t *order, int32_t *rowptr2, int32_t *colind2, int32_t *perm_j2,
+                    int32_t *perm_h2, int32_t *diag2)
+{
+    if (dim < 1 || !rowptr || !colind || !order || !rowptr2 || !colind2) return ORC_BAD;
+    int64_t nnzk = rowptr[dim];
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)dim);
+    int64_t *cnt = (int64_t *)calloc((size_t)dim + 1, sizeof(int64_t));
+    int64_t *map = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnzk ? nnzk : 1));
+    ent_t *ent = (ent_t *)malloc(sizeof(ent_t) * (size_t)(nnzk ? nnzk : 1));
+    int64_t *fillp = (int64_t *)malloc(sizeof(int64_t) * (size_t)dim);
+    int rc = ORC_OK;
+    if (!pos || !cnt || !map || !ent || !fillp) { rc = ORC_BAD; goto done; }
+    for (int64_t i = 0; i < dim; i++) pos[i] = -1;
+    for (int64_t i = 0; i < dim; i++) {
+        int64_t o = order[i];
+        if (o < 0 || o >= dim || pos[o] >= 0) { rc = ORC_BAD; goto done; }
+        pos[o] = i;
+    }
+    /* new row of every stored entry */
+    for (int64_t r = 0; r < dim; r++)
+        for (int64_t q = rowptr[r]; q < rowptr[r + 1]; q++) {
+            int64_t a = pos[r], b = pos[colind[q]];
+            cnt[(a > b ? a : b) + 1]++;
+        }
+    for (int64_t i = 0; i < dim; i++) cnt[i + 1] += cnt[i];
+    memcpy(fillp, cnt, sizeof(int64_t) * (size_t)dim);
+    for (int64_t r = 0; r < dim; r++)
+        for (int64_t q = rowptr[r]; q < rowptr[r + 1]; q++) {
+            int64_t a = pos[r], b = pos[colind[q]];
+            int64_t row = a > b ? a : b, col = a > b ? b : a;
+            ent_t t = { col, q };
+            ent[fillp[row]++] = t;
+        }
+    for (int64_t i = 0; i < dim; i++) {
+        qsort(ent + cnt[i], (size_t)(cnt[i + 1] - cnt[i]), sizeof(ent_t), ent_cmp);
+        rowptr2[i] = (int32_t)cnt[i];
+        for (int64_t u = cnt[i]; u < cnt[i + 1]; u++) {
+            if (u > cnt[i] && ent[u].col == ent[u - 1].col) rc = ORC_BAD;  /* duplicate */
+            colind2[u] = (int32_t)ent[u].col;
+            map[ent[u].src] = u;
+        }
+    }
+    rowptr2[dim] = (int32_t)nnzk;
+    if (perm_j2) for (int64_t e = 0; e < nnzj; e++) perm_j2[e] = (int32_t)map[perm_j[e]];
+    if (perm_h2) for (int64_t e = 0; e < nnzh; e++) perm_h2[e] = (int32_t)map[perm_h[e]];
+    if (diag2) for (int64_t d = 0; d < dim; d++) diag2[d] = (int32_t)map[rowptr[d + 1] - 1];
+done:
+    free(pos); free(cnt); free(map); free(ent); free(fillp);
+    return rc;
+}
+
+/* Assembly through slot maps alone: kkt = 0; kkt[perm_h[e]] = hess[e];
+ * kkt[perm_j[e]] = jac[e]; then kkt[diag[d]] += reg[d] for every row d. */
+int orc_assemble_mapped(int64_t nnzk, int64_t dim, const int32_t *diag,
+                        int64_t nnzj, const int32_t *perm_j, const double *jac,
+                        int64_t nnzh, const int32_t *perm_h, const double *hess,
+                        const double *reg, double *kkt)
+{
+    if (!kkt || !diag || nnzk < 0) return ORC_BAD;
+    for (int64_t x = 0; x < nnzk; x++) kkt[x] = 0.0;
+    for (int64_t e = 0; e < nnzh; e++) kkt[perm_h[e]] = hess[e];
+    for (int64_t e = 0; e < nnzj; e++) kkt[perm_j[e]] = jac[e];
+    if (reg)
+        for (int64_t d = 0; d < dim; d++) kkt[diag[d]] += reg[d];
+    return ORC_OK;
+}

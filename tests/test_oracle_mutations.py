@@ -10,6 +10,7 @@ import pytest
 import oracle
 from tests import test_oracle_diff_pins as D
 from tests import test_oracle_ex_pins as E
+from tests import test_oracle_perm_pins as R
 from tests import test_oracle_pins as P
 from tests import test_oracle_quad_pins as Q
 
@@ -82,6 +83,10 @@ MUTATIONS = [
     ("quad reference ramp", "d[2] = 2.0 * t;", "d[2] = t;"),
     ("quad cost half", "acc_add(&a, w * (0.5 * L));", "acc_add(&a, w * L);"),
     ("quad boundary node", "double v = z[(int64_t)(b % QN) * (N + 1) + (b < QN ? 0 : N)];", "double v = z[(int64_t)(b % QN) * (N + 1) + (b < QN ? 0 : N - 1)];"),
+    ("permute column of an entry", "ent_t t = { col, q };", "ent_t t = { row, q };"),
+    ("permute inverse ordering", "        pos[o] = i;\n", "        pos[i] = o;\n"),
+    ("permute diagonal map", "diag2[d] = (int32_t)map[rowptr[d + 1] - 1];", "diag2[d] = (int32_t)map[rowptr[d]];"),
+    ("mapped assembly reg add", "kkt[diag[d]] += reg[d];", "kkt[diag[d]] = reg[d];"),
 ]
 
 # Pins run against each mutant: (test function, arguments after the oracle).
@@ -127,6 +132,8 @@ PINS = [
     (Q.test_gradient_complex_step, ()),
     (Q.test_hessian_mixed_difference, (1, 1, 1.3)),
     (Q.test_kkt_matches_scipy, (3, 1)),
+    (R.test_permuted_structure_matches_scipy, (5, 3, 2, 0, 0)),
+    (R.test_mapped_assembly_equals_dense_reordering, (6, 3, 2, 0, 0)),
 ]
 
 
