@@ -1,6 +1,6 @@
 """Benchmark of the evaluation path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler] [--no-quad] [--only-quad]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler] [--no-quad] [--only-quad] [--no-reorder] [--only-reorder]
 
 Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
 controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
@@ -357,6 +357,71 @@ def quadrotor(torch, ocp, synth, reps=10):
     return out
 
 
+def reordered(torch, ocp, synth, reps=10):
+    """Assembly into the fill-reducingly reordered KKT matrix P K P^T, the
+    ordering folded into the slot maps (ocp_assemble_kkt_mapped), against the
+    natural-order assembly and against natural assembly followed by a device
+    gather into the reordered layout (what a solver does without the fold).
+    Quadrotor at N = 1e6 and the synthetic family at N = 1e5 (n = 8, m = 4)."""
+    out = {}
+    dev = torch.device("cuda", 0)
+    cases = (("quadrotor_N1e6", lambda: synth.make_quadrotor(synth.QUAD_LARGE, seed=0, bnd=1)),
+             ("synthetic_N1e5_n8_m4", lambda: synth.make_instance(*synth.IPM_LOOP, seed=0)))
+    for tag, make in cases:
+        inst = make()
+        if tag.startswith("quadrotor"):
+            prob = ocp.QuadrotorProblem.from_instance(inst, dev)
+            rp, ci, pj, ph = ocp.quad_kkt_pattern(inst.N, 1)
+            order = ocp.quad_stage_order(inst.N, 1)
+        else:
+            prob = ocp.Problem.from_instance(inst, dev)
+            rp, ci, pj, ph = ocp.kkt_pattern(inst.N, inst.n, inst.m)
+            order = ocp.stage_order(inst.N, inst.n, inst.m)
+        s = prob.sizes
+        t0 = time.perf_counter()
+        rp2, ci2, pj2, ph2, dg2 = ocp.kkt_permute(rp, ci, pj, ph, order)
+        t_perm = time.perf_counter() - t0
+        # old slot -> new slot, then new slot -> old slot for the gather
+        smap = np.empty(s["nnzk"], np.int64)
+        smap[pj], smap[ph], smap[rp[1:] - 1] = pj2, ph2, dg2
+        inv = np.empty(s["nnzk"], np.int64)
+        inv[smap] = np.arange(s["nnzk"])
+        del ci, ci2, smap
+        z, y = (torch.from_numpy(a).to(dev) for a in (inst.z, inst.y))
+        jv, hv = prob.jac(z), prob.hess(z, y, 1.0)
+        t_pj, t_ph, t_rp, t_pj2, t_ph2, t_dg2 = (torch.from_numpy(a).to(dev) for a in (pj, ph, rp, pj2, ph2, dg2))
+        t_inv = torch.from_numpy(inv).to(dev)
+        del inv
+        f64 = dict(dtype=torch.float64, device=dev)
+        kkt, kkt2 = torch.empty(s["nnzk"], **f64), torch.empty(s["nnzk"], **f64)
+        nbytes = 12 * (s["nnzj"] + s["nnzh"]) + 8 * s["nnzk"] + 4 * s["ncon"]
+        calls = {
+            "natural_assemble_kkt": lambda: prob.assemble_kkt(t_pj, t_ph, t_rp, jv, hv, None, out=kkt),
+            "reordered_assemble_kkt_mapped": lambda: prob.assemble_kkt_mapped(t_pj2, t_ph2, t_dg2, jv, hv,
+                                                                              None, out=kkt2),
+            "natural_then_gather": lambda: (prob.assemble_kkt(t_pj, t_ph, t_rp, jv, hv, None, out=kkt),
+                                            torch.index_select(kkt, 0, t_inv, out=kkt2)),
+        }
+        r = {"nnzk": s["nnzk"], "host_permute_s": round(t_perm, 2), "bytes": nbytes}
+        for name, fn in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            r[name] = {"ms": round(ms, 4), "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+        r["speedup_fold_vs_gather"] = round(r["natural_then_gather"]["ms"] / r["reordered_assemble_kkt_mapped"]["ms"], 3)
+        prob.close()
+        del jv, hv, kkt, kkt2, t_pj, t_ph, t_rp, t_pj2, t_ph2, t_dg2, t_inv
+        torch.cuda.empty_cache()
+        out[tag] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +434,10 @@ def main():
                     help="skip the 512-instance batched measurement (profiling runs)")
     ap.add_argument("--no-euler", action="store_true",
                     help="skip the forward-Euler measurement (profiling runs)")
+    ap.add_argument("--no-reorder", action="store_true",
+                    help="skip the reordered-KKT assembly measurement (profiling runs)")
+    ap.add_argument("--only-reorder", action="store_true",
+                    help="run only the reordered-KKT assembly measurement (profiling runs)")
     ap.add_argument("--no-quad", action="store_true",
                     help="skip the quadrotor measurement (profiling runs)")
     ap.add_argument("--only-quad", action="store_true",
@@ -394,6 +463,10 @@ def main():
         torch.cuda.set_device(0)
         log("[bench] batched workload only")
         print(json.dumps({"batched": batched(torch, ocp, synth)}), flush=True)
+        return
+    if args.only_reorder:
+        log("[bench] reordered KKT assembly only")
+        print(json.dumps({"reordered": reordered(torch, ocp, synth)}), flush=True)
         return
     if args.only_quad:
         log("[bench] quadrotor workload only")
@@ -558,6 +631,9 @@ def main():
     if not args.no_quad:
         log("[bench] quadrotor workload")
         out["quadrotor"] = quadrotor(torch, ocp, synth)
+    if not args.no_reorder:
+        log("[bench] reordered KKT assembly")
+        out["reordered"] = reordered(torch, ocp, synth)
     if not args.no_diff:
         log("[bench] differentiation workload")
         out["differentiation"] = differentiation(torch, ocp, synth)

@@ -208,6 +208,56 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
                      const double *reg, double *kkt, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Symmetric reordering of the KKT matrix (Sec. 6: the one-time host analysis
+ * reorders the matrix for the sparse LDL^T factorization).  Folding the
+ * ordering into the slot maps lets the device assemble P K P^T directly.
+ * An ordering is given as order[new] = old, a permutation of [0, dim).
+ * ------------------------------------------------------------------------- */
+
+/* A fill-reducing ordering in closed form for the problem of (N, n, m, opt):
+ * unknowns and rows grouped by grid node -- node k's block holds its states,
+ * its controls (when it has any), the boundary rows fixed at it, then the
+ * defect rows of interval k.  The reordered KKT matrix is banded with a
+ * bandwidth independent of N, so the LDL^T fill grows linearly in N.
+ * order: dim int32 (host, caller-owned).  Host only.
+ * Errors: as ocp_sizes_ex, OCP_ERR_ARG for a NULL order. */
+int ocp_stage_order(int64_t N, int32_t n, int32_t m, const ocp_options *opt, int32_t *order);
+
+/* The same ordering for the quadrotor NLP (ocp_quad_sizes). */
+int ocp_quad_stage_order(int64_t N, int32_t boundary, int32_t *order);
+
+/* Lower CSR of P K P^T from the lower CSR (rowptr, colind) of K and an
+ * ordering, with the slot maps carried over: perm_j2[e] and perm_h2[e] are
+ * the new slots of the entries perm_j[e], perm_h[e] point at, and diag2[d]
+ * the new slot of old row d's diagonal.  An entry (r, c) of K moves to
+ * (pos r, pos c), mirrored into the lower triangle, where pos inverts order.
+ * All host arrays, caller-owned: rowptr2 dim+1, colind2 nnzk, perm_j2 nnzj,
+ * perm_h2 nnzh, diag2 dim (perm_j/perm_j2, perm_h/perm_h2 and diag2 may be
+ * NULL to skip them).  Generic in the structure: any lower CSR with every
+ * diagonal last in its row.  Host only, several threads.
+ * Errors: OCP_ERR_ARG (not a permutation, malformed CSR, a slot map outside
+ * [0, nnzk)), OCP_ERR_ALLOC. */
+int ocp_kkt_permute(int64_t dim, const int32_t *rowptr, const int32_t *colind, int64_t nnzj,
+                    const int32_t *perm_j, int64_t nnzh, const int32_t *perm_h, const int32_t *order,
+                    int32_t *rowptr2, int32_t *colind2, int32_t *perm_j2, int32_t *perm_h2,
+                    int32_t *diag2);
+
+/* KKT assembly through slot maps alone, for any ordering:
+ *   kkt[perm_h[e]] = hvals[e] (+ reg[d] when entry e is row d's diagonal),
+ *   kkt[perm_j[e]] = jvals[e], and kkt[diag[d]] = reg[d] (0 when reg is
+ *   NULL) for every constraint row d.
+ * perm_j (nnzj), perm_h (nnzh), diag (dim: the slot of every row's
+ * diagonal, as from ocp_kkt_permute), jvals, hvals, reg (dim, nullable,
+ * indexed by the original rows) and kkt (nnzk) are device arrays; the slot
+ * maps must be injective and together cover [0, nnzk).  Works for every
+ * handle (both models and schemes).  Fastest for node-grouped orderings
+ * such as ocp_stage_order, whose rows of a run of nodes form one contiguous
+ * range of the CSR.  Fully overwrites kkt.  No atomics in global memory. */
+int ocp_assemble_kkt_mapped(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,
+                            const int32_t *diag, const double *jvals, const double *hvals,
+                            const double *reg, double *kkt, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Lagrangian derivatives for differentiable programming (the paper names
  * tighter integration with differentiable programming workflows as future
  * work, Sec. 8).  L(z, y) = sigma f(z) + y^T c(z); the dynamics coefficients

@@ -103,6 +103,10 @@ def lib():
         L.ocp_assemble_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_last_error.restype = ctypes.c_char_p
         L.ocp_quad_sizes.argtypes = [i64, i32, ctypes.POINTER(Sizes)]
+        L.ocp_stage_order.argtypes = [i64, i32, i32, ctypes.POINTER(Options), vp]
+        L.ocp_quad_stage_order.argtypes = [i64, i32, vp]
+        L.ocp_kkt_permute.argtypes = [i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_assemble_kkt_mapped.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_quad_pattern.argtypes = [i64, i32, vp, vp, vp, vp]
         L.ocp_quad_kkt.argtypes = [i64, i32, vp, vp, vp, vp]
         L.ocp_quad_create.argtypes = [i64, i32, dbl, dbl, ctypes.POINTER(vp)]
@@ -181,6 +185,44 @@ def kkt_pattern(N: int, n: int, m: int, rowptr=True, colind=True, perm_j=True, p
     _check(lib().ocp_build_kkt_ex(N, n, m, ctypes.byref(o), _hp(rp), _hp(ci), _hp(pj), _hp(ph)),
            "ocp_build_kkt")
     return rp, ci, pj, ph
+
+
+# ---- symmetric reordering of the KKT matrix --------------------------------------
+
+def stage_order(N: int, n: int, m: int, scheme=0, boundary=0) -> np.ndarray:
+    """Node-grouped fill-reducing ordering (order[new] = old), int32."""
+    s = sizes(N, n, m, scheme, boundary)
+    order = np.empty(s["dim"], np.int32)
+    o = _opts(scheme, boundary)
+    _check(lib().ocp_stage_order(int(N), int(n), int(m), ctypes.byref(o), _hp(order)), "ocp_stage_order")
+    return order
+
+
+def quad_stage_order(N: int, boundary: int = 1) -> np.ndarray:
+    s = quad_sizes(N, boundary)
+    order = np.empty(s["dim"], np.int32)
+    _check(lib().ocp_quad_stage_order(int(N), int(boundary), _hp(order)), "ocp_quad_stage_order")
+    return order
+
+
+def kkt_permute(rowptr, colind, perm_j, perm_h, order):
+    """Lower CSR of P K P^T with the slot maps carried over:
+    (rowptr2, colind2, perm_j2, perm_h2, diag2), all int32 host arrays."""
+    i32 = lambda a: np.ascontiguousarray(a, np.int32)
+    rowptr, colind, perm_j, perm_h, order = (i32(a) for a in (rowptr, colind, perm_j, perm_h, order))
+    dim = len(rowptr) - 1
+    if len(order) != dim:
+        raise ValueError(f"order has {len(order)} entries, the KKT matrix {dim} rows")
+    nnzk = int(rowptr[-1])
+    rp2 = np.empty(dim + 1, np.int32)
+    ci2 = np.empty(nnzk, np.int32)
+    pj2 = np.empty(len(perm_j), np.int32)
+    ph2 = np.empty(len(perm_h), np.int32)
+    dg2 = np.empty(dim, np.int32)
+    _check(lib().ocp_kkt_permute(dim, _hp(rowptr), _hp(colind), len(perm_j), _hp(perm_j), len(perm_h),
+                                 _hp(perm_h), _hp(order), _hp(rp2), _hp(ci2), _hp(pj2), _hp(ph2),
+                                 _hp(dg2)), "ocp_kkt_permute")
+    return rp2, ci2, pj2, ph2, dg2
 
 
 # ---- the quadrotor model (paper Appendix A) ----------------------------------
@@ -339,6 +381,21 @@ class Problem:
         out, op = self._out(out, s["nnzk"], "kkt")
         _check(lib().ocp_assemble_kkt(self._h, pj, ph, rp, jp, hp, gp, op, self._stream()),
                "ocp_assemble_kkt")
+        return out
+
+    def assemble_kkt_mapped(self, perm_j, perm_h, diag, jvals, hvals, reg=None, out=None):
+        """Assembly through slot maps alone (any ordering, e.g. from kkt_permute)."""
+        torch = _torch()
+        s = self.sizes
+        pj = self._dev(perm_j, s["nnzj"], torch.int32, "perm_j")
+        ph = self._dev(perm_h, s["nnzh"], torch.int32, "perm_h")
+        dg = self._dev(diag, s["dim"], torch.int32, "diag")
+        jp = self._dev(jvals, s["nnzj"], torch.float64, "jvals")
+        hp = self._dev(hvals, s["nnzh"], torch.float64, "hvals")
+        gp = None if reg is None else self._dev(reg, s["dim"], torch.float64, "reg")
+        out, op = self._out(out, s["nnzk"], "kkt")
+        _check(lib().ocp_assemble_kkt_mapped(self._h, pj, ph, dg, jp, hp, gp, op, self._stream()),
+               "ocp_assemble_kkt_mapped")
         return out
 
     # -- Lagrangian derivatives ---------------------------------------------------

@@ -19,7 +19,7 @@ GRID = [(1, 1, 0), (1, 1, 1), (2, 1, 0), (3, 2, 0), (2, 2, 1), (5, 3, 0), (4, 3,
 def test_library_exports_every_declared_symbol():
     L = ocp.lib()
     names = ocp.exported_names()
-    assert len(names) == 37, names
+    assert len(names) == 41, names
     for name in names:
         assert hasattr(L, name), name
     text = open(ocp.HEADER).read()
@@ -224,3 +224,101 @@ def test_quad_rejects_bad_arguments_before_any_hip_call():
     with pytest.raises(ocp.OcpError) as e:
         ocp.quad_sizes(400_000_000, 1)
     assert e.value.code == ocp.OCP_ERR_OVERFLOW
+
+
+# ---- symmetric reordering ---------------------------------------------------------
+
+def _symbolic_fill(rowptr, colind):
+    """Entries of L in an LDL^T factorization without pivoting, by symbolic
+    elimination of the symmetric pattern (the definition of fill)."""
+    dim = len(rowptr) - 1
+    M = np.zeros((dim, dim), bool)
+    rows = np.repeat(np.arange(dim), np.diff(rowptr))
+    M[rows, colind] = True
+    M[colind, rows] = True
+    total = 0
+    for k in range(dim):
+        nb = np.flatnonzero(M[k, k + 1:]) + k + 1
+        total += len(nb)
+        if len(nb):
+            M[np.ix_(nb, nb)] = True
+    return total
+
+
+@pytest.mark.parametrize("n,m,scheme,bnd", [(3, 2, 0, 0), (3, 2, 1, 2), (4, 1, 0, 1), (2, 0, 0, 2)])
+def test_stage_order_is_fill_reducing(n, m, scheme, bnd):
+    """Under the node-grouped ordering the LDL^T fill grows linearly in N
+    (equal increments per doubling step once N is past the boundary effects),
+    while in the natural order it grows faster."""
+    fills, natural = [], []
+    for N in (8, 16, 32):
+        rp, ci, pj, ph = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd)
+        order = ocp.stage_order(N, n, m, scheme, bnd)
+        assert np.array_equal(np.sort(order), np.arange(len(rp) - 1))
+        rp2, ci2, _, _, _ = ocp.kkt_permute(rp, ci, pj, ph, order)
+        fills.append(_symbolic_fill(rp2, ci2))
+        natural.append(_symbolic_fill(rp, ci))
+    per_node = [(fills[1] - fills[0]) / 8, (fills[2] - fills[1]) / 16]
+    assert per_node[0] == per_node[1], fills
+    # linear growth would add twice as much from 16 to 32 nodes as from 8 to 16
+    assert (natural[2] - natural[1]) / (natural[1] - natural[0]) > 2.5, natural
+    assert fills[2] < natural[2]
+
+
+@pytest.mark.parametrize("N", [10, 100, 1000])
+def test_stage_order_bandwidth_independent_of_N(N):
+    n, m = 4, 2
+    rp, ci, pj, ph = ocp.kkt_pattern(N, n, m, boundary=2)
+    rp2, ci2, _, _, _ = ocp.kkt_permute(rp, ci, pj, ph, ocp.stage_order(N, n, m, 0, 2))
+    rows = np.repeat(np.arange(len(rp2) - 1), np.diff(rp2))
+    # a node block has n + m + n rows (plus n boundary rows at the ends); an
+    # entry reaches at most into the previous block
+    assert int((rows - ci2).max()) < 2 * (2 * n + m) + n
+
+
+@pytest.mark.parametrize("N,n,m,scheme,bnd", [(1, 1, 0, 0, 0), (2, 3, 1, 1, 2), (7, 5, 3, 0, 1),
+                                              (33, 16, 8, 1, 0), (1000, 4, 2, 0, 2)])
+def test_kkt_permute_bit_exact(orc, N, n, m, scheme, bnd):
+    rp, ci, pj, ph = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd)
+    orders = [ocp.stage_order(N, n, m, scheme, bnd),
+              np.random.default_rng(N).permutation(len(rp) - 1).astype(np.int32)]
+    for order in orders:
+        got = ocp.kkt_permute(rp, ci, pj, ph, order)
+        want = orc.kkt_permute(rp, ci, pj, ph, order)
+        for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h", "diag"), got, want):
+            assert np.array_equal(g, w), name
+
+
+@pytest.mark.parametrize("N,bnd", [(1, 0), (5, 2), (300, 1)])
+def test_quad_stage_order_and_permute(orc, N, bnd):
+    order = ocp.quad_stage_order(N, bnd)
+    rp, ci, pj, ph = ocp.quad_kkt_pattern(N, bnd)
+    assert np.array_equal(np.sort(order), np.arange(len(rp) - 1))
+    got = ocp.kkt_permute(rp, ci, pj, ph, order)
+    want = orc.kkt_permute(rp, ci, pj, ph, order)
+    for name, g, w in zip(("rowptr", "colind", "perm_j", "perm_h", "diag"), got, want):
+        assert np.array_equal(g, w), name
+
+
+def test_kkt_permute_rejects_bad_input():
+    rp, ci, pj, ph = ocp.kkt_pattern(6, 3, 1)
+    dim = len(rp) - 1
+    bad = np.arange(dim, dtype=np.int32)
+    bad[2] = bad[4]
+    for order in (bad, np.arange(1, dim + 1, dtype=np.int32)):
+        with pytest.raises(ocp.OcpError) as e:
+            ocp.kkt_permute(rp, ci, pj, ph, order)
+        assert e.value.code == ocp.OCP_ERR_ARG
+    ident = np.arange(dim, dtype=np.int32)
+    pj_bad = pj.copy()
+    pj_bad[3] = rp[-1]
+    with pytest.raises(ocp.OcpError) as e:
+        ocp.kkt_permute(rp, ci, pj_bad, ph, ident)
+    assert e.value.code == ocp.OCP_ERR_ARG
+    ci_bad = ci.copy()
+    ci_bad[0] = dim - 1  # above the diagonal of row 0
+    with pytest.raises(ocp.OcpError) as e:
+        ocp.kkt_permute(rp, ci_bad, pj, ph, ident)
+    assert e.value.code == ocp.OCP_ERR_ARG
+    with pytest.raises(ocp.OcpError):
+        ocp.stage_order(0, 3, 1)
