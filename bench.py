@@ -1,6 +1,6 @@
 """Benchmark of the evaluation path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler] [--no-quad] [--only-quad] [--no-reorder] [--only-reorder]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ipm-loop] [--no-batched] [--no-diff] [--no-euler] [--no-quad] [--only-quad] [--no-reorder] [--only-reorder] [--no-fused]
 
 Workload: the large single instance -- N = 1e6 intervals, n = 16 states, m = 8
 controls, dense 16 x 16 A, FP64, synthetic seeded inputs (numpy PCG64, seed 0)
@@ -434,6 +434,8 @@ def main():
                     help="skip the 512-instance batched measurement (profiling runs)")
     ap.add_argument("--no-euler", action="store_true",
                     help="skip the forward-Euler measurement (profiling runs)")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip the fused KKT evaluation measurement (profiling runs)")
     ap.add_argument("--no-reorder", action="store_true",
                     help="skip the reordered-KKT assembly measurement (profiling runs)")
     ap.add_argument("--only-reorder", action="store_true",
@@ -620,6 +622,28 @@ def main():
         "jac_frac_of_write_stream": round(kern["eval_jac"]["GB_per_s"] * 1e9 / write_bw, 4),
         "kkt_host_build_s": round(t_kkt_build, 2),
     }
+    # the fused path: the same KKT values written straight from (z, y) by
+    # ocp_eval_kkt, against eval_jac + eval_hess + assemble_kkt above
+    if not args.no_fused:
+        log("[bench] fused evaluation into the KKT matrix")
+        prob.eval_kkt(z, y, 1.0, reg, out=kkt)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(args.steps, 5)
+        e0.record()
+        for _ in range(reps):
+            prob.eval_kkt(z, y, 1.0, reg, out=kkt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        fbytes = 8 * n * (N + 1) + 8 * n * N + 8 * s["dim"] + 8 * s["nnzk"]
+        sep_ms = avg["eval_jac"] + avg["eval_hess"] + avg["assemble_kkt"]
+        out["fused_kkt"] = {
+            "call": "ocp_eval_kkt (Jacobian + Hessian + reg into the CSR KKT values)",
+            "ms": round(ms, 4), "bytes": fbytes, "hbm_frac": round(fbytes / (ms * 1e-3) / HBM_PEAK, 4),
+            "separate_jac_hess_assemble_ms": round(sep_ms, 4), "speedup_vs_separate": round(sep_ms / ms, 3),
+            "jac_hess_nnz_per_s": nnz_jh / (ms * 1e-3),
+            "step_ms_with_fused": round(avg["eval_obj"] + avg["eval_grad"] + avg["eval_cons"] + ms, 4)}
     del jv, hv, kkt, pj, ph, rp, z, y, g, c, reg
     torch.cuda.empty_cache()
     if not args.no_ipm_loop:

@@ -207,6 +207,17 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
                      const int32_t *rowptr, const double *jvals, const double *hvals,
                      const double *reg, double *kkt, hipStream_t stream);
 
+/* Fused evaluation into the KKT matrix: the values ocp_eval_jac,
+ * ocp_eval_hess(z, y, sigma) and ocp_assemble_kkt (with the slot maps of
+ * ocp_build_kkt and the same reg) would produce, written straight into kkt
+ * (nnzk doubles, device, the layout of ocp_build_kkt), without the COO value
+ * arrays.  This is what an interior-point iteration factorizes (Sec. 6); the
+ * matrix is written once.  Same expressions as the separate calls.  Supports
+ * the synthetic family under the trapezoidal scheme (any boundary option);
+ * other handles get OCP_ERR_ARG. */
+int ocp_eval_kkt(const ocp_problem *p, const double *z, const double *y, double sigma, const double *reg,
+                 double *kkt, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Symmetric reordering of the KKT matrix (Sec. 6: the one-time host analysis
  * reorders the matrix for the sparse LDL^T factorization).  Folding the

@@ -107,6 +107,7 @@ def lib():
         L.ocp_quad_stage_order.argtypes = [i64, i32, vp]
         L.ocp_kkt_permute.argtypes = [i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_assemble_kkt_mapped.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_eval_kkt.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.ocp_quad_pattern.argtypes = [i64, i32, vp, vp, vp, vp]
         L.ocp_quad_kkt.argtypes = [i64, i32, vp, vp, vp, vp]
         L.ocp_quad_create.argtypes = [i64, i32, dbl, dbl, ctypes.POINTER(vp)]
@@ -381,6 +382,18 @@ class Problem:
         out, op = self._out(out, s["nnzk"], "kkt")
         _check(lib().ocp_assemble_kkt(self._h, pj, ph, rp, jp, hp, gp, op, self._stream()),
                "ocp_assemble_kkt")
+        return out
+
+    def eval_kkt(self, z, y, sigma=1.0, reg=None, out=None):
+        """Jacobian and Hessian evaluated straight into the KKT values (the
+        layout of kkt_pattern), the fused form of jac + hess + assemble_kkt."""
+        torch = _torch()
+        s = self.sizes
+        zp = self._dev(z, s["nvar"], torch.float64, "z")
+        yp = self._dev(y, s["ncon"], torch.float64, "y")
+        gp = None if reg is None else self._dev(reg, s["dim"], torch.float64, "reg")
+        out, op = self._out(out, s["nnzk"], "kkt")
+        _check(lib().ocp_eval_kkt(self._h, zp, yp, float(sigma), gp, op, self._stream()), "ocp_eval_kkt")
         return out
 
     def assemble_kkt_mapped(self, perm_j, perm_h, diag, jvals, hvals, reg=None, out=None):

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libocpeval.so")
 SOURCES = [os.path.join(CSRC, "ocp_eval.hip"), os.path.join(CSRC, "ocp_batch.hip"),
            os.path.join(CSRC, "ocp_diff.hip"), os.path.join(CSRC, "ocp_host.cpp"),
            os.path.join(CSRC, "ocp_quad.hip"), os.path.join(CSRC, "ocp_quad_host.cpp"),
-           os.path.join(CSRC, "ocp_mapped.hip"), os.path.join(CSRC, "ocp_order_host.cpp")]
+           os.path.join(CSRC, "ocp_mapped.hip"), os.path.join(CSRC, "ocp_order_host.cpp"),
+           os.path.join(CSRC, "ocp_fused.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

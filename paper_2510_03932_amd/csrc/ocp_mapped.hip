@@ -29,7 +29,8 @@ using namespace ocp::dev;
 
 namespace {
 
-constexpr int kMapCap = 7936;  // values staged per workgroup (62 KiB of LDS)
+constexpr int kMapTarget = 2048;  // values staged per workgroup when a node fits (16 KiB)
+constexpr int kMapCap = 7936;     // most values staged per workgroup (62 KiB of LDS)
 
 struct MP {
     int N, N1, NU;
@@ -44,6 +45,7 @@ struct MP {
     int64_t nvar, ndef, nnzj_def;
     int nnzk;
     int KT, lgKT;
+    int cap;  // LDS tile capacity (values)
 };
 
 // Node offset (0 or 1) of the column of Jacobian slot row sigma.
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void mapped_assemble_kernel(
     const int32_t *__restrict__ diag, const double *__restrict__ jv, const double *__restrict__ hv,
     const double *__restrict__ reg, double *__restrict__ kkt)
 {
-    __shared__ double tile[kMapCap];
+    extern __shared__ double tile[];  // the tile's entries (host-sized, <= kMapCap)
     __shared__ int smin, smax, scount;
     const int KT = P.KT, lg = P.lgKT;
     const int64_t k0 = (int64_t)blockIdx.x * KT;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void mapped_assemble_kernel(
     __syncthreads();
     const int qmin = smin, qmax = smax, count = scount;
     if (count == 0) return;
-    const bool exact = qmin >= 0 && qmax < P.nnzk && count <= kMapCap && qmax - qmin + 1 == count;
+    const bool exact = qmin >= 0 && qmax < P.nnzk && count <= P.cap && qmax - qmin + 1 == count;
     if (exact) {
         visit([&](int32_t q, double v) { tile[q - qmin] = v; }, true);
         __syncthreads();
@@ -210,15 +212,20 @@ int ocp_assemble_kkt_mapped(const ocp_problem *p, const int32_t *perm_j, const i
     P.ndef = d.ndef;
     P.nnzj_def = d.nnzj_def;
     P.nnzk = (int)d.nnzk;
-    // nodes per tile: the largest power of two whose entries fit the LDS tile
+    // nodes per tile: the largest power of two whose entries fit a 16 KiB tile
+    // (small tiles keep several workgroups per CU), but at least 4 nodes
+    // while they fit the 62 KiB maximum
     const int64_t per_node = (int64_t)P.nJ + P.sA + P.sB + P.n;
+    auto need = [&](int lgk) { return ((int64_t)1 << lgk) * per_node + 2 * P.n; };
     int lg = 0;
-    while (((int64_t)2 << lg) * per_node + 2 * P.n <= kMapCap && lg < 10) lg++;
+    while (lg < 10 && need(lg + 1) <= kMapTarget) lg++;
+    while (lg < 2 && need(lg + 1) <= kMapCap) lg++;
     P.KT = 1 << lg;
     P.lgKT = lg;
+    P.cap = (int)need(lg);
     const unsigned tiles = blocks_for(d.N1, P.KT);
-    hipLaunchKernelGGL(mapped_assemble_kernel, dim3(tiles), dim3(kBlock), 0, stream, P, perm_j, perm_h, diag,
-                       jvals, hvals, reg, kkt);
+    hipLaunchKernelGGL(mapped_assemble_kernel, dim3(tiles), dim3(kBlock), (size_t)P.cap * sizeof(double), stream,
+                       P, perm_j, perm_h, diag, jvals, hvals, reg, kkt);
     return check_launch("ocp_assemble_kkt_mapped");
 }
 

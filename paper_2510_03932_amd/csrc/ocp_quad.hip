@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void quad_grad_kernel(QP P, const double *_
 // the boundary rows.
 // ---------------------------------------------------------------------------
 constexpr int kGroups = kStates + kVars;
-constexpr int kTileCap = 1024;  // values staged per workgroup
+constexpr int kTileCap = 2048;  // values staged per workgroup (16 KiB of LDS)
 
 struct AsmGroups {
     int tile0[kGroups + 1];  // first workgroup of each group; tile0[kGroups] = first boundary workgroup
@@ -365,10 +365,11 @@ __global__ __launch_bounds__(kBlock) void quad_assemble_kernel(
             put(q0, v0);
             if (two) put(q1, v1);
         }
-        if (!is_h && threadIdx.x < kn) {
-            const int64_t d = d0 + threadIdx.x;
-            put(rowptr[d + 1] - 1, reg ? reg[d] : 0.0);
-        }
+        if (!is_h)
+            for (int x = threadIdx.x; x < kn; x += kBlock) {
+                const int64_t d = d0 + x;
+                put(rowptr[d + 1] - 1, reg ? reg[d] : 0.0);
+            }
     };
     int mine = 0;
     visit([&](int32_t q, double v) {
