@@ -260,13 +260,29 @@ int ocp_kkt_permute(int64_t dim, const int32_t *rowptr, const int32_t *colind, i
  * perm_j (nnzj), perm_h (nnzh), diag (dim: the slot of every row's
  * diagonal, as from ocp_kkt_permute), jvals, hvals, reg (dim, nullable,
  * indexed by the original rows) and kkt (nnzk) are device arrays; the slot
- * maps must be injective and together cover [0, nnzk).  Works for every
- * handle (both models and schemes).  Fastest for node-grouped orderings
- * such as ocp_stage_order, whose rows of a run of nodes form one contiguous
- * range of the CSR.  Fully overwrites kkt.  No atomics in global memory. */
+ * maps must be injective and together cover [0, nnzk).  plan (nullable) is
+ * the output of ocp_mapped_plan for these same maps; it saves a pass over
+ * the maps on every call.  A plan made from other maps gives wrong values
+ * (never an access outside the arrays).  Works for every handle (both
+ * models and schemes).  Fastest for node-grouped orderings such as
+ * ocp_stage_order, whose rows of a run of nodes form one contiguous range of
+ * the CSR.  Fully overwrites kkt.  No atomics in global memory. */
 int ocp_assemble_kkt_mapped(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,
-                            const int32_t *diag, const double *jvals, const double *hvals,
-                            const double *reg, double *kkt, hipStream_t stream);
+                            const int32_t *diag, const int32_t *plan, const double *jvals,
+                            const double *hvals, const double *reg, double *kkt, hipStream_t stream);
+
+/* Number of int32 entries of a plan for ocp_assemble_kkt_mapped on this
+ * handle (two per tile of grid nodes).  Host only. */
+int ocp_mapped_plan_size(const ocp_problem *p, int64_t *entries);
+
+/* Record, for slot maps (perm_j, perm_h, diag as for
+ * ocp_assemble_kkt_mapped), the CSR range each node tile fills: plan
+ * (device, ocp_mapped_plan_size entries) receives per tile the first slot
+ * (or -1 when the tile's slots are not one contiguous range) and the
+ * number of slots.  One launch; the maps are fixed across an
+ * interior-point solve, so this runs once. */
+int ocp_mapped_plan(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,
+                    const int32_t *diag, int32_t *plan, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Lagrangian derivatives for differentiable programming (the paper names

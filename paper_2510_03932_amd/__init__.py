@@ -106,7 +106,9 @@ def lib():
         L.ocp_stage_order.argtypes = [i64, i32, i32, ctypes.POINTER(Options), vp]
         L.ocp_quad_stage_order.argtypes = [i64, i32, vp]
         L.ocp_kkt_permute.argtypes = [i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
-        L.ocp_assemble_kkt_mapped.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_assemble_kkt_mapped.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_mapped_plan_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.ocp_mapped_plan.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ocp_eval_kkt.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.ocp_quad_pattern.argtypes = [i64, i32, vp, vp, vp, vp]
         L.ocp_quad_kkt.argtypes = [i64, i32, vp, vp, vp, vp]
@@ -396,8 +398,23 @@ class Problem:
         _check(lib().ocp_eval_kkt(self._h, zp, yp, float(sigma), gp, op, self._stream()), "ocp_eval_kkt")
         return out
 
-    def assemble_kkt_mapped(self, perm_j, perm_h, diag, jvals, hvals, reg=None, out=None):
-        """Assembly through slot maps alone (any ordering, e.g. from kkt_permute)."""
+    def mapped_plan(self, perm_j, perm_h, diag):
+        """Per-tile CSR ranges of slot maps, for assemble_kkt_mapped (int32 device tensor)."""
+        torch = _torch()
+        s = self.sizes
+        pj = self._dev(perm_j, s["nnzj"], torch.int32, "perm_j")
+        ph = self._dev(perm_h, s["nnzh"], torch.int32, "perm_h")
+        dg = self._dev(diag, s["dim"], torch.int32, "diag")
+        cnt = ctypes.c_int64()
+        _check(lib().ocp_mapped_plan_size(self._h, ctypes.byref(cnt)), "ocp_mapped_plan_size")
+        plan = torch.empty(cnt.value, dtype=torch.int32, device=self.device)
+        _check(lib().ocp_mapped_plan(self._h, pj, ph, dg, ctypes.c_void_p(plan.data_ptr()), self._stream()),
+               "ocp_mapped_plan")
+        return plan
+
+    def assemble_kkt_mapped(self, perm_j, perm_h, diag, jvals, hvals, reg=None, out=None, plan=None):
+        """Assembly through slot maps alone (any ordering, e.g. from kkt_permute);
+        plan (from mapped_plan for the same maps) skips a pass over the maps."""
         torch = _torch()
         s = self.sizes
         pj = self._dev(perm_j, s["nnzj"], torch.int32, "perm_j")
@@ -406,8 +423,13 @@ class Problem:
         jp = self._dev(jvals, s["nnzj"], torch.float64, "jvals")
         hp = self._dev(hvals, s["nnzh"], torch.float64, "hvals")
         gp = None if reg is None else self._dev(reg, s["dim"], torch.float64, "reg")
+        pl = None
+        if plan is not None:
+            cnt = ctypes.c_int64()
+            _check(lib().ocp_mapped_plan_size(self._h, ctypes.byref(cnt)), "ocp_mapped_plan_size")
+            pl = self._dev(plan, cnt.value, torch.int32, "plan")
         out, op = self._out(out, s["nnzk"], "kkt")
-        _check(lib().ocp_assemble_kkt_mapped(self._h, pj, ph, dg, jp, hp, gp, op, self._stream()),
+        _check(lib().ocp_assemble_kkt_mapped(self._h, pj, ph, dg, pl, jp, hp, gp, op, self._stream()),
                "ocp_assemble_kkt_mapped")
         return out
 

@@ -1,5 +1,6 @@
-"""GPU parity of the KKT assembly through slot maps (ocp_assemble_kkt_mapped)
-against the oracle's slot-map assembly, bit for bit: under the node-grouped
+"""GPU parity of the KKT assembly through slot maps (ocp_assemble_kkt_mapped,
+with and without a plan from ocp_mapped_plan) against the oracle's slot-map
+assembly, bit for bit: under the node-grouped
 fill-reducing ordering (every tile staged), under a random ordering (every
 tile falls back to direct stores) and under the natural ordering (where it
 must equal ocp_assemble_kkt); for both models, both schemes and every
@@ -50,11 +51,18 @@ def _check_orders(ocp, prob, rp, ci, pj, ph, jv, hv, stage, seed):
     gj, gh = _dev(jv, hv)
     for name, order in orders.items():
         rp2, ci2, pj2, ph2, dg2 = ocp.kkt_permute(rp, ci, pj, ph, order)
+        maps = _dev(pj2, ph2, dg2)
+        plan = prob.mapped_plan(*maps)
+        pl = plan.cpu().numpy().reshape(-1, 2)
+        assert pl[:, 1].sum() == rp2[-1]  # the tiles' slots partition the KKT
+        if name == "stage":
+            assert np.all(pl[:, 0] >= 0)  # every tile is one contiguous CSR range
         for r in (None, reg):
             rt = None if r is None else _dev(r)[0]
-            got = prob.assemble_kkt_mapped(*_dev(pj2, ph2, dg2), gj, gh, rt).cpu().numpy()
             want = oracle.assemble_mapped(rp2[-1], dg2, pj2, jv, ph2, hv, r)
-            assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (name, r is None)
+            for use_plan in (False, True):
+                got = prob.assemble_kkt_mapped(*maps, gj, gh, rt, plan=plan if use_plan else None).cpu().numpy()
+                assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (name, r is None, use_plan)
         if name == "natural":
             nat = prob.assemble_kkt(*_dev(pj, ph, rp), gj, gh, _dev(reg)[0]).cpu().numpy()
             got = prob.assemble_kkt_mapped(*_dev(pj2, ph2, dg2), gj, gh, _dev(reg)[0]).cpu().numpy()
@@ -117,9 +125,12 @@ def test_mapped_assembly_large(ocp):
     rp2, ci2, pj2, ph2, dg2 = ocp.kkt_permute(rp, ci, pj, ph, ocp.quad_stage_order(N, 1))
     del ci, ci2
     reg = np.full(prob.sizes["dim"], 1e-8)
-    got = prob.assemble_kkt_mapped(*_dev(pj2, ph2, dg2), jv, hv, _dev(reg)[0]).cpu().numpy()
+    maps = _dev(pj2, ph2, dg2)
+    plan = prob.mapped_plan(*maps)
     want = oracle.assemble_mapped(rp2[-1], dg2, pj2, jv.cpu().numpy(), ph2, hv.cpu().numpy(), reg)
-    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    for pl in (None, plan):
+        got = prob.assemble_kkt_mapped(*maps, jv, hv, _dev(reg)[0], plan=pl).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
     prob.close()
     del got, want, jv, hv
     torch.cuda.empty_cache()
