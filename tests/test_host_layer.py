@@ -322,3 +322,30 @@ def test_kkt_permute_rejects_bad_input():
     assert e.value.code == ocp.OCP_ERR_ARG
     with pytest.raises(ocp.OcpError):
         ocp.stage_order(0, 3, 1)
+
+
+def test_newer_entry_points_reject_null_handles_before_any_hip_call():
+    L = ocp.lib()
+    c = ctypes.c_int64()
+    assert L.ocp_mapped_plan_size(None, ctypes.byref(c)) == ocp.OCP_ERR_ARG
+    assert L.ocp_mapped_plan(None, None, None, None, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_assemble_kkt_mapped(None, None, None, None, None, None, None, None, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_eval_kkt(None, None, None, 1.0, None, None, None) == ocp.OCP_ERR_ARG
+    for name in ("ocp_eval_obj", "ocp_eval_grad", "ocp_eval_cons", "ocp_eval_jac"):
+        assert getattr(L, name)(None, None, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_stage_order(10, 3, 1, None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_quad_stage_order(10, 1, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_quad_sizes(10, 1, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_kkt_permute(0, None, None, 0, None, 0, None, None, None, None, None, None, None) == ocp.OCP_ERR_ARG
+    assert b"ocp_kkt_permute" in L.ocp_last_error()
+
+
+def test_quad_pattern_and_kkt_partial_outputs_match_full():
+    """NULL outputs are skipped without touching the others (host only)."""
+    full = ocp.quad_pattern(40, 1)
+    jr, jc, hr, hc = ocp.quad_pattern(40, 1, jac=True, hess=False)
+    assert np.array_equal(jr, full[0]) and np.array_equal(jc, full[1]) and hr is None and hc is None
+    rp, ci, pj, ph = ocp.quad_kkt_pattern(40, 1, colind=False, perm_h=False)
+    full = ocp.quad_kkt_pattern(40, 1)
+    assert ci is None and ph is None
+    assert np.array_equal(rp, full[0]) and np.array_equal(pj, full[2])
