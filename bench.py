@@ -86,10 +86,33 @@ def cpu_baseline(inst, target_s=12.0):
     oracle.hess(inst, 0, K)
     dt = time.perf_counter() - t0
     nnz = K * inst.n * T + K * S
+    # the same on one thread, over a slice sized for about a tenth of target_s
+    K1 = max(1000, min(N, int(K * (target_s / 10) / max(dt * threads, 1e-6))))
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.jac(inst, 0, K1)
+        oracle.hess(inst, 0, K1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    nnz1 = K1 * inst.n * T + K1 * S
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": nnz / dt, "unit": "nonzeros/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle jac on intervals [0,{K}) + hess on nodes [0,{K}) of the "
                       f"N={N} n={inst.n} m={inst.m} workload ({nnz} nonzeros, {dt:.2f} s, "
                       f"OpenMP threads={threads})",
+            "single_thread_value": nnz1 / dt1,
+            "single_thread_sample": f"intervals/nodes [0,{K1}), {nnz1} nonzeros, {dt1:.2f} s",
+            "cpu_model": model,
             "seconds": dt}
 
 
