@@ -22,26 +22,47 @@ SOURCES = [os.path.join(CSRC, "ocp_eval.hip"), os.path.join(CSRC, "ocp_batch.hip
            os.path.join(CSRC, "ocp_fused.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = [
+COMPILE_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,
     "-I", CSRC,
 ]
+# kept for callers that want the single-command form
+FLAGS = [*COMPILE_FLAGS, "-shared"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every source to an object (in parallel, one hipcc per source),
+    then link the shared library.  Always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in SOURCES]
+    cmds = [[HIPCC, *COMPILE_FLAGS, "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1, 16))
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd).returncode
+
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        codes = list(pool.map(run, cmds))
+    bad = [os.path.basename(src) for src, rc in zip(SOURCES, codes) if rc != 0]
+    if bad:
+        raise RuntimeError(f"hipcc failed for {', '.join(bad)}")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp, "-lpthread"]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 
