@@ -293,8 +293,10 @@ int ocp_mapped_plan(const ocp_problem *p, const int32_t *perm_j, const int32_t *
  * ------------------------------------------------------------------------- */
 
 /* Replace the handle's A (n x n), B (n x m; NULL when m = 0) and gamma (n)
- * with device arrays, by stream-ordered device-to-device copies on `stream`.
- * Evaluations queued on other streams must be ordered by the caller. */
+ * with device arrays, by stream-ordered device-to-device copies on `stream`,
+ * followed by a small kernel on `stream` that rebuilds the handle's
+ * column-major copies of A and B.  Evaluations queued on other streams must
+ * be ordered by the caller.  Errors: OCP_ERR_ARG, OCP_ERR_HIP. */
 int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const double *gamma,
                          hipStream_t stream);
 

@@ -46,6 +46,7 @@ struct TileDesc {
 struct BP {
     int n, m, npair, T, S;
     const double *A, *B, *gam, *q, *r;
+    const double *AT, *BT;  // padded columns: n kLd and m kLd doubles per instance
 };
 
 template <int NB, int BS>
@@ -80,6 +81,8 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, const InstDesc *__rest
         P.gam = bp.gam + (int64_t)td.b * bp.n;
         P.q = bp.q + (int64_t)td.b * bp.n;
         P.r = bp.r + (int64_t)td.b * bp.m;
+        P.AT = bp.AT + (int64_t)td.b * bp.n * kLd;
+        P.BT = bp.BT + (int64_t)td.b * bp.m * kLd;
         const double *zb = z + id.z_off;
         if (is_jac) {
             if (td.npt == 2) {
@@ -114,7 +117,7 @@ struct ocp_batch {
     std::vector<int64_t> z_off, c_off, jac_off, hess_off;  // count + 1 each
     int device = 0;
     int cus = 0;
-    double *coef = nullptr;        // device: A | B | gamma | q | r (instance-major blocks)
+    double *coef = nullptr;        // device: A | B | gamma | q | r | AT | BT (instance-major blocks)
     InstDesc *inst = nullptr;      // device offset table
     TileDesc *tiles = nullptr;     // device tile list of the current config
     int ntiles = 0;
@@ -251,6 +254,8 @@ static int batch_launch(const ocp_batch *b, const TileDesc *tiles, int32_t what,
         P.gam = b->bp.gam + (int64_t)i * b->n;
         P.q = b->bp.q + (int64_t)i * b->n;
         P.r = b->bp.r + (int64_t)i * b->m;
+        P.AT = b->bp.AT + (int64_t)i * b->n * kLd;
+        P.BT = b->bp.BT + (int64_t)i * b->m * kLd;
         const double *zb = z + b->z_off[i];
         hipError_t e = hipSuccess;
         if (what & OCP_EVAL_JAC) e = launch_jac(P, zb, jac + b->jac_off[i], pair_ok, s);
@@ -312,7 +317,9 @@ int ocp_batch_create(int32_t count, const int64_t *Ns, int32_t n, int32_t m, con
         delete b;
         return hip_fail_b("ocp_batch_create", e);
     }
-    const size_t ncoef = nA + nB + 2 * nV + nR;
+    const size_t nplain = nA + nB + 2 * nV + nR;
+    const size_t nAT = (size_t)count * n * kLd, nBT = (size_t)count * m * kLd;
+    const size_t ncoef = nplain + nAT + nBT;
     e = hipMalloc(&b->coef, ncoef * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&b->inst, (size_t)count * sizeof(InstDesc));
     if (e != hipSuccess) {
@@ -326,6 +333,10 @@ int ocp_batch_create(int32_t count, const int64_t *Ns, int32_t n, int32_t m, con
     std::memcpy(host.data() + o, gamma, nV * sizeof(double)); o += nV;
     std::memcpy(host.data() + o, q, nV * sizeof(double)); o += nV;
     if (nR) std::memcpy(host.data() + o, r, nR * sizeof(double));
+    for (int32_t i = 0; i < count; i++)
+        pack_columns(n, m, A + (size_t)i * n * n, B ? B + (size_t)i * n * m : nullptr,
+                     host.data() + nplain + (size_t)i * n * kLd,
+                     host.data() + nplain + nAT + (size_t)i * m * kLd);
     std::vector<InstDesc> inst(count);
     for (int32_t i = 0; i < count; i++) {
         inst[i].z_off = b->z_off[i];
@@ -354,6 +365,8 @@ int ocp_batch_create(int32_t count, const int64_t *Ns, int32_t n, int32_t m, con
     b->bp.gam = b->bp.B + nB;
     b->bp.q = b->bp.gam + nV;
     b->bp.r = b->bp.q + nV;
+    b->bp.AT = b->coef + nplain;
+    b->bp.BT = b->bp.AT + nAT;
     rc = upload_tiles(b, b->cfg);
     if (rc) {
         std::string msg = ocp_last_error();

@@ -43,7 +43,26 @@ struct KP {
     const double *gam;  // n
     const double *q;    // n
     const double *r;    // m
+    const double *AT;   // n columns of kLd: AT[j kLd + i] = A_ij (i < n), 0 (n <= i < kLd)
+    const double *BT;   // m columns of kLd: BT[l kLd + i] = B_il (i < n), 0 (n <= i < kLd)
 };
+
+// Column stride of the padded copies AT and BT (the bound on n).  A kernel
+// whose register bound NB <= kLd sums a column over all NB rows without a
+// guard, the padding adding exact zeros; the column's entries are contiguous
+// at offsets known at compile time, so a wavefront fetches them with a few
+// wide scalar loads instead of one load per coefficient behind a branch.
+constexpr int kLd = 32;
+
+// Host side: the padded copies of one instance's A (n x n) and B (n x m),
+// both row-major, into AT (n kLd doubles) and BT (m kLd doubles).
+inline void pack_columns(int n, int m, const double *A, const double *B, double *AT, double *BT)
+{
+    for (int j = 0; j < n; j++)
+        for (int i = 0; i < kLd; i++) AT[j * kLd + i] = i < n ? A[i * n + j] : 0.0;
+    for (int l = 0; l < m; l++)
+        for (int i = 0; i < kLd; i++) BT[l * kLd + i] = i < n ? B[i * m + l] : 0.0;
+}
 
 // Cost weight of node k: trapezoidal rule (end nodes h/2), or the forward
 // Euler sum over nodes 0..N-1 (weight h, none at node N).
@@ -196,10 +215,10 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
     for (int j = 0; j < NB; j++) {
         if (j < n) {
             const double sx = sin(x[j]);
+            const double *a = P.AT + j * kLd;
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) s += yt[i] * P.A[i * n + j];
+            for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
             if (n == 1) v -= P.h * yt[0] * P.gam[0];
             st_nt(hv + j * N1 + k, v);
@@ -237,16 +256,16 @@ __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__
     for (int j = 0; j < NB; j++) {
         if (j < n) {
             const double s = sin(x[j]);
+            const double *a = P.AT + j * kLd;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) F[i] += P.A[i * n + j] * s;
+            for (int i = 0; i < NB; i++) F[i] = __builtin_fma(a[i], s, F[i]);
         }
     }
     for (int l = 0; l < m; l++) {
         const double u = U[(int64_t)l * P.NU + k];
+        const double *b = P.BT + l * kLd;
 #pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < n) F[i] += P.B[i * m + l] * u;
+        for (int i = 0; i < NB; i++) F[i] = __builtin_fma(b[i], u, F[i]);
     }
 #pragma unroll
     for (int i = 0; i < NB; i++) {
@@ -360,10 +379,10 @@ __device__ __forceinline__ void hess_node_euler(const KP &P, const double *__res
     for (int j = 0; j < NB; j++) {
         if (j < n) {
             const double sx = sin(x[j]);
+            const double *a = P.AT + j * kLd;
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) s += yt[i] * P.A[i * n + j];
+            for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             double v = 2.0 * sigma * w * P.q[j] + h * sx * s;
             if (n == 1) v -= 2.0 * h * yt[0] * P.gam[0];
             st_nt(hv + j * N1 + k, v);

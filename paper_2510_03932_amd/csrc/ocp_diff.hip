@@ -150,10 +150,10 @@ __global__ __launch_bounds__(kBlock) void lag_grad_kernel(KP P, const double *__
 #pragma unroll
     for (int j = 0; j < NB; j++) {
         if (j < n) {
+            const double *a = P.AT + j * kLd;
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) s += yt[i] * P.A[i * n + j];
+            for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             const double xn = (j + 1 < n) ? x[(j + 1) % NB] : x[0];
             const int jm = (j == 0) ? n - 1 : j - 1;
             const double xm = (j == 0) ? x_last : x[(j + NB - 1) % NB];
@@ -164,10 +164,10 @@ __global__ __launch_bounds__(kBlock) void lag_grad_kernel(KP P, const double *__
     }
     const double *U = z + (int64_t)n * N1;
     for (int l = 0; l < m; l++) {
+        const double *b = P.BT + l * kLd;
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < n) s += yt[i] * P.B[i * m + l];
+        for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], b[i], s);
         st_nt(g + (n + l) * N1 + k, 2.0 * sigma * w * P.r[l] * U[l * N1 + k] - P.hh * s);
     }
 }
@@ -194,10 +194,10 @@ __global__ __launch_bounds__(kBlock) void hvp_kernel(KP P, const double *__restr
 #pragma unroll
     for (int j = 0; j < NB; j++) {
         if (j < n) {
+            const double *a = P.AT + j * kLd;
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) s += (yl[i] + yr[i]) * P.A[i * n + j];
+            for (int i = 0; i < NB; i++) s = __builtin_fma(yl[i] + yr[i], a[i], s);
             const double d = 2.0 * sigma * w * P.q[j] + P.hh * sin(x[j]) * s;
             const double vn = (j + 1 < n) ? vx[(j + 1) % NB] : vx[0];
             const double vm = (j == 0) ? v_last : vx[(j + NB - 1) % NB];
@@ -236,16 +236,16 @@ __global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restr
         for (int j = 0; j < NB; j++) {
             if (j < n) {
                 const double t = cos(x[j]) * vx[j];
+                const double *a = P.AT + j * kLd;
 #pragma unroll
-                for (int i = 0; i < NB; i++)
-                    if (i < n) D[i] += P.A[i * n + j] * t;
+                for (int i = 0; i < NB; i++) D[i] = __builtin_fma(a[i], t, D[i]);
             }
         }
         for (int l = 0; l < m; l++) {
             const double u = v[(n + l) * N1 + k];
+            const double *b = P.BT + l * kLd;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) D[i] += P.B[i * m + l] * u;
+            for (int i = 0; i < NB; i++) D[i] = __builtin_fma(b[i], u, D[i]);
         }
 #pragma unroll
         for (int i = 0; i < NB; i++) {
@@ -333,6 +333,21 @@ __global__ __launch_bounds__(kBlock) void coef_final_kernel(KP P, const double *
 
 int nb_of(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
+// Rebuild the padded columns AT, BT (kLd rows each, zero below row n) from
+// the row-major A and B, on the device so that a coefficient update stays
+// asynchronous on the caller's stream.
+__global__ __launch_bounds__(kBlock) void pack_columns_kernel(int n, int m, const double *__restrict__ A,
+                                                              const double *__restrict__ B,
+                                                              double *__restrict__ AT,
+                                                              double *__restrict__ BT)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= (n + m) * kLd) return;
+    const int c = e / kLd, i = e % kLd;
+    if (c < n) AT[e] = i < n ? A[i * n + c] : 0.0;
+    else BT[e - n * kLd] = i < n ? B[i * m + (c - n)] : 0.0;
+}
+
 }  // namespace
 
 #define OCP_DISPATCH_NB(n, KERNEL, grid, ...)                                                   \
@@ -365,7 +380,10 @@ int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const
         e = hipMemcpyAsync(const_cast<double *>(p->kp.gam), gamma, sizeof(double) * n,
                            hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return hip_fail("ocp_set_coefficients", e);
-    return OCP_OK;
+    hipLaunchKernelGGL(pack_columns_kernel, dim3(blocks_for((int64_t)(n + m) * kLd, kBlock)),
+                       dim3(kBlock), 0, stream, n, m, p->kp.A, p->kp.B,
+                       const_cast<double *>(p->kp.AT), const_cast<double *>(p->kp.BT));
+    return check_launch("ocp_set_coefficients");
 }
 
 int ocp_eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma,

@@ -417,7 +417,9 @@ int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const
     p->d = d;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { delete p; return hip_fail("ocp_create: hipGetDevice", e); }
-    const size_t ncoef = (size_t)n * n + (size_t)n * m + 3 * (size_t)n + (size_t)m;
+    static_assert(kLd == OCP_MAX_DIM, "padded coefficient columns hold up to OCP_MAX_DIM rows");
+    const size_t nplain = (size_t)n * n + (size_t)n * m + 3 * (size_t)n + (size_t)m;
+    const size_t ncoef = nplain + (size_t)(n + m) * kLd;
     e = hipMalloc(&p->coef, ncoef * sizeof(double));
     if (e != hipSuccess) { delete p; return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e)); }
     e = hipMalloc(&p->partials, kObjBlocks * sizeof(double));
@@ -435,6 +437,7 @@ int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const
     std::memcpy(host + o, gamma, sizeof(double) * n); o += n;
     std::memcpy(host + o, q, sizeof(double) * n); o += n;
     if (m) std::memcpy(host + o, r, sizeof(double) * m);
+    pack_columns(n, m, A, B, host + nplain, host + nplain + (size_t)n * kLd);
     e = hipMemcpy(p->coef, host, ncoef * sizeof(double), hipMemcpyHostToDevice);
     delete[] host;
     if (e != hipSuccess) { ocp_destroy(p); return hip_fail("ocp_create: hipMemcpy", e); }
@@ -458,6 +461,8 @@ int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const
     kp.gam = kp.B + (size_t)n * m;
     kp.q = kp.gam + n;
     kp.r = kp.q + n;
+    kp.AT = p->coef + nplain;
+    kp.BT = kp.AT + (size_t)n * kLd;
     *out = p;
     return OCP_OK;
 }

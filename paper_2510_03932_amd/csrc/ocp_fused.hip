@@ -139,10 +139,10 @@ __global__ __launch_bounds__(kBlock) void kkt_var_kernel(KP P, KKTLayout Lo, con
         dg[j] = 0.0;
         if (j < n) {
             const double sx = sin(x[j]);
+            const double *a = P.AT + j * kLd;
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NB; i++)
-                if (i < n) s += yt[i] * P.A[i * n + j];
+            for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
             if (n == 1) v -= P.h * yt[0] * P.gam[0];
             if (live && reg) v += reg[j * N1 + k];

@@ -17,7 +17,7 @@ constexpr int kCoefBlocks = 256;
 struct ocp_problem {
     ocp::Dims d;
     int device;
-    double *coef;       // device: A | B | gamma | q | r
+    double *coef;       // device: A | B | gamma | q | r | AT | BT (padded columns, kLd each)
     double *partials;   // device: kObjBlocks doubles (objective and Lagrangian sums)
     double *cpart;      // device: n (n+m+1) kCoefBlocks doubles (coefficient-gradient sums)
     ocp::dev::KP kp;
