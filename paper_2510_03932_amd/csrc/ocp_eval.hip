@@ -167,20 +167,32 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__rest
 // shuffles) and over the 4 waves; pass 2: one workgroup sums the partials in a
 // fixed order.  The grid depends only on N, so the result is reproducible.
 // ---------------------------------------------------------------------------
+template <int NB>
 __global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double *__restrict__ z,
                                                              double *__restrict__ partials)
 {
-    const int n = P.n, nc = P.n + P.m;
-    const int64_t N1 = P.N1;
+    const int n = P.n, m = P.m;
+    const int64_t N1 = P.N1, NU = P.NU;
+    const double *U = z + (int64_t)n * N1;
     double acc = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N1;
          k += (int64_t)gridDim.x * kBlock) {
+        // every load of a group is issued before its products are summed
+        double v[NB];
+#pragma unroll
+        for (int c = 0; c < NB; c++) v[c] = c < n ? z[c * N1 + k] : 0.0;
         double s = 0.0;
-#pragma unroll 8
-        for (int c = 0; c < nc; c++) {
-            if (c >= n && k >= P.NU) continue;  // controls exist on NU nodes
-            const double v = c < n ? z[c * N1 + k] : z[n * N1 + (c - n) * (int64_t)P.NU + k];
-            s += (c < n ? P.q[c] : P.r[c - n]) * v * v;
+#pragma unroll
+        for (int c = 0; c < NB; c++)
+            if (c < n) s += P.q[c] * v[c] * v[c];
+        if (k < NU) {  // controls exist on NU nodes
+            for (int l0 = 0; l0 < m; l0 += NB) {
+#pragma unroll
+                for (int u = 0; u < NB; u++) v[u] = l0 + u < m ? U[(l0 + u) * NU + k] : 0.0;
+#pragma unroll
+                for (int u = 0; u < NB; u++)
+                    if (l0 + u < m) s += P.r[l0 + u] * v[u] * v[u];
+            }
         }
         acc += node_weight(P, (int)k) * s;
     }
@@ -492,7 +504,11 @@ int ocp_eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t
     if (!z || !obj) return fail(OCP_ERR_ARG, "ocp_eval_obj: null array");
     if (p->model == quad::kModel) return quad::eval_obj(p, z, obj, stream);
     const unsigned g = (unsigned)std::min<int64_t>(kObjBlocks, blocks_for(p->d.N1, kBlock));
-    hipLaunchKernelGGL(obj_partial_kernel, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
+    const int n = p->d.n;
+    if (n <= 4) hipLaunchKernelGGL(obj_partial_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
+    else if (n <= 8) hipLaunchKernelGGL(obj_partial_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
+    else if (n <= 16) hipLaunchKernelGGL(obj_partial_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
+    else hipLaunchKernelGGL(obj_partial_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
     if (int rc = check_launch("ocp_eval_obj")) return rc;
     hipLaunchKernelGGL(obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, (int)g, obj);
     return check_launch("ocp_eval_obj");
