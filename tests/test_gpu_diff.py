@@ -89,10 +89,15 @@ def test_deterministic(ocp):
     prob.close()
 
 
-def test_set_coefficients(ocp):
-    """Coefficients pushed from device tensors replace the ones given at creation."""
-    inst = synth.make_instance(400, 5, 2, seed=4)
-    other = synth.make_instance(400, 5, 2, seed=5)
+@pytest.mark.parametrize("N,n,m", [(400, 5, 2), (300, 16, 8), (200, 3, 0), (100, 20, 32)])
+def test_set_coefficients(ocp, N, n, m):
+    """Coefficients pushed from device tensors replace the ones given at
+    creation, including the handle's padded column copies: every evaluation
+    afterwards is bitwise equal to that of a handle created with the new
+    coefficients, and the defects and grad_z L match the oracle."""
+    _say(f"[set_coefficients] N={N} n={n} m={m}")
+    inst = synth.make_instance(N, n, m, seed=4)
+    other = synth.make_instance(N, n, m, seed=5)
     dev, z, y, v, vt = _dev_inputs(inst)
     prob = ocp.Problem.from_instance(other, dev)
     prob.set_coefficients(*(torch.from_numpy(a).to(dev) for a in (inst.A, inst.B, inst.gamma)))
@@ -102,6 +107,14 @@ def test_set_coefficients(ocp):
     c = prob.cons(z).cpu().numpy()
     want, mu = oracle.cons(inst)
     check_close(c, want, mu, what="cons after set_coefficients")
+    fresh = ocp.Problem.from_instance(inst, dev)
+    for name, fn in (("cons", lambda P: P.cons(z)), ("jac", lambda P: P.jac(z)),
+                     ("hess", lambda P: P.hess(z, y, 0.9)), ("lag_grad", lambda P: P.lag_grad(z, y, 0.9)),
+                     ("hvp", lambda P: P.hvp(z, y, vt, 0.9)), ("jvp", lambda P: P.jvp(z, vt)),
+                     ("eval_kkt", lambda P: P.eval_kkt(z, y, 0.9))):
+        a, b = fn(prob), fn(fresh)
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64)), name
+    fresh.close()
     prob.close()
 
 

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 
 CASES = [(s, b) for s in (0, 1) for b in (0, 1, 2)]
 SHAPES = [(1000, 4, 2), (777, 5, 3), (1, 1, 0), (2, 2, 1), (3, 3, 0), (257, 16, 8), (513, 32, 32),
-          (4096, 8, 4)]
+          (4096, 8, 4), (60, 2, 9)]
 
 
 def _say(msg):

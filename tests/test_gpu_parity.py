@@ -37,6 +37,8 @@ SHAPES = [
     (4097, 8, 4),
     (513, 32, 32),
     (100, 17, 0),
+    (50, 2, 9),
+    (33, 5, 20),
 ]
 
 
