@@ -439,9 +439,13 @@ class Problem:
         (stream-ordered on the current stream)."""
         torch = _torch()
         n, m = self.n, self.m
-        Ap = self._dev(A.contiguous(), n * n, torch.float64, "A")
-        Bp = self._dev(B.contiguous(), n * m, torch.float64, "B") if m else None
-        gp = self._dev(gamma.contiguous(), n, torch.float64, "gamma")
+        # the contiguous copies stay referenced until the copies are queued:
+        # a freed temporary could be handed to the next temporary's copy kernel
+        A, gamma = A.contiguous(), gamma.contiguous()
+        B = B.contiguous() if m else None
+        Ap = self._dev(A, n * n, torch.float64, "A")
+        Bp = self._dev(B, n * m, torch.float64, "B") if m else None
+        gp = self._dev(gamma, n, torch.float64, "gamma")
         _check(lib().ocp_set_coefficients(self._h, Ap, Bp, gp, self._stream()), "ocp_set_coefficients")
 
     def lagrangian(self, z, y, sigma=1.0, out=None):

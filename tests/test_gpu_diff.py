@@ -89,18 +89,32 @@ def test_deterministic(ocp):
     prob.close()
 
 
+def _strided(a, dev):
+    """The values of a as a non-contiguous device tensor."""
+    if a.ndim == 2:
+        return torch.from_numpy(np.ascontiguousarray(a.T)).to(dev).t()
+    return torch.from_numpy(np.repeat(a, 2)).to(dev)[::2]
+
+
+@pytest.mark.parametrize("layout", ["contiguous", "strided"])
 @pytest.mark.parametrize("N,n,m", [(400, 5, 2), (300, 16, 8), (200, 3, 0), (100, 20, 32)])
-def test_set_coefficients(ocp, N, n, m):
-    """Coefficients pushed from device tensors replace the ones given at
-    creation, including the handle's padded column copies: every evaluation
-    afterwards is bitwise equal to that of a handle created with the new
-    coefficients, and the defects and grad_z L match the oracle."""
-    _say(f"[set_coefficients] N={N} n={n} m={m}")
+def test_set_coefficients(ocp, N, n, m, layout):
+    """Coefficients pushed from device tensors (contiguous, or strided views
+    that the binding copies first) replace the ones given at creation,
+    including the handle's padded column copies: every evaluation afterwards
+    is bitwise equal to that of a handle created with the new coefficients,
+    and the defects and grad_z L match the oracle."""
+    _say(f"[set_coefficients] N={N} n={n} m={m} {layout}")
     inst = synth.make_instance(N, n, m, seed=4)
     other = synth.make_instance(N, n, m, seed=5)
     dev, z, y, v, vt = _dev_inputs(inst)
     prob = ocp.Problem.from_instance(other, dev)
-    prob.set_coefficients(*(torch.from_numpy(a).to(dev) for a in (inst.A, inst.B, inst.gamma)))
+    if layout == "strided":
+        coefs = [_strided(a, dev) for a in (inst.A, inst.B, inst.gamma)]
+        assert not any(t.is_contiguous() for t in coefs if t.numel() > 1)
+    else:
+        coefs = [torch.from_numpy(a).to(dev) for a in (inst.A, inst.B, inst.gamma)]
+    prob.set_coefficients(*coefs)
     got = prob.lag_grad(z, y, 1.0).cpu().numpy()
     want, mu = oracle.lag_grad(inst)
     check_close(got, want, mu, what="after set_coefficients")
