@@ -149,8 +149,32 @@ def ipm_loop(torch, ocp, synth, iters=50):
         torch.cuda.synchronize()
         if it >= 3:  # the first three are warm-up
             times.append(e0.elapsed_time(e1))
+    # the same four calls captured once in a HIP graph and replayed, each
+    # iteration's point copied into the captured inputs outside the timing
+    zs, ys = synth.device_point(torch, dev, N, n, m, 1000)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        prob.cons(zs, out=c)
+        prob.jac(zs, out=jv)
+        prob.hess(zs, ys, 1.0, out=hv)
+        prob.assemble_kkt(pj, ph, rp, jv, hv, reg, out=kkt)
+    gtimes = []
+    for it in range(iters + 3):
+        z, y = synth.device_point(torch, dev, N, n, m, 1000 + (it % iters))
+        zs.copy_(z)
+        ys.copy_(y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if it >= 3:
+            gtimes.append(e0.elapsed_time(e1))
+    del graph
     prob.close()
     ms = float(np.median(times))
+    gms = float(np.median(gtimes))
     return {"workload": f"N={N} n={n} m={m}, {iters} iterations of cons+jac+hess+assemble_kkt "
                         "at fresh device-drawn points",
             "ms_per_iteration": round(ms, 4),
@@ -158,6 +182,9 @@ def ipm_loop(torch, ocp, synth, iters=50):
             "p10_ms": round(float(np.percentile(times, 10)), 4),
             "p90_ms": round(float(np.percentile(times, 90)), 4),
             "jac_hess_nnz_per_s_in_loop": (s["nnzj"] + s["nnzh"]) / (ms * 1e-3),
+            "graph_ms_per_iteration": round(gms, 4),
+            "graph_p10_ms": round(float(np.percentile(gtimes, 10)), 4),
+            "graph_p90_ms": round(float(np.percentile(gtimes, 90)), 4),
             "note": "J+H values fit in the 256 MiB Infinity Cache"}
 
 
@@ -373,6 +400,30 @@ def quadrotor(torch, ocp, synth, reps=10):
         r["step_ms"] = round(sum(r[k]["ms"] for k in calls), 4)
         t = (r["eval_jac"]["ms"] + r["eval_hess"]["ms"]) * 1e-3
         r["jac_hess_nnz_per_s"] = (s["nnzj"] + s["nnzh"]) / t
+
+        # the six calls back to back as one step, eagerly and replayed from a
+        # HIP graph captured once
+        def step():
+            for fn, _ in calls.values():
+                fn()
+
+        def timed_steps(run):
+            run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        r["eager_step_ms"] = round(timed_steps(step), 4)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        r["graph_step_ms"] = round(timed_steps(graph.replay), 4)
+        del graph
         prob.close()
         del pj, ph, rp, jv, hv, kkt
         torch.cuda.empty_cache()

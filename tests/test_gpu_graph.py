@@ -1,0 +1,119 @@
+"""The evaluation calls captured in a HIP graph (torch.cuda.CUDAGraph on the
+current stream, which the binding passes to the library): none of them
+allocates or clears memory with a memset, so a whole step can be captured
+once and replayed.  Each replay runs at a new point copied into the captured
+input tensors, with eager evaluations of the same point between the replays,
+and every output of every replay must equal the eager one bit for bit (the
+kernels and their reduction orders are the same)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ocp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_03932_amd as ocp
+    ocp.lib()
+    return ocp
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda", 0))
+
+
+def _outputs(prob, fused):
+    s = prob.sizes
+    f64 = dict(dtype=torch.float64, device=torch.device("cuda", 0))
+    names = {"obj": 1, "grad": s["nvar"], "cons": s["ncon"], "jac": s["nnzj"], "hess": s["nnzh"],
+             "kkt": s["nnzk"]}
+    if fused:
+        names["kkt_fused"] = s["nnzk"]
+    return {k: torch.full((v,), float("nan"), **f64) for k, v in names.items()}
+
+
+def _step(prob, maps, z, y, reg, o, fused):
+    pj, ph, rp = maps
+    prob.obj(z, out=o["obj"])
+    prob.grad(z, out=o["grad"])
+    prob.cons(z, out=o["cons"])
+    prob.jac(z, out=o["jac"])
+    prob.hess(z, y, 0.8, out=o["hess"])
+    prob.assemble_kkt(pj, ph, rp, o["jac"], o["hess"], reg, out=o["kkt"])
+    if fused:
+        prob.eval_kkt(z, y, 0.8, reg, out=o["kkt_fused"])
+
+
+def _points(make, count):
+    return [make(seed) for seed in range(100, 100 + count)]
+
+
+def _run(ocp, prob, pattern, points, fused):
+    dev = torch.device("cuda", 0)
+    rowptr, _, perm_j, perm_h = pattern
+    maps = tuple(_t(a) for a in (perm_j, perm_h, rowptr))
+    reg = torch.linspace(1e-6, 2e-6, prob.sizes["dim"], dtype=torch.float64, device=dev)
+    zs, ys = _t(points[0][0]).clone(), _t(points[0][1]).clone()
+    outs = _outputs(prob, fused)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        _step(prob, maps, zs, ys, reg, outs, fused)
+    torch.cuda.synchronize()
+    for r, (z, y) in enumerate(points):
+        ref = _outputs(prob, fused)
+        _step(prob, maps, _t(z), _t(y), reg, ref, fused)  # eager, same point
+        torch.cuda.synchronize()
+        zs.copy_(_t(z))
+        ys.copy_(_t(y))
+        g.replay()
+        torch.cuda.synchronize()
+        for k in outs:
+            assert torch.equal(outs[k].view(torch.int64), ref[k].view(torch.int64)), (r, k)
+        assert not torch.isnan(outs["kkt"]).any()
+    del g
+
+
+@pytest.mark.parametrize("N,n,m,scheme,bnd", [(3000, 6, 3, 0, 0), (1001, 16, 8, 0, 1), (777, 5, 2, 1, 2)])
+def test_graph_replays_equal_eager_synthetic(ocp, N, n, m, scheme, bnd):
+    _say(f"[graph] synthetic N={N} n={n} m={m} scheme={scheme} bnd={bnd}")
+    base = synth.make_instance(N, n, m, seed=61, scheme=scheme, bnd=bnd)
+    prob = ocp.Problem.from_instance(base, torch.device("cuda", 0))
+
+    def point(seed):
+        other = synth.make_instance(N, n, m, seed=seed, scheme=scheme, bnd=bnd)
+        return other.z, other.y
+
+    pattern = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd, colind=False)
+    _run(ocp, prob, pattern, _points(point, 3), fused=(scheme == 0))
+    prob.close()
+
+
+@pytest.mark.parametrize("N,bnd", [(2000, 1), (333, 0)])
+def test_graph_replays_equal_eager_quadrotor(ocp, N, bnd):
+    _say(f"[graph] quadrotor N={N} bnd={bnd}")
+    prob = ocp.QuadrotorProblem.from_instance(synth.make_quadrotor(N, seed=62, bnd=bnd),
+                                              torch.device("cuda", 0))
+
+    def point(seed):
+        q = synth.make_quadrotor(N, seed=seed, bnd=bnd)
+        return q.z, q.y
+
+    pattern = ocp.quad_kkt_pattern(N, bnd, colind=False)
+    _run(ocp, prob, pattern, _points(point, 3), fused=False)
+    prob.close()
