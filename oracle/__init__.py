@@ -9,6 +9,7 @@ of the objective and constraints used to pin the C oracle.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -244,6 +245,92 @@ class Oracle:
                                     _p(mg)), "coef_grad")
         return (gA, gB, gg), (mA, mB, mg)
 
+    # ---- Lagrangian derivatives for every scheme and boundary option --------
+    # The definitions written out over the oracle's own _ex arrays:
+    # L = sigma f + y^T c, grad_z L = sigma grad f + J^T y, (Hessian of L) v
+    # from the lower-triangle Hessian, J v, and dL/dtheta = y^T dc/dtheta for
+    # theta = (A, B, gamma), where the defects are linear in theta.  The sparse
+    # products are scatter-adds in COO order (numpy bincount); each mu is the
+    # same sum over the entries' magnitudes (the _ex arrays' own mu) times |y|
+    # or |v|.  The paper's Sec. 8 names differentiable programming as future
+    # work; the scheme and boundary rows follow Sec. 3 and Sec. 4.
+    def lagrangian_ex(self, inst, scheme=0, bnd=0, sigma=None, y=None):
+        """(L, mu_L); y has ncon entries (defect rows, then boundary rows)."""
+        sigma = inst.sigma if sigma is None else sigma
+        y = _d(inst.y if y is None else y)
+        f, fmu = self.obj_ex(inst, scheme, bnd)
+        c, cmu = self.cons_ex(inst, scheme, bnd)
+        yc = math.fsum(y * c)
+        return sigma * f + yc, abs(sigma) * fmu + float(np.abs(y) @ cmu)
+
+    def lag_grad_ex(self, inst, scheme=0, bnd=0, sigma=None, y=None):
+        """grad_z L (nvar entries, the layout of z) and its mu."""
+        sigma = inst.sigma if sigma is None else sigma
+        y = _d(inst.y if y is None else y)
+        g, gmu = self.grad_ex(inst, scheme, bnd)
+        jv, jmu = self.jac_ex(inst, scheme, bnd)
+        jr, jc, _, _ = self.pattern_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        nv = len(g)
+        out = sigma * g + np.bincount(jc, weights=jv * y[jr], minlength=nv)
+        mu = abs(sigma) * gmu + np.bincount(jc, weights=jmu * np.abs(y[jr]), minlength=nv)
+        return out, mu
+
+    def hvp_ex(self, inst, v, scheme=0, bnd=0, sigma=None, y=None):
+        """(Hessian of L) v and its mu; the Hessian is the symmetric matrix
+        whose lower triangle hess_ex holds."""
+        v = _d(v)
+        hv, hmu = self.hess_ex(inst, scheme, bnd, sigma, y)
+        _, _, hr, hc = self.pattern_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        nv = len(v)
+        off = hr != hc
+        out = (np.bincount(hr, weights=hv * v[hc], minlength=nv)
+               + np.bincount(hc[off], weights=hv[off] * v[hr[off]], minlength=nv))
+        mu = (np.bincount(hr, weights=hmu * np.abs(v[hc]), minlength=nv)
+              + np.bincount(hc[off], weights=hmu[off] * np.abs(v[hr[off]]), minlength=nv))
+        return out, mu
+
+    def jvp_ex(self, inst, v, scheme=0, bnd=0):
+        """J v (ncon entries, the layout of c) and its mu."""
+        v = _d(v)
+        jv, jmu = self.jac_ex(inst, scheme, bnd)
+        jr, jc, _, _ = self.pattern_ex(inst.N, inst.n, inst.m, scheme, bnd)
+        nc = self.sizes_ex(inst.N, inst.n, inst.m, scheme, bnd)["ncon"]
+        out = np.bincount(jr, weights=jv * v[jc], minlength=nc)
+        mu = np.bincount(jr, weights=jmu * np.abs(v[jc]), minlength=nc)
+        return out, mu
+
+    def coef_grad_ex(self, inst, scheme=0, bnd=0, y=None):
+        """(dL/dA, dL/dB, dL/dgamma) and their mu arrays.  With S = sin X and
+        Y the defect multipliers as an n x N matrix (boundary rows do not
+        depend on the coefficients):
+          trapezoidal  dc_ik/dA_ij = -h/2 (S_jk + S_j,k+1), dc_ik/dB_il = -h/2 (U_lk + U_l,k+1),
+                       dc_ik/dgamma_i = -h/2 (X_ik X_pk + X_i,k+1 X_p,k+1);
+          Euler        dc_ik/dA_ij = -h S_jk, dc_ik/dB_il = -h U_lk, dc_ik/dgamma_i = -h X_ik X_pk,
+        with p = (i+1) mod n; the sums over k are matrix products."""
+        N, n, m = inst.N, inst.n, inst.m
+        y = _d(inst.y if y is None else y)
+        NU = N + 1 if scheme == 0 else N
+        X = _d(inst.z[:n * (N + 1)]).reshape(n, N + 1)
+        U = _d(inst.z[n * (N + 1):]).reshape(m, NU)
+        Y = y[:n * N].reshape(n, N)
+        S = np.sin(X)
+        P = X * X[(np.arange(n) + 1) % n]
+        if scheme == 0:
+            w = 0.5 * (1.0 / N)
+            SA, UB, PG = S[:, :N] + S[:, 1:], U[:, :N] + U[:, 1:], P[:, :N] + P[:, 1:]
+            SAm = np.abs(S[:, :N]) + np.abs(S[:, 1:])
+            UBm = np.abs(U[:, :N]) + np.abs(U[:, 1:])
+            PGm = np.abs(P[:, :N]) + np.abs(P[:, 1:])
+        else:
+            w = 1.0 / N
+            SA, UB, PG = S[:, :N], U, P[:, :N]
+            SAm, UBm, PGm = np.abs(SA), np.abs(UB), np.abs(PG)
+        Ya = np.abs(Y)
+        gA, mA = -w * (Y @ SA.T), w * (Ya @ SAm.T)
+        gB, mB = -w * (Y @ UB.T), w * (Ya @ UBm.T)
+        gg, mg = -w * np.sum(Y * PG, axis=1), w * np.sum(Ya * PGm, axis=1)
+        return (gA, gB, gg), (mA, mB, mg)
+
     # ---- schemes (0 trapezoidal, 1 forward Euler) and boundary rows --------
     def sizes_ex(self, N, n, m, scheme=0, bnd=0) -> dict:
         out = np.zeros(10, np.int64)
@@ -430,6 +517,11 @@ lag_grad = DEFAULT.lag_grad
 hvp = DEFAULT.hvp
 jvp = DEFAULT.jvp
 coef_grad = DEFAULT.coef_grad
+lagrangian_ex = DEFAULT.lagrangian_ex
+lag_grad_ex = DEFAULT.lag_grad_ex
+hvp_ex = DEFAULT.hvp_ex
+jvp_ex = DEFAULT.jvp_ex
+coef_grad_ex = DEFAULT.coef_grad_ex
 sizes_ex = DEFAULT.sizes_ex
 obj_ex = DEFAULT.obj_ex
 grad_ex = DEFAULT.grad_ex

@@ -1,0 +1,175 @@
+"""Pins of the oracle's Lagrangian derivatives under every scheme and boundary
+option (trapezoidal or forward Euler; no boundary rows, initial-state rows,
+or initial- and final-state rows): L = sigma f + y^T c, grad_z L, (Hessian
+of L) v, J v and dL/d(A, B, gamma), against a 50-digit evaluation,
+complex-step and mixed differences of the independent definition module, and
+against the C oracle's own trapezoidal functions."""
+from __future__ import annotations
+
+import cmath
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import defn
+from tests.helpers import check_close
+
+CASES = [(scheme, bnd) for scheme in (0, 1) for bnd in (0, 1, 2)]
+SHAPES = [(1, 1, 0), (2, 1, 1), (3, 2, 1), (4, 3, 1), (3, 5, 0), (5, 3, 2)]
+
+
+def _inst(N, n, m, seed, scheme, bnd):
+    return synth.make_instance(N, n, m, seed=seed, scheme=scheme, bnd=bnd)
+
+
+def _L(inst, z, y, sigma, A=None, B=None, gamma=None, sin=cmath.sin):
+    A0, B0, g0, q, r = defn.as_lists(inst)
+    return defn.lagrangian_ex(z, y, sigma, inst.N, inst.n, inst.m, A if A is not None else A0,
+                              B if B is not None else B0, gamma if gamma is not None else g0, q, r,
+                              inst.scheme, inst.bnd, sin=sin)
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+def test_lagrangian_ex_high_precision(orc, scheme, bnd):
+    import mpmath
+    mpmath.mp.dps = 50
+    inst = _inst(9, 3, 2, 200 + 3 * scheme + bnd, scheme, bnd)
+    Lo, mu = orc.lagrangian_ex(inst, scheme, bnd, sigma=1.3)
+    mp = mpmath.mpf
+    A, B, g, q, r = defn.as_lists(inst)
+    cv = lambda x: [mp(v) for v in x]
+    want = defn.lagrangian_ex(cv(inst.z), cv(inst.y), mp(1.3), inst.N, 3, 2, [cv(a) for a in A],
+                              [cv(b) for b in B], cv(g), cv(q), cv(r), scheme, bnd, sin=mpmath.sin,
+                              dt=mp(1) / inst.N)
+    assert abs(Lo - float(want)) <= 1e-13 * mu
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+@pytest.mark.parametrize("N,n,m", SHAPES)
+def test_lag_grad_ex_complex_step(orc, N, n, m, scheme, bnd):
+    inst = _inst(N, n, m, 210 + N + n, scheme, bnd)
+    sigma = 0.8
+    g, mu = orc.lag_grad_ex(inst, scheme, bnd, sigma=sigma)
+    tau = 1e-30
+    y = list(map(float, inst.y))
+    cs = []
+    for col in range(len(inst.z)):
+        z = [complex(v) for v in inst.z]
+        z[col] += 1j * tau
+        cs.append(_L(inst, z, y, sigma).imag / tau)
+    check_close(g, np.array(cs), mu, rel=1e-13, what=f"grad_z L scheme={scheme} bnd={bnd}")
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+@pytest.mark.parametrize("N,n,m", SHAPES)
+def test_jvp_ex_complex_step(orc, N, n, m, scheme, bnd):
+    """J v is the directional derivative of c: Im c(z + i tau v) / tau."""
+    inst = _inst(N, n, m, 220 + N + n, scheme, bnd)
+    v = np.random.default_rng(4).normal(size=len(inst.z))
+    jv, mu = orc.jvp_ex(inst, v, scheme, bnd)
+    A, B, g, q, r = defn.as_lists(inst)
+    tau = 1e-30
+    z = [complex(a, tau * b) for a, b in zip(inst.z, v)]
+    c = defn.constraints_ex(z, N, n, m, A, B, g, scheme, bnd, sin=cmath.sin)
+    check_close(jv, np.array([x.imag / tau for x in c]), mu, rel=1e-13, what="J v")
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+@pytest.mark.parametrize("N,n,m", [(1, 1, 1), (3, 1, 0), (3, 2, 1), (2, 3, 1), (2, 4, 2)])
+def test_hvp_ex_mixed_difference(orc, N, n, m, scheme, bnd):
+    """(H v)_a = d/dz_a of the directional derivative of L along v: complex
+    step in z_a, central difference (step 1e-5) along v."""
+    inst = _inst(N, n, m, 230 + N + n, scheme, bnd)
+    sigma = 1.1
+    v = np.random.default_rng(5).normal(size=len(inst.z))
+    hv, mu = orc.hvp_ex(inst, v, scheme, bnd, sigma=sigma)
+    tau, delta = 1e-30, 1e-5
+    y = list(map(float, inst.y))
+    want = np.empty(len(inst.z))
+    for a in range(len(inst.z)):
+        vals = []
+        for s in (+1, -1):
+            z = [complex(x + s * delta * d) for x, d in zip(inst.z, v)]
+            z[a] += 1j * tau
+            vals.append(_L(inst, z, y, sigma).imag)
+        want[a] = (vals[0] - vals[1]) / (2 * tau * delta)
+    scale = max(float(np.max(mu)), 1.0)
+    assert np.max(np.abs(hv - want)) <= 1e-7 * scale
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+@pytest.mark.parametrize("N,n,m", [(5, 3, 2), (6, 1, 1), (4, 2, 0), (40, 4, 2)])
+def test_coef_grad_ex_complex_step(orc, N, n, m, scheme, bnd):
+    """L is affine in (A, B, gamma): the complex step is exact to rounding."""
+    inst = _inst(N, n, m, 240 + N, scheme, bnd)
+    (gA, gB, gg), (mA, mB, mg) = orc.coef_grad_ex(inst, scheme, bnd)
+    A, B, g, q, r = defn.as_lists(inst)
+    y = list(map(float, inst.y))
+    z = list(map(float, inst.z))
+    tau = 1e-30
+    for i in range(n):
+        for j in range(n):
+            Ac = [[complex(v) for v in row] for row in A]
+            Ac[i][j] += 1j * tau
+            want = _L(inst, z, y, inst.sigma, A=Ac).imag / tau
+            assert abs(gA[i, j] - want) <= 1e-13 * mA[i, j] + 1e-300, ("A", i, j)
+        for l in range(m):
+            Bc = [[complex(v) for v in row] for row in B]
+            Bc[i][l] += 1j * tau
+            want = _L(inst, z, y, inst.sigma, B=Bc).imag / tau
+            assert abs(gB[i, l] - want) <= 1e-13 * mB[i, l] + 1e-300, ("B", i, l)
+        gc = [complex(v) for v in g]
+        gc[i] += 1j * tau
+        want = _L(inst, z, y, inst.sigma, gamma=gc).imag / tau
+        assert abs(gg[i] - want) <= 1e-13 * mg[i] + 1e-300, ("gamma", i)
+
+
+@pytest.mark.parametrize("N,n,m", [(300, 4, 2), (1, 1, 0), (64, 6, 3)])
+def test_trapezoidal_composites_equal_c_oracle(orc, N, n, m):
+    """Without boundary rows the trapezoidal composites and the C oracle's
+    node-by-node derivative functions (a different evaluation of the same
+    definitions) agree within 1e-13 mu."""
+    inst = _inst(N, n, m, 250 + N, 0, 0)
+    v = np.random.default_rng(6).normal(size=len(inst.z))
+    g1, m1 = orc.lag_grad_ex(inst, 0, 0, sigma=0.9)
+    g2, _ = orc.lag_grad(inst, sigma=0.9)
+    check_close(g1, g2, m1, rel=1e-13, what="grad_z L")
+    h1, hm = orc.hvp_ex(inst, v, 0, 0, sigma=0.9)
+    h2, _ = orc.hvp(inst, v, sigma=0.9)
+    check_close(h1, h2, hm, rel=1e-13, what="H v")
+    j1, jm = orc.jvp_ex(inst, v, 0, 0)
+    j2, _ = orc.jvp(inst, v)
+    check_close(j1, j2, jm, rel=1e-13, what="J v")
+    L1, Lm = orc.lagrangian_ex(inst, 0, 0, sigma=0.9)
+    L2, _ = orc.lagrangian(inst, sigma=0.9)
+    assert abs(L1 - L2) <= 1e-13 * Lm
+    (a1, b1, c1), (ma, mb, mc) = orc.coef_grad_ex(inst, 0, 0)
+    (a2, b2, c2), _ = orc.coef_grad(inst)
+    check_close(a1.ravel(), a2.ravel(), ma.ravel(), rel=1e-13, what="dL/dA")
+    check_close(b1.ravel(), b2.ravel(), mb.ravel(), rel=1e-13, what="dL/dB")
+    check_close(c1, c2, mc, rel=1e-13, what="dL/dgamma")
+
+
+def test_boundary_rows_enter_linearly(orc):
+    """A boundary row's multiplier adds exactly y_b to grad_z L at its state
+    and nothing elsewhere; it leaves H v and dL/dtheta unchanged."""
+    for scheme in (0, 1):
+        inst = _inst(30, 3, 2, 260 + scheme, scheme, 2)
+        N, n = inst.N, inst.n
+        y0 = inst.y.copy()
+        y0[n * N:] = 0.0
+        g0, _ = orc.lag_grad_ex(inst, scheme, 2, y=y0)
+        g1, _ = orc.lag_grad_ex(inst, scheme, 2)
+        d = g1 - g0
+        want = np.zeros_like(d)
+        for i in range(n):
+            want[i * (N + 1)] += inst.y[n * N + i]
+            want[i * (N + 1) + N] += inst.y[n * N + n + i]
+        check_close(d, want, np.abs(g1) + np.abs(g0) + 1e-300, rel=1e-15, what="boundary rows")
+        v = np.random.default_rng(7).normal(size=len(inst.z))
+        assert np.array_equal(orc.hvp_ex(inst, v, scheme, 2, y=y0)[0], orc.hvp_ex(inst, v, scheme, 2)[0])
+        ca, _ = orc.coef_grad_ex(inst, scheme, 2, y=y0)
+        cb, _ = orc.coef_grad_ex(inst, scheme, 2)
+        for x, w in zip(ca, cb):
+            assert np.array_equal(x, w)
