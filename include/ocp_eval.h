@@ -157,10 +157,10 @@ int ocp_build_kkt_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, in
 int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B,
                const double *gamma, const double *q, const double *r, ocp_problem **out);
 
-/* ocp_create with transcription options (NULL = defaults).  Every evaluation
- * and the assembly follow the handle's options; the batched and the
- * Lagrangian-derivative entry points accept only the defaults (OCP_ERR_ARG
- * otherwise). */
+/* ocp_create with transcription options (NULL = defaults).  Every evaluation,
+ * the assembly and the Lagrangian derivatives follow the handle's options;
+ * the batched entry points accept only the defaults, and ocp_eval_kkt only
+ * the trapezoidal scheme (OCP_ERR_ARG otherwise). */
 int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const double *A,
                   const double *B, const double *gamma, const double *q, const double *r,
                   ocp_problem **out);
@@ -288,8 +288,13 @@ int ocp_mapped_plan(const ocp_problem *p, const int32_t *perm_j, const int32_t *
  * Lagrangian derivatives for differentiable programming (the paper names
  * tighter integration with differentiable programming workflows as future
  * work, Sec. 8).  L(z, y) = sigma f(z) + y^T c(z); the dynamics coefficients
- * (A, B, gamma) are parameters of c.  All arrays are device pointers; every
- * sum over nodes uses a fixed reduction order (bitwise reproducible).
+ * (A, B, gamma) are parameters of c.  Either scheme and any boundary option
+ * of the handle: y has ncon doubles (defect rows, then boundary rows), and z,
+ * v and the gradients use the handle's layout (controls on NU nodes).  The
+ * boundary rows are linear in z and do not involve the coefficients.  All
+ * arrays are device pointers; every sum over nodes uses a fixed reduction
+ * order (bitwise reproducible).  The quadrotor handle is rejected
+ * (OCP_ERR_ARG).
  * ------------------------------------------------------------------------- */
 
 /* Replace the handle's A (n x n), B (n x m; NULL when m = 0) and gamma (n)

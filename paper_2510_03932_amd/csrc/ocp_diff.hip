@@ -19,6 +19,13 @@
 //                             + gamma_i (X_p v_i + X_i v_p)
 //   dL/dA_ij = -hh sum_k yt_ik sin X_jk,  dL/dB_il = -hh sum_k yt_ik U_lk,
 //   dL/dgamma_i = -hh sum_k yt_ik X_ik X_{p(i)k}.
+// Forward Euler (Sec. 3), c_ik = X_{i,k+1} - X_ik - h F_i(k): the same with
+// hh replaced by h and the node multiplier yt_ik = y_ik [k < N] (F at node k
+// enters only row (i, k)); controls exist on nodes k < N.  Generally the
+// defect is X_{i,k+1} - X_ik - al F_i(k) - be F_i(k+1) with (al, be) =
+// (hh, hh) or (h, 0).  Boundary rows (the state itself at node 0, and at node
+// N) add their multiplier to grad_z L at that state and v at that state to
+// J v; they are linear, so H v and dL/dtheta do not see them.
 // Every sum over nodes is a fixed-shape two-pass reduction (deterministic).
 #include <hip/hip_runtime.h>
 
@@ -33,15 +40,12 @@
 using namespace ocp;
 using namespace ocp::dev;
 
-// The derivative kernels implement the trapezoidal transcription without
-// boundary rows.
+// The derivative kernels implement the synthetic dynamics family (either
+// scheme, any boundary option).
 static int check_default_options(const ocp_problem *p, const char *what)
 {
     if (p->model != 0)
         return fail(OCP_ERR_ARG, std::string(what) + ": supports the synthetic dynamics family only");
-    if (p->d.scheme != OCP_SCHEME_TRAPEZOIDAL || p->d.nb != 0)
-        return fail(OCP_ERR_ARG, std::string(what) +
-                                     ": supports the trapezoidal scheme without boundary rows only");
     return OCP_OK;
 }
 
@@ -63,20 +67,31 @@ __global__ __launch_bounds__(kBlock) void lag_partial_kernel(KP P, const double 
     __shared__ double Ms[NB][kBlock];
     const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
-    const int64_t N = P.N, N1 = P.N1;
+    const int64_t N = P.N, N1 = P.N1, NU = P.NU;
     const double *U = z + (int64_t)n * N1;
+    const double *yb = y + (int64_t)n * N;  // boundary-row multipliers
+    const bool euler = P.scheme != 0;
+    const double al = euler ? P.h : P.hh, be = euler ? 0.0 : P.hh;
     double acc = 0.0;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int64_t k = (int64_t)ch * (kBlock - 1) + tid;
         double Pk[NB];
         if (k <= N) {
             double x[NB], F[NB];
-            dyn_node<NB>(P, z, k, x, F);
+            if (k < NU) {
+                dyn_node<NB>(P, z, k, x, F);
+            } else {  // forward Euler, node N: F(N) enters no row
+#pragma unroll
+                for (int i = 0; i < NB; i++) {
+                    x[i] = (i < n) ? z[i * N1 + k] : 0.0;
+                    F[i] = 0.0;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < NB; i++) {
                 if (i < n) {
-                    Ms[i][tid] = x[i] - P.hh * F[i];
-                    Pk[i] = x[i] + P.hh * F[i];
+                    Ms[i][tid] = x[i] - be * F[i];
+                    Pk[i] = x[i] + al * F[i];
                 }
             }
             if (tid < kBlock - 1 || k == N) {
@@ -84,11 +99,24 @@ __global__ __launch_bounds__(kBlock) void lag_partial_kernel(KP P, const double 
 #pragma unroll
                 for (int i = 0; i < NB; i++)
                     if (i < n) s += P.q[i] * x[i] * x[i];
-                for (int l = 0; l < m; l++) {
-                    const double u = U[l * N1 + k];
-                    s += P.r[l] * u * u;
+                if (k < NU) {
+                    for (int l = 0; l < m; l++) {
+                        const double u = U[l * NU + k];
+                        s += P.r[l] * u * u;
+                    }
                 }
                 acc += sigma * node_weight(P, (int)k) * s;
+                // boundary rows: the state at node 0 (and at node N)
+                if (P.nb >= n && k == 0) {
+#pragma unroll
+                    for (int i = 0; i < NB; i++)
+                        if (i < n) acc += yb[i] * x[i];
+                }
+                if (P.nb >= 2 * n && k == N) {
+#pragma unroll
+                    for (int i = 0; i < NB; i++)
+                        if (i < n) acc += yb[n + i] * x[i];
+                }
             }
         }
         __syncthreads();
@@ -140,13 +168,19 @@ __global__ __launch_bounds__(kBlock) void lag_grad_kernel(KP P, const double *__
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k > P.N) return;
     const int n = P.n, m = P.m;
-    const int64_t N1 = P.N1;
+    const int64_t N = P.N, N1 = P.N1, NU = P.NU;
+    const bool euler = P.scheme != 0;
+    const double wF = euler ? P.h : P.hh;
     const double w = node_weight(P, k);
     double x[NB], yl[NB], yr[NB], yt[NB];
     node_x_yt<NB>(P, z, y, k, x, yl, yr);
 #pragma unroll
-    for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
+    for (int i = 0; i < NB; i++) yt[i] = euler ? yr[i] : yl[i] + yr[i];
     const double x_last = last_of<NB>(x, n), yt_last = last_of<NB>(yt, n);
+    // boundary rows at this node add their multiplier to the state's entry
+    const double *yb = nullptr;
+    if (P.nb >= n && k == 0) yb = y + (int64_t)n * N;
+    if (P.nb >= 2 * n && k == N) yb = y + (int64_t)n * N + n;
 #pragma unroll
     for (int j = 0; j < NB; j++) {
         if (j < n) {
@@ -159,16 +193,19 @@ __global__ __launch_bounds__(kBlock) void lag_grad_kernel(KP P, const double *__
             const double xm = (j == 0) ? x_last : x[(j + NB - 1) % NB];
             const double ym = (j == 0) ? yt_last : yt[(j + NB - 1) % NB];
             const double G = cos(x[j]) * s + yt[j] * P.gam[j] * xn + ym * P.gam[jm] * xm;
-            st_nt(g + j * N1 + k, 2.0 * sigma * w * P.q[j] * x[j] + (yl[j] - yr[j]) - P.hh * G);
+            double val = 2.0 * sigma * w * P.q[j] * x[j] + (yl[j] - yr[j]) - wF * G;
+            if (yb) val += yb[j];
+            st_nt(g + j * N1 + k, val);
         }
     }
+    if (k >= NU) return;  // forward Euler: no controls at node N
     const double *U = z + (int64_t)n * N1;
     for (int l = 0; l < m; l++) {
         const double *b = P.BT + l * kLd;
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], b[i], s);
-        st_nt(g + (n + l) * N1 + k, 2.0 * sigma * w * P.r[l] * U[l * N1 + k] - P.hh * s);
+        st_nt(g + n * N1 + l * NU + k, 2.0 * sigma * w * P.r[l] * U[l * NU + k] - wF * s);
     }
 }
 
@@ -181,14 +218,17 @@ __global__ __launch_bounds__(kBlock) void hvp_kernel(KP P, const double *__restr
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k > P.N) return;
     const int n = P.n, m = P.m;
-    const int64_t N1 = P.N1;
+    const int64_t N1 = P.N1, NU = P.NU;
+    const bool euler = P.scheme != 0;
+    const double wF = euler ? P.h : P.hh;
     const double w = node_weight(P, k);
     double x[NB], yl[NB], yr[NB], vx[NB], pr[NB];
     node_x_yt<NB>(P, z, y, k, x, yl, yr);
 #pragma unroll
     for (int i = 0; i < NB; i++) {
+        if (euler) yl[i] = 0.0;  // node multiplier y_ik only
         vx[i] = (i < n) ? v[i * N1 + k] : 0.0;
-        pr[i] = (i < n) ? -P.hh * (yl[i] + yr[i]) * P.gam[i] : 0.0;
+        pr[i] = (i < n) ? -wF * (yl[i] + yr[i]) * P.gam[i] : 0.0;
     }
     const double v_last = last_of<NB>(vx, n), p_last = last_of<NB>(pr, n);
 #pragma unroll
@@ -198,21 +238,22 @@ __global__ __launch_bounds__(kBlock) void hvp_kernel(KP P, const double *__restr
             double s = 0.0;
 #pragma unroll
             for (int i = 0; i < NB; i++) s = __builtin_fma(yl[i] + yr[i], a[i], s);
-            const double d = 2.0 * sigma * w * P.q[j] + P.hh * sin(x[j]) * s;
+            const double d = 2.0 * sigma * w * P.q[j] + wF * sin(x[j]) * s;
             const double vn = (j + 1 < n) ? vx[(j + 1) % NB] : vx[0];
             const double vm = (j == 0) ? v_last : vx[(j + NB - 1) % NB];
             const double pm = (j == 0) ? p_last : pr[(j + NB - 1) % NB];
             st_nt(out + j * N1 + k, d * vx[j] + pr[j] * vn + pm * vm);
         }
     }
+    if (k >= NU) return;  // forward Euler: no controls at node N
     for (int l = 0; l < m; l++) {
-        const int64_t e = (int64_t)(n + l) * N1 + k;
+        const int64_t e = (int64_t)n * N1 + l * NU + k;
         st_nt(out + e, 2.0 * sigma * w * P.r[l] * v[e]);
     }
 }
 
-// J v, laid out like the defects: lane k publishes v_ik - hh D_i(k) for lane
-// k-1 and keeps v_ik + hh D_i(k).
+// J v, laid out like the defects: lane k publishes v_ik - be D_i(k) for lane
+// k-1 and keeps v_ik + al D_i(k).
 template <int NB>
 __global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restrict__ z,
                                                      const double *__restrict__ v,
@@ -222,7 +263,9 @@ __global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restr
     const int tid = threadIdx.x;
     const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
     const int n = P.n, m = P.m;
-    const int64_t N = P.N, N1 = P.N1;
+    const int64_t N = P.N, N1 = P.N1, NU = P.NU;
+    const bool euler = P.scheme != 0;
+    const double al = euler ? P.h : P.hh, be = euler ? 0.0 : P.hh;
     double Pk[NB];
     if (k <= N) {
         double x[NB], vx[NB], D[NB];
@@ -241,8 +284,8 @@ __global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restr
                 for (int i = 0; i < NB; i++) D[i] = __builtin_fma(a[i], t, D[i]);
             }
         }
-        for (int l = 0; l < m; l++) {
-            const double u = v[(n + l) * N1 + k];
+        for (int l = 0; l < m && k < NU; l++) {
+            const double u = v[n * N1 + l * NU + k];
             const double *b = P.BT + l * kLd;
 #pragma unroll
             for (int i = 0; i < NB; i++) D[i] = __builtin_fma(b[i], u, D[i]);
@@ -253,8 +296,8 @@ __global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restr
                 const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
                 const double vp = (i + 1 < n) ? vx[(i + 1) % NB] : vx[0];
                 D[i] += P.gam[i] * (xp * vx[i] + x[i] * vp);
-                Ms[i][tid] = vx[i] - P.hh * D[i];
-                Pk[i] = vx[i] + P.hh * D[i];
+                Ms[i][tid] = vx[i] - be * D[i];
+                Pk[i] = vx[i] + al * D[i];
             }
         }
     }
@@ -264,6 +307,18 @@ __global__ __launch_bounds__(kBlock) void jvp_kernel(KP P, const double *__restr
         for (int i = 0; i < NB; i++)
             if (i < n) st_nt(out + i * N + k, Ms[i][tid + 1] - Pk[i]);
     }
+}
+
+// Boundary rows of J v: row n N + b holds the state X_{b mod n} at node 0
+// (b < n) or at node N.
+__global__ __launch_bounds__(kBlock) void bnd_jvp_kernel(KP P, const double *__restrict__ v,
+                                                         double *__restrict__ out)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= P.nb) return;
+    const int i = b % P.n;
+    const int64_t node = b < P.n ? 0 : P.N;
+    out[(int64_t)P.n * P.N + b] = v[(int64_t)i * P.N1 + node];
 }
 
 // Coefficient gradient, pass 1.  Grid (G, n, ceil((n+m+1)/kCols)): row i,
@@ -282,15 +337,20 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(KP P, const double
     double acc[kCols];
 #pragma unroll
     for (int c = 0; c < kCols; c++) acc[c] = 0.0;
+    const int64_t NU = P.NU;
+    const bool euler = P.scheme != 0;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k <= N; k += (int64_t)G * kBlock) {
         const double *yi = y + i * N + k;
-        const double yt = (k >= 1 ? yi[-1] : 0.0) + (k < N ? yi[0] : 0.0);
+        // node multiplier: F at node k enters rows (i, k-1) and (i, k), or
+        // only (i, k) under forward Euler
+        const double yt = euler ? (k < N ? yi[0] : 0.0) : (k >= 1 ? yi[-1] : 0.0) + (k < N ? yi[0] : 0.0);
 #pragma unroll
         for (int c = 0; c < kCols; c++) {
             const int col = c0 + c;
             if (col < n) acc[c] += yt * sin(z[col * N1 + k]);
-            else if (col < n + m) acc[c] += yt * z[col * N1 + k];
-            else if (col == n + m) acc[c] += yt * (z[i * N1 + k] * z[p * N1 + k]);
+            else if (col < n + m) {
+                if (k < NU) acc[c] += yt * z[n * N1 + (col - n) * NU + k];
+            } else if (col == n + m) acc[c] += yt * (z[i * N1 + k] * z[p * N1 + k]);
         }
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -324,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void coef_final_kernel(KP P, const double *
     for (int b = threadIdx.x; b < G; b += kBlock) s += cpart[(int64_t)idx * G + b];
     s = block_sum<kBlock>(s);
     if (threadIdx.x != 0) return;
-    const double val = -P.hh * s;
+    const double val = -(P.scheme != 0 ? P.h : P.hh) * s;
     const int i = idx / ncol, col = idx - i * ncol;
     if (col < n) gA[i * n + col] = val;
     else if (col < n + m) gB[i * m + (col - n)] = val;
@@ -437,6 +497,10 @@ int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double 
     if (!z || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_jvp: null array");
     OCP_DISPATCH_NB(p->d.n, jvp_kernel, dim3(blocks_for(p->d.N, kBlock - 1)), stream, p->kp, z, v,
                     out);
+    if (int rc = check_launch("ocp_eval_jvp")) return rc;
+    if (p->d.nb > 0)
+        hipLaunchKernelGGL(bnd_jvp_kernel, dim3(blocks_for(p->d.nb, kBlock)), dim3(kBlock), 0, stream,
+                           p->kp, v, out);
     return check_launch("ocp_eval_jvp");
 }
 

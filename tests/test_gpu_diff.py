@@ -71,6 +71,54 @@ def test_derivatives_match_oracle(ocp, N, n, m):
     _check_all(ocp, synth.make_instance(N, n, m, seed=2), 1.3, f"{N},{n},{m}")
 
 
+def _check_all_ex(ocp, inst, sigma, tag):
+    """Every derivative under the instance's scheme and boundary option,
+    against the oracle's definitions over its _ex arrays."""
+    scheme, bnd = inst.scheme, inst.bnd
+    dev, z, y, v, vt = _dev_inputs(inst)
+    prob = ocp.Problem.from_instance(inst, dev)
+    L = prob.lagrangian(z, y, sigma).cpu().numpy()
+    g = prob.lag_grad(z, y, sigma).cpu().numpy()
+    hv = prob.hvp(z, y, vt, sigma).cpu().numpy()
+    jv = prob.jvp(z, vt).cpu().numpy()
+    gA, gB, gg = (t.cpu().numpy() for t in prob.coef_grad(z, y))
+    Lo, Lm = oracle.lagrangian_ex(inst, scheme, bnd, sigma=sigma)
+    check_close(L, np.array([Lo]), np.array([Lm]), what=f"L {tag}")
+    want, mu = oracle.lag_grad_ex(inst, scheme, bnd, sigma=sigma)
+    check_close(g, want, mu, what=f"grad_z L {tag}")
+    want, mu = oracle.hvp_ex(inst, v, scheme, bnd, sigma=sigma)
+    check_close(hv, want, mu, what=f"H v {tag}")
+    want, mu = oracle.jvp_ex(inst, v, scheme, bnd)
+    check_close(jv, want, mu, what=f"J v {tag}")
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_grad_ex(inst, scheme, bnd)
+    check_close(gA.ravel(), oA.ravel(), mA.ravel(), what=f"dL/dA {tag}")
+    check_close(gB.ravel(), oB.ravel(), mB.ravel(), what=f"dL/dB {tag}")
+    check_close(gg, og, mg, what=f"dL/dgamma {tag}")
+    prob.close()
+
+
+EX_SHAPES = [(1000, 4, 2), (777, 5, 3), (1, 1, 0), (1, 1, 1), (2, 2, 1), (3, 3, 0), (257, 16, 8),
+             (513, 32, 32), (300, 9, 4), (50, 2, 9)]
+
+
+@pytest.mark.parametrize("scheme,bnd", [(0, 1), (0, 2), (1, 0), (1, 1), (1, 2)])
+@pytest.mark.parametrize("N,n,m", EX_SHAPES)
+def test_derivatives_other_schemes_match_oracle(ocp, N, n, m, scheme, bnd):
+    """Forward Euler and boundary rows: every derivative entry point against
+    the oracle (values within 1e-12 mu)."""
+    _say(f"[diff ex] N={N} n={n} m={m} scheme={scheme} bnd={bnd}")
+    inst = synth.make_instance(N, n, m, seed=7, scheme=scheme, bnd=bnd)
+    _check_all_ex(ocp, inst, 1.3, f"{N},{n},{m},{scheme},{bnd}")
+
+
+def test_derivatives_other_schemes_workload(ocp):
+    """The differentiation workload's size (N = 2e5, n = 8, m = 4) under
+    forward Euler with initial and final state rows, full arrays."""
+    N, n, m = synth.DIFF
+    _say(f"[diff ex] workload N={N} n={n} m={m} Euler bnd=2")
+    _check_all_ex(ocp, synth.make_instance(N, n, m, seed=0, scheme=1, bnd=2), 1.0, "Euler 2e5")
+
+
 def test_differentiation_workload_full_arrays(ocp):
     N, n, m = synth.DIFF
     _say(f"[diff] workload N={N} n={n} m={m}")
@@ -158,10 +206,12 @@ def test_autograd_backward_matches_oracle(ocp):
     prob.close()
 
 
-@pytest.mark.parametrize("N,n,m", [(4, 3, 2), (3, 1, 1), (5, 2, 0)])
-def test_autograd_gradcheck(ocp, N, n, m):
+@pytest.mark.parametrize("N,n,m,scheme,bnd", [(4, 3, 2, 0, 0), (3, 1, 1, 0, 0), (5, 2, 0, 0, 0),
+                                              (4, 3, 2, 1, 2), (3, 1, 1, 1, 1), (5, 2, 0, 0, 2),
+                                              (4, 2, 1, 1, 0)])
+def test_autograd_gradcheck(ocp, N, n, m, scheme, bnd):
     from paper_2510_03932_amd.autograd import constraints, lagrangian, lagrangian_grad
-    inst = synth.make_instance(N, n, m, seed=7)
+    inst = synth.make_instance(N, n, m, seed=7, scheme=scheme, bnd=bnd)
     dev = torch.device("cuda", 0)
     prob = ocp.Problem.from_instance(inst, dev)
     z, y, A, B, g = _leaf_inputs(inst, dev)

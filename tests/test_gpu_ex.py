@@ -103,15 +103,3 @@ def test_euler_large_full_arrays(ocp):
     del got, want, mu
     prob.close()
     torch.cuda.empty_cache()
-
-
-def test_derivatives_reject_non_default_options(ocp):
-    dev = torch.device("cuda", 0)
-    inst = synth.make_instance(10, 3, 1, seed=1, scheme=1, bnd=0)
-    prob = ocp.Problem.from_instance(inst, dev)
-    z = torch.from_numpy(inst.z).to(dev)
-    y = torch.from_numpy(inst.y).to(dev)
-    with pytest.raises(ocp.OcpError) as e:
-        prob.lag_grad(z, y)
-    assert e.value.code == ocp.OCP_ERR_ARG
-    prob.close()
