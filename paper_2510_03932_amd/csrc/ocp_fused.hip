@@ -10,8 +10,10 @@
 // the COO kernels and the assembly.
 //
 // Defect rows: workgroup b owns intervals [b KT, b KT + KT).  It stages the
-// states and their cosines at the KT+1 nodes, and the rows' regularization,
-// in LDS; then, for each state
+// states and their cosines at the KT+1 nodes, the rows' regularization and
+// the scaled coefficients -hh A, -hh B, -hh gamma in LDS (a wavefront spans
+// four slots of a row, so coefficient reads from global memory would be
+// per-lane loads, each waited for); then, for each state
 // component i, it computes the tile's KT rows (T Jacobian entries and the
 // diagonal each) slot by slot into an LDS tile and writes the rows'
 // contiguous CSR range with full-line stores.
@@ -56,7 +58,15 @@ __global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, 
     double *xs = lds;                     // [n][W] states
     double *cs = lds + n * W;             // [n][W] cosines
     double *rg = lds + 2 * n * W;         // [n][KT] the tile's defect-row diagonals (reg or 0)
-    double *tile = rg + n * KT;           // [KT][T1] output rows
+    double *cf = rg + n * KT;             // [n][n+m] -hh A | -hh B, then [n] -hh gamma
+    double *gs = cf + n * (n + m);
+    double *tile = gs + n;                // [KT][T1] output rows
+    const double hh = P.hh;
+    for (int x = threadIdx.x; x < n * (n + m); x += kBlock) {
+        const int i = x / (n + m), j = x - i * (n + m);
+        cf[x] = -hh * (j < n ? P.A[i * n + j] : P.B[i * m + (j - n)]);
+    }
+    for (int x = threadIdx.x; x < n; x += kBlock) gs[x] = -hh * P.gam[x];
     for (int x = threadIdx.x; x < n * W; x += kBlock) {
         const int j = x / W, u = x - j * W;
         const int64_t k = k0 + u;
@@ -71,10 +81,9 @@ __global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, 
         rg[x] = (reg && kk < kn) ? reg[nvar + i * N + k0 + kk] : 0.0;
     }
     __syncthreads();
-    const double hh = P.hh;
     for (int i = 0; i < n; i++) {
-        // slot t of the tile's rows, interval fastest: a wavefront shares t,
-        // so the branches and the coefficient loads are uniform
+        // slot t of the tile's rows, interval fastest: 16 lanes share t, so
+        // a wavefront covers four slots; its coefficients come from LDS
         for (int w = threadIdx.x; w < T1 << LG; w += kBlock) {
             const int t = w >> LG, kk = w & (KT - 1);
             if (kk >= kn) continue;
@@ -83,15 +92,14 @@ __global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, 
                 const int j = t >> 1, s = t & 1, u = kk + s;
                 const int jn = (j + 1 == n) ? 0 : j + 1;
                 const int jp = (j == 0) ? n - 1 : j - 1;
-                const double a = -hh * P.A[i * n + j];
-                v = a * cs[j * W + u];
+                v = cf[i * (n + m) + j] * cs[j * W + u];
                 if (i == j) {
-                    const double dg = -hh * P.gam[j] * xs[jn * W + u];
+                    const double dg = gs[j] * xs[jn * W + u];
                     v += s ? dg + 1.0 : dg - 1.0;
                 }
-                if (i == jp) v += -hh * P.gam[jp] * xs[jp * W + u];
+                if (i == jp) v += gs[jp] * xs[jp * W + u];
             } else if (t < T) {
-                v = -hh * P.B[i * m + ((t - 2 * n) >> 1)];
+                v = cf[i * (n + m) + n + ((t - 2 * n) >> 1)];
             } else {
                 v = rg[(i << LG) + kk];
             }
@@ -227,7 +235,8 @@ int ocp_eval_kkt(const ocp_problem *p, const double *z, const double *y, double 
     // defect-row tiles of kDefectTile intervals; LDS holds the tile's states,
     // their cosines and the output rows of one state component
     const size_t lds = ((size_t)kDefectTile * (d.T + 1) + 2 * (size_t)d.n * (kDefectTile + 1) +
-                        (size_t)d.n * kDefectTile) * sizeof(double);
+                        (size_t)d.n * kDefectTile + (size_t)d.n * (d.n + d.m) + (size_t)d.n) *
+                       sizeof(double);
     hipLaunchKernelGGL(kkt_defect_kernel, dim3(blocks_for(d.N, kDefectTile)), dim3(kBlock), lds, stream, p->kp,
                        Lo, z, reg, kkt);
     if (int rc = check_launch("ocp_eval_kkt")) return rc;
