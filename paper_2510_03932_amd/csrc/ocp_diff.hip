@@ -224,11 +224,12 @@ __global__ __launch_bounds__(kBlock) void hvp_kernel(KP P, const double *__restr
     const double w = node_weight(P, k);
     double x[NB], yl[NB], yr[NB], vx[NB], pr[NB];
     node_x_yt<NB>(P, z, y, k, x, yl, yr);
+    double *yt = yl;  // node multiplier, in place: y_{i,k-1} + y_ik, or y_ik under Euler
 #pragma unroll
     for (int i = 0; i < NB; i++) {
-        if (euler) yl[i] = 0.0;  // node multiplier y_ik only
+        yt[i] = euler ? yr[i] : yl[i] + yr[i];
         vx[i] = (i < n) ? v[i * N1 + k] : 0.0;
-        pr[i] = (i < n) ? -wF * (yl[i] + yr[i]) * P.gam[i] : 0.0;
+        pr[i] = (i < n) ? -wF * yt[i] * P.gam[i] : 0.0;
     }
     const double v_last = last_of<NB>(vx, n), p_last = last_of<NB>(pr, n);
 #pragma unroll
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void hvp_kernel(KP P, const double *__restr
             const double *a = P.AT + j * kLd;
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NB; i++) s = __builtin_fma(yl[i] + yr[i], a[i], s);
+            for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             const double d = 2.0 * sigma * w * P.q[j] + wF * sin(x[j]) * s;
             const double vn = (j + 1 < n) ? vx[(j + 1) % NB] : vx[0];
             const double vm = (j == 0) ? v_last : vx[(j + NB - 1) % NB];
