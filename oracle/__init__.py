@@ -266,38 +266,21 @@ class Oracle:
     def lag_grad_ex(self, inst, scheme=0, bnd=0, sigma=None, y=None):
         """grad_z L (nvar entries, the layout of z) and its mu."""
         sigma = inst.sigma if sigma is None else sigma
-        y = _d(inst.y if y is None else y)
-        g, gmu = self.grad_ex(inst, scheme, bnd)
-        jv, jmu = self.jac_ex(inst, scheme, bnd)
         jr, jc, _, _ = self.pattern_ex(inst.N, inst.n, inst.m, scheme, bnd)
-        nv = len(g)
-        out = sigma * g + np.bincount(jc, weights=jv * y[jr], minlength=nv)
-        mu = abs(sigma) * gmu + np.bincount(jc, weights=jmu * np.abs(y[jr]), minlength=nv)
-        return out, mu
+        return _grad_plus_jt_y(sigma, self.grad_ex(inst, scheme, bnd), self.jac_ex(inst, scheme, bnd),
+                               jr, jc, _d(inst.y if y is None else y))
 
     def hvp_ex(self, inst, v, scheme=0, bnd=0, sigma=None, y=None):
         """(Hessian of L) v and its mu; the Hessian is the symmetric matrix
         whose lower triangle hess_ex holds."""
-        v = _d(v)
-        hv, hmu = self.hess_ex(inst, scheme, bnd, sigma, y)
         _, _, hr, hc = self.pattern_ex(inst.N, inst.n, inst.m, scheme, bnd)
-        nv = len(v)
-        off = hr != hc
-        out = (np.bincount(hr, weights=hv * v[hc], minlength=nv)
-               + np.bincount(hc[off], weights=hv[off] * v[hr[off]], minlength=nv))
-        mu = (np.bincount(hr, weights=hmu * np.abs(v[hc]), minlength=nv)
-              + np.bincount(hc[off], weights=hmu[off] * np.abs(v[hr[off]]), minlength=nv))
-        return out, mu
+        return _sym_lower_mv(self.hess_ex(inst, scheme, bnd, sigma, y), hr, hc, _d(v))
 
     def jvp_ex(self, inst, v, scheme=0, bnd=0):
         """J v (ncon entries, the layout of c) and its mu."""
-        v = _d(v)
-        jv, jmu = self.jac_ex(inst, scheme, bnd)
         jr, jc, _, _ = self.pattern_ex(inst.N, inst.n, inst.m, scheme, bnd)
         nc = self.sizes_ex(inst.N, inst.n, inst.m, scheme, bnd)["ncon"]
-        out = np.bincount(jr, weights=jv * v[jc], minlength=nc)
-        mu = np.bincount(jr, weights=jmu * np.abs(v[jc]), minlength=nc)
-        return out, mu
+        return _coo_mv(self.jac_ex(inst, scheme, bnd), jr, jc, _d(v), nc)
 
     def coef_grad_ex(self, inst, scheme=0, bnd=0, y=None):
         """(dL/dA, dL/dB, dL/dgamma) and their mu arrays.  With S = sin X and
@@ -481,6 +464,61 @@ class Oracle:
                "quad_hess")
         return v, mu
 
+    # Lagrangian derivatives of the quadrotor model, written out over the
+    # arrays above as for the synthetic family (the model has no coefficient
+    # parameters, so there is no dL/dtheta).
+    def quad_lagrangian(self, q, sigma=None, y=None):
+        sigma = q.sigma if sigma is None else sigma
+        y = _d(q.y if y is None else y)
+        f, fmu = self.quad_obj(q)
+        c, cmu = self.quad_cons(q)
+        return sigma * f + math.fsum(y * c), abs(sigma) * fmu + float(np.abs(y) @ cmu)
+
+    def quad_lag_grad(self, q, sigma=None, y=None):
+        sigma = q.sigma if sigma is None else sigma
+        jr, jc, _, _ = self.quad_pattern(q.N, q.bnd)
+        return _grad_plus_jt_y(sigma, self.quad_grad(q), self.quad_jac(q), jr, jc,
+                               _d(q.y if y is None else y))
+
+    def quad_hvp(self, q, v, sigma=None, y=None):
+        _, _, hr, hc = self.quad_pattern(q.N, q.bnd)
+        return _sym_lower_mv(self.quad_hess(q, sigma, y), hr, hc, _d(v))
+
+    def quad_jvp(self, q, v):
+        jr, jc, _, _ = self.quad_pattern(q.N, q.bnd)
+        return _coo_mv(self.quad_jac(q), jr, jc, _d(v), self.quad_sizes(q.N, q.bnd)["ncon"])
+
+
+def _grad_plus_jt_y(sigma, grad, jac, jr, jc, y):
+    """sigma grad f + J^T y from COO (values, mu) arrays, and its mu: a
+    scatter-add over the entries in COO order."""
+    g, gmu = grad
+    jv, jmu = jac
+    nv = len(g)
+    out = sigma * g + np.bincount(jc, weights=jv * y[jr], minlength=nv)
+    mu = abs(sigma) * gmu + np.bincount(jc, weights=jmu * np.abs(y[jr]), minlength=nv)
+    return out, mu
+
+
+def _sym_lower_mv(hess, hr, hc, v):
+    """H v for the symmetric H whose lower triangle is the COO (values, mu)
+    pair hess, and its mu."""
+    hv, hmu = hess
+    nv = len(v)
+    off = hr != hc
+    out = (np.bincount(hr, weights=hv * v[hc], minlength=nv)
+           + np.bincount(hc[off], weights=hv[off] * v[hr[off]], minlength=nv))
+    mu = (np.bincount(hr, weights=hmu * np.abs(v[hc]), minlength=nv)
+          + np.bincount(hc[off], weights=hmu[off] * np.abs(v[hr[off]]), minlength=nv))
+    return out, mu
+
+
+def _coo_mv(jac, jr, jc, v, rows):
+    """J v from COO (values, mu) arrays, and its mu."""
+    jv, jmu = jac
+    return (np.bincount(jr, weights=jv * v[jc], minlength=rows),
+            np.bincount(jr, weights=jmu * np.abs(v[jc]), minlength=rows))
+
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
@@ -540,6 +578,10 @@ quad_grad = DEFAULT.quad_grad
 quad_cons = DEFAULT.quad_cons
 quad_jac = DEFAULT.quad_jac
 quad_hess = DEFAULT.quad_hess
+quad_lagrangian = DEFAULT.quad_lagrangian
+quad_lag_grad = DEFAULT.quad_lag_grad
+quad_hvp = DEFAULT.quad_hvp
+quad_jvp = DEFAULT.quad_jvp
 
 
 def build_variant(src_text: str, out_path: str) -> "Oracle":

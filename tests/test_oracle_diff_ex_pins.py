@@ -3,10 +3,13 @@ option (trapezoidal or forward Euler; no boundary rows, initial-state rows,
 or initial- and final-state rows): L = sigma f + y^T c, grad_z L, (Hessian
 of L) v, J v and dL/d(A, B, gamma), against a 50-digit evaluation,
 complex-step and mixed differences of the independent definition module, and
-against the C oracle's own trapezoidal functions."""
+against the C oracle's own trapezoidal functions; and the same derivatives
+(no coefficients there) of the quadrotor model."""
 from __future__ import annotations
 
 import cmath
+import math
+import types
 
 import numpy as np
 import pytest
@@ -173,3 +176,69 @@ def test_boundary_rows_enter_linearly(orc):
         cb, _ = orc.coef_grad_ex(inst, scheme, 2)
         for x, w in zip(ca, cb):
             assert np.array_equal(x, w)
+
+
+# ---- the quadrotor model (paper Appendix A) ---------------------------------
+
+QCFN = types.SimpleNamespace(sin=cmath.sin, cos=cmath.cos, tan=cmath.tan, pi=math.pi)
+
+
+def _qL(q, z, y, sigma, fn=QCFN):
+    return defn.quad_lagrangian(z, y, sigma, q.N, q.g, q.r, q.bnd, fn=fn)
+
+
+@pytest.mark.parametrize("N,bnd", [(1, 0), (2, 1), (3, 2), (4, 1)])
+def test_quad_lagrangian_high_precision(orc, N, bnd):
+    import mpmath
+    mpmath.mp.dps = 50
+    q = synth.make_quadrotor(N, seed=300 + N, bnd=bnd)
+    Lo, mu = orc.quad_lagrangian(q, sigma=0.9)
+    mp = mpmath.mpf
+    fn = types.SimpleNamespace(sin=mpmath.sin, cos=mpmath.cos, tan=mpmath.tan, pi=mpmath.pi)
+    want = defn.quad_lagrangian([mp(v) for v in q.z], [mp(v) for v in q.y], mp("0.9"), N, mp(q.g),
+                                mp(q.r), bnd, fn=fn, dt=mp(1) / N)
+    assert abs(Lo - float(want)) <= 1e-13 * mu
+
+
+@pytest.mark.parametrize("N,bnd", [(1, 0), (2, 1), (3, 2), (5, 1)])
+def test_quad_lag_grad_complex_step(orc, N, bnd):
+    q = synth.make_quadrotor(N, seed=310 + N, bnd=bnd)
+    g, mu = orc.quad_lag_grad(q, sigma=0.8)
+    tau = 1e-30
+    y = list(map(float, q.y))
+    cs = []
+    for col in range(len(q.z)):
+        z = [complex(v) for v in q.z]
+        z[col] += 1j * tau
+        cs.append(_qL(q, z, y, 0.8).imag / tau)
+    check_close(g, np.array(cs), mu, rel=1e-13, what="quadrotor grad_z L")
+
+
+@pytest.mark.parametrize("N,bnd", [(1, 0), (2, 1), (3, 2), (5, 1)])
+def test_quad_jvp_complex_step(orc, N, bnd):
+    q = synth.make_quadrotor(N, seed=320 + N, bnd=bnd)
+    v = np.random.default_rng(8).normal(size=len(q.z))
+    jv, mu = orc.quad_jvp(q, v)
+    tau = 1e-30
+    z = [complex(a, tau * b) for a, b in zip(q.z, v)]
+    c = defn.quad_constraints(z, N, q.g, bnd, fn=QCFN)
+    check_close(jv, np.array([x.imag / tau for x in c]), mu, rel=1e-13, what="quadrotor J v")
+
+
+@pytest.mark.parametrize("N,bnd", [(1, 0), (2, 1), (3, 2)])
+def test_quad_hvp_mixed_difference(orc, N, bnd):
+    q = synth.make_quadrotor(N, seed=330 + N, bnd=bnd)
+    v = np.random.default_rng(9).normal(size=len(q.z))
+    hv, mu = orc.quad_hvp(q, v, sigma=1.1)
+    tau, delta = 1e-30, 1e-5
+    y = list(map(float, q.y))
+    want = np.empty(len(q.z))
+    for a in range(len(q.z)):
+        vals = []
+        for s in (+1, -1):
+            z = [complex(x + s * delta * d) for x, d in zip(q.z, v)]
+            z[a] += 1j * tau
+            vals.append(_qL(q, z, y, 1.1).imag)
+        want[a] = (vals[0] - vals[1]) / (2 * tau * delta)
+    scale = max(float(np.max(mu)), 1.0)
+    assert np.max(np.abs(hv - want)) <= 1e-7 * scale
