@@ -293,8 +293,10 @@ int ocp_mapped_plan(const ocp_problem *p, const int32_t *perm_j, const int32_t *
  * v and the gradients use the handle's layout (controls on NU nodes).  The
  * boundary rows are linear in z and do not involve the coefficients.  All
  * arrays are device pointers; every sum over nodes uses a fixed reduction
- * order (bitwise reproducible).  The quadrotor handle is rejected
- * (OCP_ERR_ARG).
+ * order (bitwise reproducible).  A quadrotor handle is accepted by
+ * ocp_eval_lagrangian, ocp_eval_lag_grad, ocp_eval_hvp and ocp_eval_jvp (its
+ * own layouts); the model has no coefficient arrays, so ocp_set_coefficients
+ * and ocp_eval_coef_grad reject it (OCP_ERR_ARG).
  * ------------------------------------------------------------------------- */
 
 /* Replace the handle's A (n x n), B (n x m; NULL when m = 0) and gamma (n)
@@ -363,8 +365,9 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
  *
  * A handle from ocp_quad_create works with ocp_problem_sizes, ocp_eval_obj,
  * ocp_eval_grad, ocp_eval_cons, ocp_eval_jac, ocp_eval_hess,
- * ocp_assemble_kkt and ocp_destroy, with the arrays and layouts above.  The
- * Lagrangian-derivative entry points and ocp_set_coefficients reject it
+ * ocp_assemble_kkt, ocp_eval_lagrangian, ocp_eval_lag_grad, ocp_eval_hvp,
+ * ocp_eval_jvp and ocp_destroy, with the arrays and layouts above.
+ * ocp_set_coefficients, ocp_eval_coef_grad and ocp_eval_kkt reject it
  * (OCP_ERR_ARG).
  * ------------------------------------------------------------------------- */
 

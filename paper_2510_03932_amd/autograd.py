@@ -18,6 +18,10 @@ import torch
 
 
 def _coefficients(prob, A, B, gamma):
+    """Push the coefficient tensors into the handle; a model without
+    coefficient arrays (the quadrotor) takes A = B = gamma = None."""
+    if A is None and B is None and gamma is None:
+        return
     prob.set_coefficients(A.detach(), B.detach(), gamma.detach())
 
 
@@ -115,18 +119,19 @@ class _Lagrangian(torch.autograd.Function):
         return gz, gy, gA, gB, gg, None, None
 
 
-def lagrangian(prob, z, y, A, B, gamma, sigma: float = 1.0):
+def lagrangian(prob, z, y, A=None, B=None, gamma=None, sigma: float = 1.0):
     """L(z, y) = sigma f(z) + y^T c(z) with differentiable z, y, A (n, n),
     B (n, m) and gamma (n,) (float64 tensors on the problem's device);
-    sigma is a plain number."""
+    sigma is a plain number.  For the quadrotor model, which has no
+    coefficient arrays, leave A, B and gamma out."""
     return _Lagrangian.apply(z, y, A, B, gamma, float(sigma), prob)
 
 
-def lagrangian_grad(prob, z, y, A, B, gamma, sigma: float = 1.0):
+def lagrangian_grad(prob, z, y, A=None, B=None, gamma=None, sigma: float = 1.0):
     """grad_z L as a differentiable function of (z, y)."""
     return _LagGrad.apply(z, y, A, B, gamma, float(sigma), prob)
 
 
-def constraints(prob, z, A, B, gamma):
+def constraints(prob, z, A=None, B=None, gamma=None):
     """c(z) as a differentiable function of (z, A, B, gamma)."""
     return _Cons.apply(z, A, B, gamma, prob)

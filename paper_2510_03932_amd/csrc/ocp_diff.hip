@@ -36,13 +36,14 @@
 #include "ocp_device.h"
 #include "ocp_internal.h"
 #include "ocp_problem.h"
+#include "ocp_quad.h"
 
 using namespace ocp;
 using namespace ocp::dev;
 
-// The derivative kernels implement the synthetic dynamics family (either
-// scheme, any boundary option).
-static int check_default_options(const ocp_problem *p, const char *what)
+// The coefficient gradient needs the synthetic family's coefficient arrays
+// (either scheme, any boundary option); the quadrotor model has none.
+static int check_coefficients(const ocp_problem *p, const char *what)
 {
     if (p->model != 0)
         return fail(OCP_ERR_ARG, std::string(what) + ": supports the synthetic dynamics family only");
@@ -452,9 +453,9 @@ int ocp_eval_lagrangian(const ocp_problem *p, const double *z, const double *y, 
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_lagrangian")) return rc;
-    if (int rc = check_default_options(p, "ocp_eval_lagrangian")) return rc;
     if (!z || !y || !L) return fail(OCP_ERR_ARG, "ocp_eval_lagrangian: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_lagrangian: sigma is not finite");
+    if (p->model == quad::kModel) return quad::eval_lagrangian(p, z, y, sigma, L, stream);
     const int nchunks = (int)blocks_for(p->d.N, kBlock - 1);
     const int g = std::min(nchunks, kObjBlocks);
     OCP_DISPATCH_NB(p->d.n, lag_partial_kernel, dim3(g), stream, p->kp, z, y, sigma, nchunks, p->partials);
@@ -468,9 +469,9 @@ int ocp_eval_lag_grad(const ocp_problem *p, const double *z, const double *y, do
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_lag_grad")) return rc;
-    if (int rc = check_default_options(p, "ocp_eval_lag_grad")) return rc;
     if (!z || !y || !g) return fail(OCP_ERR_ARG, "ocp_eval_lag_grad: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_lag_grad: sigma is not finite");
+    if (p->model == quad::kModel) return quad::eval_lag_grad(p, z, y, sigma, g, stream);
     OCP_DISPATCH_NB(p->d.n, lag_grad_kernel, dim3(blocks_for(p->d.N1, kBlock)), stream, p->kp, z, y,
                     sigma, g);
     return check_launch("ocp_eval_lag_grad");
@@ -481,9 +482,9 @@ int ocp_eval_hvp(const ocp_problem *p, const double *z, const double *y, double 
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_hvp")) return rc;
-    if (int rc = check_default_options(p, "ocp_eval_hvp")) return rc;
     if (!z || !y || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_hvp: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_hvp: sigma is not finite");
+    if (p->model == quad::kModel) return quad::eval_hvp(p, z, y, sigma, v, out, stream);
     OCP_DISPATCH_NB(p->d.n, hvp_kernel, dim3(blocks_for(p->d.N1, kBlock)), stream, p->kp, z, y, sigma,
                     v, out);
     return check_launch("ocp_eval_hvp");
@@ -494,8 +495,8 @@ int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double 
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_jvp")) return rc;
-    if (int rc = check_default_options(p, "ocp_eval_jvp")) return rc;
     if (!z || !v || !out) return fail(OCP_ERR_ARG, "ocp_eval_jvp: null array");
+    if (p->model == quad::kModel) return quad::eval_jvp(p, z, v, out, stream);
     OCP_DISPATCH_NB(p->d.n, jvp_kernel, dim3(blocks_for(p->d.N, kBlock - 1)), stream, p->kp, z, v,
                     out);
     if (int rc = check_launch("ocp_eval_jvp")) return rc;
@@ -510,7 +511,7 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
 {
     clear_error();
     if (int rc = check_handle(p, "ocp_eval_coef_grad")) return rc;
-    if (int rc = check_default_options(p, "ocp_eval_coef_grad")) return rc;
+    if (int rc = check_coefficients(p, "ocp_eval_coef_grad")) return rc;
     if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_grad: null array");
     const int n = p->d.n, m = p->d.m, ncol = n + m + 1;

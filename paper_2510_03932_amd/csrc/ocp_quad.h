@@ -24,6 +24,15 @@ int eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t stre
 int eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream_t stream);
 int eval_hess(const ocp_problem *p, const double *z, const double *y, double sigma, double *hvals,
               hipStream_t stream);
+// Lagrangian derivatives (no coefficient gradient: the model has no
+// coefficient arrays).
+int eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma, double *L,
+                    hipStream_t stream);
+int eval_lag_grad(const ocp_problem *p, const double *z, const double *y, double sigma, double *g,
+                  hipStream_t stream);
+int eval_hvp(const ocp_problem *p, const double *z, const double *y, double sigma, const double *v,
+             double *out, hipStream_t stream);
+int eval_jvp(const ocp_problem *p, const double *z, const double *v, double *out, hipStream_t stream);
 int assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t *perm_h,
                  const int32_t *rowptr, const double *jvals, const double *hvals, const double *reg,
                  double *kkt, hipStream_t stream);

@@ -394,6 +394,215 @@ __global__ __launch_bounds__(kBlock) void quad_assemble_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lagrangian derivatives, L = sigma f + y^T c (the same set as the synthetic
+// family's, without the coefficient gradient: the model has no coefficient
+// arrays).  With the node multiplier yt_i = y_{i,k-1} [k >= 1] + y_ik [k < N]
+// and the right-hand side's partials dF_i/dv on the Jacobian support:
+//   grad_z L at (v, k) = sigma df/dv + (y_{v,k-1} - y_vk) [v state]
+//                        - hh sum_i yt_i dF_i/dv (k) + boundary multipliers
+//   (J v)_ik = (v_{i,k+1} - v_ik) - hh (D_i(k) + D_i(k+1)),
+//              D_i = sum over the support of dF_i/dv v
+//   (H v) at node k: the node's 23 Hessian entries (lower triangle) times v.
+// ---------------------------------------------------------------------------
+
+// Node k's variables (states then controls) from a vector in the layout of z.
+__device__ __forceinline__ void load_node(const QP &P, const double *__restrict__ z, int64_t k, double *v)
+{
+#pragma unroll
+    for (int j = 0; j < kVars; j++) v[j] = z[j * (int64_t)P.N1 + k];
+}
+
+// sigma times the running cost's gradient at node k (weight included).
+__device__ __forceinline__ void cost_grad(const QP &P, int64_t k, const double *x, double sw, double *g)
+{
+    double d[3];
+    refs(P, k, d);
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        g[2 * q] = sw * (x[2 * q] - d[q]);
+        g[2 * q + 1] = 0.0;
+    }
+#pragma unroll
+    for (int j = 6; j < 9; j++) g[j] = sw * x[j];
+#pragma unroll
+    for (int l = 0; l < 4; l++) g[9 + l] = sw * P.r * x[9 + l];
+}
+
+// D_i = sum over row i's support of dF_i/dv v (all nine rows).
+__device__ __forceinline__ void dir_deriv(const Trig &t, const double *u, const double *v, double *D)
+{
+#pragma unroll
+    for (int i = 0; i < kStates; i++) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < kSupLen[i]; p++) s += partial(pair_index(i, p), t, u) * v[kSup[i][p]];
+        D[i] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void quad_lag_partial_kernel(QP P, const double *__restrict__ z,
+                                                                  const double *__restrict__ y, double sigma,
+                                                                  int nchunks, double *__restrict__ partials)
+{
+    __shared__ double Ms[kStates][kBlock];
+    const int tid = threadIdx.x;
+    const int64_t N = P.N;
+    double acc = 0.0;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t k = (int64_t)ch * (kBlock - 1) + tid;
+        double x[kVars], F[kStates];
+        if (k <= N) {
+            load_node(P, z, k, x);
+            rhs(x, x + kStates, P.g, F);
+#pragma unroll
+            for (int i = 0; i < kStates; i++) Ms[i][tid] = x[i] - P.hh * F[i];
+            if (tid < kBlock - 1 || k == N) {
+                double d[3];
+                refs(P, k, d);
+                const double e0 = x[0] - d[0], e2 = x[2] - d[1], e4 = x[4] - d[2];
+                double Lk = e0 * e0 + e2 * e2 + e4 * e4 + x[6] * x[6] + x[7] * x[7] + x[8] * x[8];
+                double uu = 0.0;
+#pragma unroll
+                for (int l = 0; l < 4; l++) uu += x[9 + l] * x[9 + l];
+                Lk += P.r * uu;
+                acc += sigma * (q_weight(P, (int)k) * (0.5 * Lk));
+                const double *yb = y + (int64_t)kStates * N;  // boundary-row multipliers
+                if (P.nb >= kStates && k == 0) {
+#pragma unroll
+                    for (int i = 0; i < kStates; i++) acc += yb[i] * x[i];
+                }
+                if (P.nb >= 2 * kStates && k == N) {
+#pragma unroll
+                    for (int i = 0; i < kStates; i++) acc += yb[kStates + i] * x[i];
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < kBlock - 1 && k < N) {
+#pragma unroll
+            for (int i = 0; i < kStates; i++)
+                acc += y[i * N + k] * (Ms[i][tid + 1] - (x[i] + P.hh * F[i]));
+        }
+        __syncthreads();
+    }
+    const double t = block_sum<kBlock>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void quad_lag_grad_kernel(QP P, const double *__restrict__ z,
+                                                               const double *__restrict__ y, double sigma,
+                                                               double *__restrict__ g)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    const int64_t N = P.N, N1 = P.N1;
+    double x[kVars], yl[kStates], yr[kStates], G[kVars];
+    load_node(P, z, k, x);
+#pragma unroll
+    for (int i = 0; i < kStates; i++) {
+        yl[i] = k >= 1 ? y[i * N + k - 1] : 0.0;
+        yr[i] = k < N ? y[i * N + k] : 0.0;
+    }
+    cost_grad(P, k, x, sigma * q_weight(P, (int)k), G);
+#pragma unroll
+    for (int j = 0; j < kStates; j++) G[j] += yl[j] - yr[j];
+    const Trig t = node_trig(x[6], x[7], x[8]);
+#pragma unroll
+    for (int i = 0; i < kStates; i++) {
+        const double yt = yl[i] + yr[i];
+#pragma unroll
+        for (int p = 0; p < kSupLen[i]; p++)
+            G[kSup[i][p]] -= P.hh * (yt * partial(pair_index(i, p), t, x + kStates));
+    }
+    if (P.nb >= kStates && k == 0) {
+#pragma unroll
+        for (int j = 0; j < kStates; j++) G[j] += y[kStates * N + j];
+    }
+    if (P.nb >= 2 * kStates && k == N) {
+#pragma unroll
+        for (int j = 0; j < kStates; j++) G[j] += y[kStates * N + kStates + j];
+    }
+#pragma unroll
+    for (int j = 0; j < kVars; j++) st_nt(g + j * N1 + k, G[j]);
+}
+
+__global__ __launch_bounds__(kBlock) void quad_hvp_kernel(QP P, const double *__restrict__ z,
+                                                          const double *__restrict__ y, double sigma,
+                                                          const double *__restrict__ v,
+                                                          double *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k > P.N) return;
+    const int64_t N = P.N, N1 = P.N1;
+    double a[3], u[4], Y[kStates], vv[kVars];
+    load_att(P, z, k, a, u);
+    load_node(P, v, k, vv);
+#pragma unroll
+    for (int i = 0; i < kStates; i++) {
+        if (i == 0 || i == 2 || i == 4) {  // linear rows: no curvature
+            Y[i] = 0.0;
+            continue;
+        }
+        double s = 0.0;
+        if (k >= 1) s += y[i * N + k - 1];
+        if (k < N) s += y[i * N + k];
+        Y[i] = s;
+    }
+    const Trig t = node_trig(a[0], a[1], a[2]);
+    double H[kHessNode];
+    hess_values(t, u, Y, sigma * q_weight(P, (int)k), P.r, P.hh, H);
+    double o[kVars];
+#pragma unroll
+    for (int j = 0; j < kVars; j++) o[j] = 0.0;
+#pragma unroll
+    for (int s = 0; s < kHessNode; s++) {
+        const int r = kHessRow[s], c = kHessCol[s];
+        o[r] += H[s] * vv[c];
+        if (r != c) o[c] += H[s] * vv[r];
+    }
+#pragma unroll
+    for (int j = 0; j < kVars; j++) st_nt(out + j * N1 + k, o[j]);
+}
+
+__global__ __launch_bounds__(kBlock) void quad_jvp_kernel(QP P, const double *__restrict__ z,
+                                                          const double *__restrict__ v,
+                                                          double *__restrict__ out)
+{
+    __shared__ double Ms[kStates][kBlock];
+    const int tid = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
+    const int64_t N = P.N;
+    double Pk[kStates];
+    if (k <= N) {
+        double a[3], u[4], vv[kVars], D[kStates];
+        load_att(P, z, k, a, u);
+        load_node(P, v, k, vv);
+        const Trig t = node_trig(a[0], a[1], a[2]);
+        dir_deriv(t, u, vv, D);
+#pragma unroll
+        for (int i = 0; i < kStates; i++) {
+            Ms[i][tid] = vv[i] - P.hh * D[i];
+            Pk[i] = vv[i] + P.hh * D[i];
+        }
+    }
+    __syncthreads();
+    if (tid < kBlock - 1 && k < N) {
+#pragma unroll
+        for (int i = 0; i < kStates; i++) st_nt(out + i * N + k, Ms[i][tid + 1] - Pk[i]);
+    }
+}
+
+// Boundary rows of J v: the direction at the fixed state.
+__global__ __launch_bounds__(kBlock) void quad_bnd_jvp_kernel(QP P, const double *__restrict__ v,
+                                                              double *__restrict__ out)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= P.nb) return;
+    const int64_t node = b < kStates ? 0 : P.N;
+    out[(int64_t)kStates * P.N + b] = v[(int64_t)(b % kStates) * P.N1 + node];
+}
+
 QP make_qp(const ocp_problem *p)
 {
     QP P;
@@ -420,6 +629,47 @@ int eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t str
     if (int rc = check_launch("ocp_eval_obj")) return rc;
     hipLaunchKernelGGL(quad_obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, (int)g, obj);
     return check_launch("ocp_eval_obj");
+}
+
+int eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma, double *L,
+                    hipStream_t stream)
+{
+    const QP P = make_qp(p);
+    const int nchunks = (int)blocks_for(p->d.N, kBlock - 1);
+    const int g = std::min(nchunks, kObjBlocks);
+    hipLaunchKernelGGL(quad_lag_partial_kernel, dim3(g), dim3(kBlock), 0, stream, P, z, y, sigma, nchunks,
+                       p->partials);
+    if (int rc = check_launch("ocp_eval_lagrangian")) return rc;
+    hipLaunchKernelGGL(quad_obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, g, L);
+    return check_launch("ocp_eval_lagrangian");
+}
+
+int eval_lag_grad(const ocp_problem *p, const double *z, const double *y, double sigma, double *g,
+                  hipStream_t stream)
+{
+    hipLaunchKernelGGL(quad_lag_grad_kernel, dim3(blocks_for(p->d.N1, kBlock)), dim3(kBlock), 0, stream,
+                       make_qp(p), z, y, sigma, g);
+    return check_launch("ocp_eval_lag_grad");
+}
+
+int eval_hvp(const ocp_problem *p, const double *z, const double *y, double sigma, const double *v,
+             double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(quad_hvp_kernel, dim3(blocks_for(p->d.N1, kBlock)), dim3(kBlock), 0, stream,
+                       make_qp(p), z, y, sigma, v, out);
+    return check_launch("ocp_eval_hvp");
+}
+
+int eval_jvp(const ocp_problem *p, const double *z, const double *v, double *out, hipStream_t stream)
+{
+    const QP P = make_qp(p);
+    hipLaunchKernelGGL(quad_jvp_kernel, dim3(blocks_for(p->d.N, kBlock - 1)), dim3(kBlock), 0, stream, P, z,
+                       v, out);
+    if (int rc = check_launch("ocp_eval_jvp")) return rc;
+    if (P.nb > 0)
+        hipLaunchKernelGGL(quad_bnd_jvp_kernel, dim3(blocks_for(P.nb, kBlock)), dim3(kBlock), 0, stream, P, v,
+                           out);
+    return check_launch("ocp_eval_jvp");
 }
 
 int eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t stream)
