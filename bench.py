@@ -302,6 +302,38 @@ def differentiation(torch, ocp, synth, reps=20):
     torch.cuda.synchronize()
     out["autograd_forward_backward_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
     prob.close()
+
+    # the same entry points on the quadrotor model at the paper's largest
+    # grid (no coefficient gradient: the model has no coefficient arrays)
+    q = synth.make_quadrotor(synth.QUAD_PAPER, seed=0, bnd=1)
+    qp = ocp.QuadrotorProblem.from_instance(q, dev)
+    qs = qp.sizes
+    qz, qy = torch.from_numpy(q.z).to(dev), torch.from_numpy(q.y).to(dev)
+    qv = torch.from_numpy(np.random.default_rng(2).normal(size=qs["nvar"])).to(dev)
+    qL, qg, qhv = torch.empty(1, **f64), torch.empty(qs["nvar"], **f64), torch.empty(qs["nvar"], **f64)
+    qjv = torch.empty(qs["ncon"], **f64)
+    qv_, qc = qs["nvar"], qs["ncon"]
+    qcalls = {
+        "lagrangian": (lambda: qp.lagrangian(qz, qy, 1.0, out=qL), 8 * (qv_ + qc)),
+        "lag_grad": (lambda: qp.lag_grad(qz, qy, 1.0, out=qg), 8 * (2 * qv_ + qc)),
+        "hvp": (lambda: qp.hvp(qz, qy, qv, 1.0, out=qhv), 8 * (qv_ + qc + 2 * qv_)),
+        "jvp": (lambda: qp.jvp(qz, qv, out=qjv), 8 * (2 * qv_ + qc)),
+    }
+    qout = {"workload": f"quadrotor, x(0) rows, N={q.N}, seed 0"}
+    for name, (fn, nbytes) in qcalls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        qout[name] = {"ms": round(ms, 4), "bytes": nbytes,
+                      "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+    qp.close()
+    out["quadrotor"] = qout
     return out
 
 
