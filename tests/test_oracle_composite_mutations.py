@@ -1,0 +1,133 @@
+"""Plant plausible mistakes in the oracle's Python-level derivative
+compositions (grad_z L = sigma grad f + J^T y, H v from the lower triangle,
+J v, and the coefficient gradient as matrix products) and check that the pins
+of tests/test_oracle_diff_ex_pins.py catch every one, as the C-level mutation
+test does for the C oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_diff_ex_pins as X
+
+_JTY = oracle._grad_plus_jt_y  # the correct composition, before any patch
+
+
+def _jt_y_no_sigma(sigma, grad, jac, jr, jc, y):
+    return _JTY(1.0, grad, jac, jr, jc, y)
+
+
+def _jt_y_defect_rows_only(sigma, grad, jac, jr, jc, y):
+    """Drops the entries of the last rows, as if the boundary rows (which
+    come after the defect rows) were forgotten."""
+    jv, jmu = jac
+    last = jr >= len(y) - max(1, len(y) // 50)
+    return _JTY(sigma, grad, (np.where(last, 0.0, jv), jmu), jr, jc, y)
+
+
+def _jt_y_row_index(sigma, grad, jac, jr, jc, y):
+    g, gmu = grad
+    jv, jmu = jac
+    nv = len(g)
+    yy = y[np.minimum(jr + 1, len(y) - 1)]  # neighbouring row's multiplier
+    out = sigma * g + np.bincount(jc, weights=jv * yy, minlength=nv)
+    mu = abs(sigma) * gmu + np.bincount(jc, weights=jmu * np.abs(yy), minlength=nv)
+    return out, mu
+
+
+def _sym_no_transpose(hess, hr, hc, v):
+    hv, hmu = hess
+    nv = len(v)
+    return (np.bincount(hr, weights=hv * v[hc], minlength=nv),
+            np.bincount(hr, weights=hmu * np.abs(v[hc]), minlength=nv))
+
+
+def _sym_diagonal_twice(hess, hr, hc, v):
+    hv, hmu = hess
+    nv = len(v)
+    out = np.bincount(hr, weights=hv * v[hc], minlength=nv) + np.bincount(hc, weights=hv * v[hr], minlength=nv)
+    mu = (np.bincount(hr, weights=hmu * np.abs(v[hc]), minlength=nv)
+          + np.bincount(hc, weights=hmu * np.abs(v[hr]), minlength=nv))
+    return out, mu
+
+
+def _coo_mv_row_col_swap(jac, jr, jc, v, rows):
+    jv, jmu = jac
+    return (np.bincount(jr, weights=jv * v[np.minimum(jr, len(v) - 1)], minlength=rows),
+            np.bincount(jr, weights=jmu * np.abs(v[np.minimum(jr, len(v) - 1)]), minlength=rows))
+
+
+def _coef_mutant(kind):
+    """A copy of coef_grad_ex with one planted mistake."""
+    def coef_grad_ex(self, inst, scheme=0, bnd=0, y=None):
+        N, n, m = inst.N, inst.n, inst.m
+        y = np.asarray(inst.y if y is None else y, dtype=float)
+        NU = N + 1 if scheme == 0 else N
+        Xv = np.asarray(inst.z[:n * (N + 1)], dtype=float).reshape(n, N + 1)
+        U = np.asarray(inst.z[n * (N + 1):], dtype=float).reshape(m, NU)
+        Y = y[:n * N].reshape(n, N)
+        S = np.sin(Xv)
+        partner = np.arange(n) if kind == "gamma partner" else (np.arange(n) + 1) % n
+        P = Xv * Xv[partner]
+        if scheme == 0:
+            w = 0.5 * (1.0 / N)
+            SA = S[:, :N] if kind == "trapezoid right node" else S[:, :N] + S[:, 1:]
+            UB, PG = U[:, :N] + U[:, 1:], P[:, :N] + P[:, 1:]
+        else:
+            w = (0.5 if kind == "euler weight" else 1.0) * (1.0 / N)
+            SA, UB, PG = S[:, :N], U, P[:, :N]
+        Ya = np.abs(Y)
+        gA, mA = -w * (Y @ SA.T), w * (Ya @ np.abs(SA).T) + 1e-300
+        gB, mB = -w * (Y @ UB.T), w * (Ya @ np.abs(UB).T) + 1e-300
+        gg, mg = -w * np.sum(Y * PG, axis=1), w * np.sum(Ya * np.abs(PG), axis=1) + 1e-300
+        return (gA, gB, gg), (mA, mB, mg)
+    return coef_grad_ex
+
+
+# (name, attribute of the oracle module or of its Oracle class, replacement)
+MUTATIONS = [
+    ("grad_z L without sigma", "_grad_plus_jt_y", _jt_y_no_sigma),
+    ("grad_z L without the last rows", "_grad_plus_jt_y", _jt_y_defect_rows_only),
+    ("grad_z L with a neighbouring multiplier", "_grad_plus_jt_y", _jt_y_row_index),
+    ("H v without the transposed triangle", "_sym_lower_mv", _sym_no_transpose),
+    ("H v with the diagonal counted twice", "_sym_lower_mv", _sym_diagonal_twice),
+    ("J v indexed by row", "_coo_mv", _coo_mv_row_col_swap),
+    ("coefficient gradient without the right node", "Oracle.coef_grad_ex", _coef_mutant("trapezoid right node")),
+    ("coefficient gradient with the trapezoid weight under Euler", "Oracle.coef_grad_ex", _coef_mutant("euler weight")),
+    ("coefficient gradient with gamma's own state as partner", "Oracle.coef_grad_ex", _coef_mutant("gamma partner")),
+]
+
+# pins, each a call that raises when the oracle is wrong
+PINS = [
+    lambda orc: X.test_lag_grad_ex_complex_step(orc, 3, 2, 1, 0, 2),
+    lambda orc: X.test_lag_grad_ex_complex_step(orc, 3, 2, 1, 1, 1),
+    lambda orc: X.test_jvp_ex_complex_step(orc, 3, 2, 1, 1, 2),
+    lambda orc: X.test_hvp_ex_mixed_difference(orc, 2, 3, 1, 0, 1),
+    lambda orc: X.test_hvp_ex_mixed_difference(orc, 2, 3, 1, 1, 0),
+    lambda orc: X.test_coef_grad_ex_complex_step(orc, 5, 3, 2, 0, 0),
+    lambda orc: X.test_coef_grad_ex_complex_step(orc, 5, 3, 2, 1, 2),
+    lambda orc: X.test_quad_lag_grad_complex_step(orc, 2, 1),
+    lambda orc: X.test_quad_hvp_mixed_difference(orc, 2, 1),
+    lambda orc: X.test_quad_jvp_complex_step(orc, 2, 1),
+]
+
+
+def test_pins_pass_on_the_oracle():
+    for pin in PINS:
+        pin(oracle.DEFAULT)
+
+
+@pytest.mark.parametrize("name,attr,repl", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(monkeypatch, name, attr, repl):
+    if attr.startswith("Oracle."):
+        monkeypatch.setattr(oracle.Oracle, attr.split(".", 1)[1], repl)
+    else:
+        monkeypatch.setattr(oracle, attr, repl)
+    caught = 0
+    for pin in PINS:
+        try:
+            pin(oracle.DEFAULT)
+        except AssertionError:
+            caught += 1
+    assert caught > 0, f"no pin catches: {name}"
