@@ -466,8 +466,11 @@ int ocp_batch_eval(const ocp_batch *b, int32_t what, int32_t mode, const double 
 
 /* Capture one ocp_batch_eval (same arguments, pointers bound at capture) into
  * a HIP graph on a private stream and instantiate it.  The graph owns a copy of
- * the tile list, so later configuration changes do not affect it.  Errors: as
- * ocp_batch_eval, plus OCP_ERR_HIP when capture or instantiation fails. */
+ * the tile list, so later configuration changes do not affect it.  It still
+ * reads the batch's coefficients and offset table and the arrays bound at
+ * capture: the batch and those arrays must outlive every launch of the graph.
+ * Errors: as ocp_batch_eval, plus OCP_ERR_HIP when capture or instantiation
+ * fails. */
 int ocp_batch_graph_create(const ocp_batch *b, int32_t what, int32_t mode, const double *z,
                            const double *y, double sigma, double *jac, double *hess,
                            ocp_graph **out);

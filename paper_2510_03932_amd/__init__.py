@@ -535,12 +535,15 @@ class Graph:
     """An instantiated HIP graph of one batched evaluation (pointers bound at
     capture).  launch() replays it on the current torch stream."""
 
-    def __init__(self, handle, device, keep):
+    def __init__(self, handle, device, keep, owner=None):
         self._h = handle
         self.device = device
         self._keep = keep  # tensors the graph reads or writes stay alive with it
+        self._owner = owner  # the batch whose coefficients the graph reads
 
     def launch(self):
+        if self._owner is not None and not self._owner._h.value:
+            raise OcpError(OCP_ERR_ARG, "ocp_graph_launch: the graph's batch has been closed")
         stream = ctypes.c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
         _check(lib().ocp_graph_launch(self._h, stream), "ocp_graph_launch")
 
@@ -649,7 +652,8 @@ class Batch:
         with _torch().cuda.device(self.device):
             _check(lib().ocp_batch_graph_create(self._h, what, MODES[mode], zp, yp, float(sigma), jp,
                                                 hp, ctypes.byref(g)), "ocp_batch_graph_create")
-        return Graph(g, self.device, (z, y, jac, hess)), jac, hess
+        # the graph also reads this batch's coefficients and offset table
+        return Graph(g, self.device, (z, y, jac, hess), owner=self), jac, hess
 
     def autotune(self, z, y=None, sigma=1.0, jac=None, hess=None, what=EVAL_JAC | EVAL_HESS,
                  reps=5, cache: str | None = None, use_cache=True):

@@ -116,8 +116,13 @@ def test_batch_graph_replays(ocp, mode):
         torch.cuda.synchronize()
         assert torch.equal(_bits(gj), _bits(ej)), rep
         assert torch.equal(_bits(gh), _bits(eh)), rep
-    g.close()
     batch.close()
+    # the graph reads the batch's coefficients: once the batch is closed the
+    # binding refuses to replay it (on the host, before any GPU work)
+    with pytest.raises(ocp.OcpError) as e:
+        g.launch()
+    assert e.value.code == ocp.OCP_ERR_ARG
+    g.close()
 
 
 def test_batch_autotune_and_cache(ocp, tmp_path):
