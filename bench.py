@@ -379,6 +379,22 @@ def euler(torch, ocp, synth, reps=10):
                      "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
     t = (out["eval_jac"]["ms"] + out["eval_hess"]["ms"]) * 1e-3
     out["jac_hess_nnz_per_s"] = (s["nnzj"] + s["nnzh"]) / t
+    # the fused evaluation into the KKT values (no reg), against the separate
+    # eval_jac + eval_hess + assemble_kkt above
+    fn = lambda: prob.eval_kkt(z, y, 1.0, None, out=kkt)
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 8 * (nx + n * N + s["nnzk"])  # states and y in, the KKT values out
+    sep = out["eval_jac"]["ms"] + out["eval_hess"]["ms"] + out["assemble_kkt"]["ms"]
+    out["eval_kkt"] = {"ms": round(ms, 4), "bytes": nbytes, "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4),
+                       "speedup_vs_separate": round(sep / ms, 3)}
     prob.close()
     return out
 

@@ -158,9 +158,8 @@ int ocp_create(int64_t N, int32_t n, int32_t m, const double *A, const double *B
                const double *gamma, const double *q, const double *r, ocp_problem **out);
 
 /* ocp_create with transcription options (NULL = defaults).  Every evaluation,
- * the assembly and the Lagrangian derivatives follow the handle's options;
- * the batched entry points accept only the defaults, and ocp_eval_kkt only
- * the trapezoidal scheme (OCP_ERR_ARG otherwise). */
+ * the assembly, the fused ocp_eval_kkt and the Lagrangian derivatives follow
+ * the handle's options; the batched entry points accept only the defaults. */
 int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const double *A,
                   const double *B, const double *gamma, const double *q, const double *r,
                   ocp_problem **out);
@@ -213,8 +212,8 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
  * (nnzk doubles, device, the layout of ocp_build_kkt), without the COO value
  * arrays.  This is what an interior-point iteration factorizes (Sec. 6); the
  * matrix is written once.  Same expressions as the separate calls.  Supports
- * the synthetic family under the trapezoidal scheme (any boundary option);
- * other handles get OCP_ERR_ARG. */
+ * the synthetic family under either scheme and any boundary option; a
+ * quadrotor handle gets OCP_ERR_ARG. */
 int ocp_eval_kkt(const ocp_problem *p, const double *z, const double *y, double sigma, const double *reg,
                  double *kkt, hipStream_t stream);
 

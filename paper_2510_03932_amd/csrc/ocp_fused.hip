@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, 
     constexpr int KT = kDefectTile, LG = 4, W = KT + 1;  // intervals k0 .. k0+KT-1, nodes k0 .. k0+KT
     const int n = P.n, m = P.m, T = P.T, T1 = P.T + 1;
     const int64_t N = P.N, N1 = P.N1;
-    const int64_t nvar = (int64_t)(n + m) * N1;
+    const int64_t nvar = (int64_t)n * N1 + (int64_t)m * P.NU;  // controls on NU nodes
     const int64_t k0 = (int64_t)blockIdx.x * KT;
     const int kn = (int)min((int64_t)KT, N - k0);
     double *xs = lds;                     // [n][W] states
@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, 
     double *cf = rg + n * KT;             // [n][n+m] -hh A | -hh B, then [n] -hh gamma
     double *gs = cf + n * (n + m);
     double *tile = gs + n;                // [KT][T1] output rows
-    const double hh = P.hh;
+    const bool euler = P.scheme != 0;
+    const double hh = euler ? P.h : P.hh;  // the weight of F in a defect row
     for (int x = threadIdx.x; x < n * (n + m); x += kBlock) {
         const int i = x / (n + m), j = x - i * (n + m);
         cf[x] = -hh * (j < n ? P.A[i * n + j] : P.B[i * m + (j - n)]);
@@ -88,7 +89,23 @@ __global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, 
             const int t = w >> LG, kk = w & (KT - 1);
             if (kk >= kn) continue;
             double v;
-            if (t < 2 * n) {
+            if (euler) {
+                // row i: X_0..X_i at k, X_i at k+1, X_{i+1}..X_{n-1} at k, U at k
+                if (t == i + 1) {
+                    v = 1.0;
+                } else if (t <= n) {
+                    const int j = t <= i ? t : t - 1;
+                    const int jn = (j + 1 == n) ? 0 : j + 1;
+                    const int jp = (j == 0) ? n - 1 : j - 1;
+                    v = cf[i * (n + m) + j] * cs[j * W + kk];
+                    if (i == j) v += gs[j] * xs[jn * W + kk] - 1.0;
+                    if (i == jp) v += gs[jp] * xs[jp * W + kk];
+                } else if (t < T) {
+                    v = cf[i * (n + m) + n + (t - n - 1)];
+                } else {
+                    v = rg[(i << LG) + kk];
+                }
+            } else if (t < 2 * n) {
                 const int j = t >> 1, s = t & 1, u = kk + s;
                 const int jn = (j + 1 == n) ? 0 : j + 1;
                 const int jp = (j == 0) ? n - 1 : j - 1;
@@ -123,7 +140,8 @@ __global__ __launch_bounds__(kBlock) void kkt_var_kernel(KP P, KKTLayout Lo, con
     const bool live = k <= P.N;
     const int kn = min(kBlock, P.N1 - k0);
     const int n = P.n, m = P.m;
-    const int64_t N = P.N, N1 = P.N1;
+    const int64_t N = P.N, N1 = P.N1, NU = P.NU;
+    const bool euler = P.scheme != 0;
     const double w = node_weight(P, k);
     double x[NB], yl[NB], yr[NB];
 #pragma unroll
@@ -136,9 +154,12 @@ __global__ __launch_bounds__(kBlock) void kkt_var_kernel(KP P, KKTLayout Lo, con
             if (k < P.N) yr[i] = yi[0];
         }
     }
+    // node multiplier: F at node k enters rows (i, k-1) and (i, k), or only
+    // (i, k) under forward Euler
     double yt[NB];
 #pragma unroll
-    for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
+    for (int i = 0; i < NB; i++) yt[i] = euler ? yr[i] : yl[i] + yr[i];
+    const double wF = euler ? P.h : P.hh;
     // Hessian values of the node, as in eval_hess: state diagonals and the
     // bilinear entries (pair i couples states i and i+1 mod n)
     double dg[NB], pr[NB];
@@ -151,15 +172,15 @@ __global__ __launch_bounds__(kBlock) void kkt_var_kernel(KP P, KKTLayout Lo, con
             double s = 0.0;
 #pragma unroll
             for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
-            double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
-            if (n == 1) v -= P.h * yt[0] * P.gam[0];
+            double v = 2.0 * sigma * w * P.q[j] + wF * sx * s;
+            if (n == 1) v -= euler ? 2.0 * P.h * yt[0] * P.gam[0] : P.h * yt[0] * P.gam[0];
             if (live && reg) v += reg[j * N1 + k];
             dg[j] = v;
         }
     }
 #pragma unroll
-    for (int i = 0; i < NB; i++) pr[i] = i < n ? -P.hh * yt[i] * P.gam[i] : 0.0;
-    if (n == 2) pr[0] = -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]);
+    for (int i = 0; i < NB; i++) pr[i] = i < n ? -wF * yt[i] * P.gam[i] : 0.0;
+    if (n == 2) pr[0] = -wF * (yt[0] * P.gam[0] + yt[1] * P.gam[1]);
     // state block a: rows (a, k0 .. k0+kn-1) are one contiguous CSR range of
     // kn * len[a] entries, staged in LDS and written with contiguous stores
 #pragma unroll
@@ -182,12 +203,12 @@ __global__ __launch_bounds__(kBlock) void kkt_var_kernel(KP P, KKTLayout Lo, con
             __syncthreads();
         }
     }
-    if (live) {
+    if (live && k < NU) {  // controls exist on NU nodes
         const int64_t NX = (int64_t)n * N1;
         for (int l = 0; l < m; l++) {
             double v = 2.0 * sigma * w * P.r[l];
-            if (reg) v += reg[NX + l * N1 + k];
-            st_nt(kkt + Lo.ctrl_start + l * N1 + k, v);
+            if (reg) v += reg[NX + l * NU + k];
+            st_nt(kkt + Lo.ctrl_start + l * NU + k, v);
         }
     }
 }
@@ -215,8 +236,8 @@ int ocp_eval_kkt(const ocp_problem *p, const double *z, const double *y, double 
     if (!z || !y || !kkt) return fail(OCP_ERR_ARG, "ocp_eval_kkt: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_kkt: sigma is not finite");
     const Dims &d = p->d;
-    if (p->model != 0 || d.scheme != OCP_SCHEME_TRAPEZOIDAL)
-        return fail(OCP_ERR_ARG, "ocp_eval_kkt: supports the synthetic family's trapezoidal scheme only");
+    if (p->model != 0)
+        return fail(OCP_ERR_ARG, "ocp_eval_kkt: supports the synthetic dynamics family only");
     // state-row layout of ocp_build_kkt: row (a, k) holds the bilinear
     // entries whose larger index is a, then the diagonal
     KKTLayout Lo;

@@ -1,4 +1,5 @@
-"""GPU parity of the fused evaluation into the KKT matrix (ocp_eval_kkt):
+"""GPU parity of the fused evaluation into the KKT matrix (ocp_eval_kkt), under
+both schemes and every boundary option:
 against the oracle's Jacobian and Hessian assembled by the oracle (values
 within 1e-12 * mu, the magnitudes assembled the same way), and against the
 separate path eval_jac + eval_hess + assemble_kkt (same expressions; the
@@ -42,15 +43,19 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda", 0))
 
 
-@pytest.mark.parametrize("N,n,m,bnd", SHAPES)
-def test_fused_matches_oracle_and_separate_path(ocp, N, n, m, bnd):
-    _say(f"[fused] N={N} n={n} m={m} bnd={bnd}")
+EULER_SHAPES = [(1000, 4, 2, 0), (777, 5, 3, 2), (1, 1, 0, 0), (1, 1, 1, 1), (2, 2, 1, 2), (3, 3, 0, 1),
+                (257, 16, 8, 0), (65, 7, 2, 1), (513, 32, 32, 2), (4097, 8, 4, 0)]
+
+
+@pytest.mark.parametrize("N,n,m,bnd,scheme", [s + (0,) for s in SHAPES] + [s + (1,) for s in EULER_SHAPES])
+def test_fused_matches_oracle_and_separate_path(ocp, N, n, m, bnd, scheme):
+    _say(f"[fused] N={N} n={n} m={m} bnd={bnd} scheme={scheme}")
     dev = torch.device("cuda", 0)
-    inst = synth.make_instance(N, n, m, seed=41, bnd=bnd)
+    inst = synth.make_instance(N, n, m, seed=41, bnd=bnd, scheme=scheme)
     prob = ocp.Problem.from_instance(inst, dev)
     s = prob.sizes
     z, y = _t(inst.z), _t(inst.y)
-    rp, ci, pj, ph = ocp.kkt_pattern(N, n, m, boundary=bnd)
+    rp, ci, pj, ph = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd)
     reg = np.random.default_rng(5).normal(size=s["dim"])
     for r in (None, reg):
         rt = None if r is None else _t(r)
@@ -58,8 +63,8 @@ def test_fused_matches_oracle_and_separate_path(ocp, N, n, m, bnd):
         fused = prob.eval_kkt(z, y, 0.7, rt, out=out).cpu().numpy()
         jv, hv = prob.jac(z), prob.hess(z, y, 0.7)
         sep = prob.assemble_kkt(_t(pj), _t(ph), _t(rp), jv, hv, rt).cpu().numpy()
-        oj, mj = oracle.jac_ex(inst, 0, bnd)
-        oh, mh = oracle.hess_ex(inst, 0, bnd, sigma=0.7)
+        oj, mj = oracle.jac_ex(inst, scheme, bnd)
+        oh, mh = oracle.hess_ex(inst, scheme, bnd, sigma=0.7)
         want = oracle.assemble(rp, pj, oj, ph, oh, r)
         mu = oracle.assemble(rp, pj, mj, ph, mh, None if r is None else np.abs(r))
         differ = np.flatnonzero(fused.view(np.uint64) != sep.view(np.uint64))
@@ -102,14 +107,8 @@ def test_fused_large_equals_separate_path(ocp):
     torch.cuda.empty_cache()
 
 
-def test_fused_rejects_other_handles(ocp):
+def test_fused_rejects_quadrotor_handles(ocp):
     dev = torch.device("cuda", 0)
-    inst = synth.make_instance(10, 3, 1, seed=42, scheme=1)
-    prob = ocp.Problem.from_instance(inst, dev)
-    with pytest.raises(ocp.OcpError) as e:
-        prob.eval_kkt(_t(inst.z), _t(inst.y))
-    assert e.value.code == ocp.OCP_ERR_ARG
-    prob.close()
     q = synth.make_quadrotor(10, seed=43)
     prob = ocp.QuadrotorProblem.from_instance(q, dev)
     with pytest.raises(ocp.OcpError) as e:

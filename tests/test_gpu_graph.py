@@ -100,7 +100,7 @@ def test_graph_replays_equal_eager_synthetic(ocp, N, n, m, scheme, bnd):
         return other.z, other.y
 
     pattern = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd, colind=False)
-    _run(ocp, prob, pattern, _points(point, 3), fused=(scheme == 0))
+    _run(ocp, prob, pattern, _points(point, 3), fused=True)
     prob.close()
 
 
