@@ -466,6 +466,13 @@ def quadrotor(torch, ocp, synth, reps=10):
             torch.cuda.synchronize()
             return e0.elapsed_time(e1) / reps
 
+        # the fused evaluation into the KKT values, against jac + hess + assemble
+        r["eval_kkt"] = {"ms": round(timed_steps(lambda: prob.eval_kkt(z, y, 1.0, None, out=kkt)), 4)}
+        nb_fused = 8 * (7 * N1 + 6 * N + s["nnzk"])  # attitude, controls, y in; KKT values out
+        r["eval_kkt"]["bytes"] = nb_fused
+        r["eval_kkt"]["hbm_frac"] = round(nb_fused / (r["eval_kkt"]["ms"] * 1e-3) / HBM_PEAK, 4)
+        sep = r["eval_jac"]["ms"] + r["eval_hess"]["ms"] + r["assemble_kkt"]["ms"]
+        r["eval_kkt"]["speedup_vs_separate"] = round(sep / r["eval_kkt"]["ms"], 3)
         r["eager_step_ms"] = round(timed_steps(step), 4)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):

@@ -212,8 +212,8 @@ int ocp_assemble_kkt(const ocp_problem *p, const int32_t *perm_j, const int32_t 
  * (nnzk doubles, device, the layout of ocp_build_kkt), without the COO value
  * arrays.  This is what an interior-point iteration factorizes (Sec. 6); the
  * matrix is written once.  Same expressions as the separate calls.  Supports
- * the synthetic family under either scheme and any boundary option; a
- * quadrotor handle gets OCP_ERR_ARG. */
+ * the synthetic family under either scheme and any boundary option, and the
+ * quadrotor model (the layout of ocp_quad_kkt). */
 int ocp_eval_kkt(const ocp_problem *p, const double *z, const double *y, double sigma, const double *reg,
                  double *kkt, hipStream_t stream);
 
@@ -364,9 +364,9 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
  *
  * A handle from ocp_quad_create works with ocp_problem_sizes, ocp_eval_obj,
  * ocp_eval_grad, ocp_eval_cons, ocp_eval_jac, ocp_eval_hess,
- * ocp_assemble_kkt, ocp_eval_lagrangian, ocp_eval_lag_grad, ocp_eval_hvp,
- * ocp_eval_jvp and ocp_destroy, with the arrays and layouts above.
- * ocp_set_coefficients, ocp_eval_coef_grad and ocp_eval_kkt reject it
+ * ocp_assemble_kkt, ocp_eval_kkt, ocp_eval_lagrangian, ocp_eval_lag_grad,
+ * ocp_eval_hvp, ocp_eval_jvp and ocp_destroy, with the arrays and layouts
+ * above.  ocp_set_coefficients and ocp_eval_coef_grad reject it
  * (OCP_ERR_ARG).
  * ------------------------------------------------------------------------- */
 

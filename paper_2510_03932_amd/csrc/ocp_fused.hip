@@ -236,8 +236,7 @@ int ocp_eval_kkt(const ocp_problem *p, const double *z, const double *y, double 
     if (!z || !y || !kkt) return fail(OCP_ERR_ARG, "ocp_eval_kkt: null array");
     if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, "ocp_eval_kkt: sigma is not finite");
     const Dims &d = p->d;
-    if (p->model != 0)
-        return fail(OCP_ERR_ARG, "ocp_eval_kkt: supports the synthetic dynamics family only");
+    if (p->model == quad::kModel) return quad::eval_kkt(p, z, y, sigma, reg, kkt, stream);
     // state-row layout of ocp_build_kkt: row (a, k) holds the bilinear
     // entries whose larger index is a, then the diagonal
     KKTLayout Lo;

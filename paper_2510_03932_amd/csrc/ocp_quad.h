@@ -24,6 +24,10 @@ int eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t stre
 int eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream_t stream);
 int eval_hess(const ocp_problem *p, const double *z, const double *y, double sigma, double *hvals,
               hipStream_t stream);
+// Fused evaluation of the Jacobian and Hessian values (+ reg) into the KKT
+// values of ocp_quad_kkt's layout.
+int eval_kkt(const ocp_problem *p, const double *z, const double *y, double sigma, const double *reg,
+             double *kkt, hipStream_t stream);
 // Lagrangian derivatives (no coefficient gradient: the model has no
 // coefficient arrays).
 int eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma, double *L,

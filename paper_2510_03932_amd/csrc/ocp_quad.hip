@@ -603,6 +603,138 @@ __global__ __launch_bounds__(kBlock) void quad_bnd_jvp_kernel(QP P, const double
     out[(int64_t)kStates * P.N + b] = v[(int64_t)(b % kStates) * P.N1 + node];
 }
 
+// ---------------------------------------------------------------------------
+// Fused evaluation into the KKT values (ocp_eval_kkt for a quadrotor
+// handle): the values eval_jac, eval_hess and assemble_kkt give with the slot
+// maps of ocp_quad_kkt, written straight into the CSR rows.  Row layout (that
+// of the host builder): variable v's row at node k holds its len_v Hessian
+// entries (the diagonal last, + reg) at var_start[v] + len_v k; defect row
+// (i, k) holds its 2 kSupLen[i] Jacobian entries, then its diagonal (reg or
+// 0), at def_start[i] + (2 kSupLen[i] + 1) k; boundary row b holds 1 and its
+// diagonal at bnd_start + 2 b.
+// ---------------------------------------------------------------------------
+struct QLayout {
+    int64_t var_start[kVars];
+    int64_t def_start[kStates];
+    int64_t bnd_start;
+};
+
+// Variable rows: one lane per node computes the node's 23 Hessian values;
+// each variable's rows of the workgroup's nodes with more than one entry are
+// staged in LDS and written with contiguous stores.
+__global__ __launch_bounds__(kBlock) void quad_kkt_var_kernel(QP P, QLayout Lo, const double *__restrict__ z,
+                                                              const double *__restrict__ y, double sigma,
+                                                              const double *__restrict__ reg,
+                                                              double *__restrict__ kkt)
+{
+    __shared__ double buf[4 * kBlock];  // one variable's rows of the workgroup (<= 4 entries each)
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock, k = k0 + threadIdx.x;
+    const bool live = k <= P.N;
+    const int kn = (int)min((int64_t)kBlock, (int64_t)P.N1 - k0);
+    const int64_t N = P.N, N1 = P.N1;
+    double H[kHessNode];
+#pragma unroll
+    for (int s = 0; s < kHessNode; s++) H[s] = 0.0;
+    if (live) {
+        double a[3], u[4], Y[kStates];
+        load_att(P, z, k, a, u);
+#pragma unroll
+        for (int i = 0; i < kStates; i++) {
+            if (i == 0 || i == 2 || i == 4) {  // linear rows: no curvature
+                Y[i] = 0.0;
+                continue;
+            }
+            double sy = 0.0;
+            if (k >= 1) sy += y[i * N + k - 1];
+            if (k < N) sy += y[i * N + k];
+            Y[i] = sy;
+        }
+        const Trig t = node_trig(a[0], a[1], a[2]);
+        hess_values(t, u, Y, sigma * q_weight(P, (int)k), P.r, P.hh, H);
+        if (reg) {
+#pragma unroll
+            for (int v = 0; v < kVars; v++) H[kHessFirst[v + 1] - 1] += reg[v * N1 + k];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < kVars; v++) {
+        const int f = kHessFirst[v], len = kHessFirst[v + 1] - f;
+        if (len == 1) {  // one entry per row: the lanes' stores are contiguous already
+            if (live) st_nt(kkt + Lo.var_start[v] + k, H[f]);
+            continue;
+        }
+        if (live) {
+#pragma unroll
+            for (int e = 0; e < len; e++) buf[threadIdx.x * len + e] = H[f + e];
+        }
+        __syncthreads();
+        double *out = kkt + Lo.var_start[v] + k0 * len;
+        for (int x = threadIdx.x; x < kn * len; x += kBlock) st_nt(out + x, buf[x]);
+        __syncthreads();
+    }
+}
+
+// Defect rows: one lane per interval evaluates the right-hand side's partials
+// at its two nodes; each row block's rows of the workgroup are staged in LDS
+// and written with contiguous stores.
+__global__ __launch_bounds__(kBlock) void quad_kkt_defect_kernel(QP P, QLayout Lo, const double *__restrict__ z,
+                                                                 const double *__restrict__ reg,
+                                                                 double *__restrict__ kkt)
+{
+    __shared__ double buf[(2 * 6 + 1) * kBlock];  // one row block's rows (<= 12 entries + diagonal)
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock, k = k0 + threadIdx.x;
+    const bool live = k < P.N;
+    const int kn = (int)min((int64_t)kBlock, (int64_t)P.N - k0);
+    const int64_t N = P.N, N1 = P.N1;
+    const int64_t nvar = (int64_t)kVars * N1;
+    Trig tr[2];
+    double u[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        tr[s] = Trig{};
+#pragma unroll
+        for (int l = 0; l < 4; l++) u[s][l] = 0.0;
+        if (live) {
+            double a[3];
+            load_att(P, z, k + s, a, u[s]);
+            tr[s] = node_trig(a[0], a[1], a[2]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kStates; i++) {
+        const int L = kSupLen[i], len = 2 * L + 1;
+        if (live) {
+            double *row = buf + threadIdx.x * len;
+#pragma unroll
+            for (int p = 0; p < L; p++) {
+                const int q = pair_index(i, p);
+                const bool own = pair_is_own_state(i, p);
+#pragma unroll
+                for (int s = 0; s < 2; s++) {
+                    const double id = own ? (s ? 1.0 : -1.0) : 0.0;
+                    row[2 * p + s] = id - P.hh * partial(q, tr[s], u[s]);
+                }
+            }
+            row[len - 1] = reg ? reg[nvar + i * N + k] : 0.0;
+        }
+        __syncthreads();
+        double *out = kkt + Lo.def_start[i] + k0 * len;
+        for (int x = threadIdx.x; x < kn * len; x += kBlock) st_nt(out + x, buf[x]);
+        __syncthreads();
+    }
+}
+
+// Boundary rows: their state entry (1) and their diagonal.
+__global__ __launch_bounds__(kBlock) void quad_kkt_bnd_kernel(QP P, QLayout Lo, const double *__restrict__ reg,
+                                                              double *__restrict__ kkt)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= P.nb) return;
+    const int64_t row = (int64_t)kVars * P.N1 + (int64_t)kStates * P.N + b;
+    kkt[Lo.bnd_start + 2 * b] = 1.0;
+    kkt[Lo.bnd_start + 2 * b + 1] = reg ? reg[row] : 0.0;
+}
+
 QP make_qp(const ocp_problem *p)
 {
     QP P;
@@ -629,6 +761,34 @@ int eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t str
     if (int rc = check_launch("ocp_eval_obj")) return rc;
     hipLaunchKernelGGL(quad_obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, (int)g, obj);
     return check_launch("ocp_eval_obj");
+}
+
+int eval_kkt(const ocp_problem *p, const double *z, const double *y, double sigma, const double *reg,
+             double *kkt, hipStream_t stream)
+{
+    const QP P = make_qp(p);
+    const int64_t N = p->d.N, N1 = p->d.N1;
+    QLayout Lo;
+    int64_t o = 0;
+    for (int v = 0; v < kVars; v++) {
+        Lo.var_start[v] = o;
+        o += (int64_t)(kHessFirst[v + 1] - kHessFirst[v]) * N1;
+    }
+    for (int i = 0; i < kStates; i++) {
+        Lo.def_start[i] = o;
+        o += (int64_t)(kRowSlot[i + 1] - kRowSlot[i] + 1) * N;
+    }
+    Lo.bnd_start = o;
+    hipLaunchKernelGGL(quad_kkt_defect_kernel, dim3(blocks_for(N, kBlock)), dim3(kBlock), 0, stream, P, Lo, z,
+                       reg, kkt);
+    if (int rc = check_launch("ocp_eval_kkt")) return rc;
+    hipLaunchKernelGGL(quad_kkt_var_kernel, dim3(blocks_for(N1, kBlock)), dim3(kBlock), 0, stream, P, Lo, z, y,
+                       sigma, reg, kkt);
+    if (int rc = check_launch("ocp_eval_kkt")) return rc;
+    if (P.nb > 0)
+        hipLaunchKernelGGL(quad_kkt_bnd_kernel, dim3(blocks_for(P.nb, kBlock)), dim3(kBlock), 0, stream, P, Lo,
+                           reg, kkt);
+    return check_launch("ocp_eval_kkt");
 }
 
 int eval_lagrangian(const ocp_problem *p, const double *z, const double *y, double sigma, double *L,

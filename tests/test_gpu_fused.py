@@ -107,11 +107,51 @@ def test_fused_large_equals_separate_path(ocp):
     torch.cuda.empty_cache()
 
 
-def test_fused_rejects_quadrotor_handles(ocp):
+QUAD_SHAPES = [(1, 0), (1, 2), (2, 1), (255, 1), (256, 0), (257, 2), (1000, 1), (4097, 1)]
+
+
+@pytest.mark.parametrize("N,bnd", QUAD_SHAPES)
+def test_fused_quadrotor_matches_oracle_and_separate_path(ocp, N, bnd):
+    """The quadrotor model's fused KKT against the oracle's Jacobian and
+    Hessian assembled by the oracle, and against the separate path."""
+    _say(f"[fused quad] N={N} bnd={bnd}")
     dev = torch.device("cuda", 0)
-    q = synth.make_quadrotor(10, seed=43)
+    q = synth.make_quadrotor(N, seed=44, bnd=bnd)
     prob = ocp.QuadrotorProblem.from_instance(q, dev)
-    with pytest.raises(ocp.OcpError) as e:
-        prob.eval_kkt(_t(q.z), _t(q.y))
-    assert e.value.code == ocp.OCP_ERR_ARG
+    s = prob.sizes
+    z, y = _t(q.z), _t(q.y)
+    rp, ci, pj, ph = ocp.quad_kkt_pattern(N, bnd)
+    reg = np.random.default_rng(6).normal(size=s["dim"])
+    for r in (None, reg):
+        rt = None if r is None else _t(r)
+        out = torch.full((s["nnzk"],), float("nan"), dtype=torch.float64, device=dev)
+        fused = prob.eval_kkt(z, y, 0.7, rt, out=out).cpu().numpy()
+        sep = prob.assemble_kkt(_t(pj), _t(ph), _t(rp), prob.jac(z), prob.hess(z, y, 0.7), rt).cpu().numpy()
+        oj, mj = oracle.quad_jac(q)
+        oh, mh = oracle.quad_hess(q, sigma=0.7)
+        want = oracle.assemble(rp, pj, oj, ph, oh, r)
+        mu = oracle.assemble(rp, pj, mj, ph, mh, None if r is None else np.abs(r))
+        check_close(fused, want, mu, what=f"quad kkt reg={r is not None}")
+        check_close(fused, sep, mu, what=f"quad fused vs separate reg={r is not None}")
     prob.close()
+
+
+def test_fused_quadrotor_large_equals_separate_path(ocp):
+    """The quadrotor at N = 1e6 with reg: the fused KKT against the separate
+    path on the device (1e-12 relative plus 1e-18 absolute)."""
+    _say("[fused quad] large")
+    N = synth.QUAD_LARGE
+    dev = torch.device("cuda", 0)
+    q = synth.make_quadrotor(N, seed=0, bnd=1)
+    prob = ocp.QuadrotorProblem.from_instance(q, dev)
+    s = prob.sizes
+    z, y = _t(q.z), _t(q.y)
+    reg = torch.full((s["dim"],), 1e-8, dtype=torch.float64, device=dev)
+    fused = prob.eval_kkt(z, y, 1.0, reg)
+    rp, _, pj, ph = ocp.quad_kkt_pattern(N, 1, colind=False)
+    sep = prob.assemble_kkt(_t(pj), _t(ph), _t(rp), prob.jac(z), prob.hess(z, y, 1.0), reg)
+    diff = (fused - sep).abs()
+    assert bool((diff <= 1e-12 * (fused.abs() + sep.abs()) + 1e-18).all())
+    prob.close()
+    del fused, sep
+    torch.cuda.empty_cache()

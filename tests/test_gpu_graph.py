@@ -115,5 +115,5 @@ def test_graph_replays_equal_eager_quadrotor(ocp, N, bnd):
         return q.z, q.y
 
     pattern = ocp.quad_kkt_pattern(N, bnd, colind=False)
-    _run(ocp, prob, pattern, _points(point, 3), fused=False)
+    _run(ocp, prob, pattern, _points(point, 3), fused=True)
     prob.close()
