@@ -24,6 +24,7 @@ namespace ocp {
 namespace dev {
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));  // FP64 MFMA 16x16 accumulator
 typedef int32_t int2v __attribute__((ext_vector_type(2)));
 
 constexpr int kBlock = 256;  // threads per workgroup of the single-instance kernels (4 waves)

@@ -52,7 +52,6 @@ static int check_coefficients(const ocp_problem *p, const char *what)
 
 namespace {
 
-constexpr int kCols = 8;  // coefficient-gradient columns per workgroup
 
 // Lagrangian value, pass 1.  Chunk c covers nodes [c (B-1), c (B-1) + B) and
 // closes the B-1 intervals starting there (one node of overlap, as in the
@@ -323,53 +322,175 @@ __global__ __launch_bounds__(kBlock) void bnd_jvp_kernel(KP P, const double *__r
     out[(int64_t)P.n * P.N + b] = v[(int64_t)i * P.N1 + node];
 }
 
-// Coefficient gradient, pass 1.  Grid (G, n, ceil((n+m+1)/kCols)): row i,
-// columns c0 .. c0+kCols-1 of [A row i | B row i | gamma_i]; lanes take nodes
-// k = blockIdx.x * B + lane + s G B in order; each column's workgroup total
-// goes to cpart[(i (n+m+1) + col) G + blockIdx.x].
-__global__ __launch_bounds__(kBlock) void coef_partial_kernel(KP P, const double *__restrict__ z,
-                                                              const double *__restrict__ y, int G,
-                                                              double *__restrict__ cpart)
+// Coefficient gradient, pass 1.  With yt_i(k) the multiplier weight of node
+// k in row block i (y_{i,k-1} + y_{i,k} for the trapezoid, y_{i,k} for
+// forward Euler), the sums S_ij = sum_k yt_i sin X_j and S_il = sum_k yt_i
+// U_l are the product of the (n x N+1) matrix yt with the (N+1 x n+m)
+// matrix [sin X | U]: a contraction over the nodes, done here on the FP64
+// matrix cores.  The gamma sums S_i = sum_k yt_i X_i X_p(i) are one per row
+// and are summed on the vector units.
+//
+// Workgroup b takes the chunks of kCoefChunk nodes b, b + G, ...  Per chunk:
+// (1) the lanes stage y and the raw columns [X | U] at the chunk's nodes in
+// LDS, one node per lane and half of the columns and rows per half
+// workgroup, with coalesced loads; (2) each lane adds the gamma terms of its
+// node for the rows of its half; (3) the sines are taken in place, once per
+// entry, spread over all lanes; (4) wave w feeds its kCoefChunk / 4 nodes to
+// v_mfma_f64_16x16x4f64, 4 nodes per instruction (lane l supplies row or
+// column l mod 16 at node l / 16 of the step), accumulating every 16 x 16
+// block of the product.  At the end the 4 waves' blocks are added in order in
+// LDS and the entries go to cpart[(i (n+m+1) + col) G + b], col n+m holding
+// the gamma sum.  MB = ceil(n / 16) row blocks, NBK = ceil((n+m) / 16)
+// column blocks.
+template <int MB, int NBK>
+__global__ __launch_bounds__(kBlock, MB == 1 && NBK <= 2 ? 2 : 1) void coef_partial_kernel(
+    KP P, const double *__restrict__ z, const double *__restrict__ y, int G, double *__restrict__ cpart)
 {
-    __shared__ double ws[kCols][kBlock / 64];
+    constexpr int W = kBlock / 64, CH = kCoefChunk, LD = CH + 2;  // LD: row stride, spreads LDS banks
+    constexpr int HR = 8 * MB, HC = 8 * NBK;                     // rows and columns per half workgroup
+    static_assert(kBlock == 2 * CH, "two lanes per node in the staging pass");
+    static_assert(W * MB * NBK * 256 <= (16 * NBK + 16 * MB) * LD, "block sums fit the staging area");
+    __shared__ double sh[(16 * NBK + 16 * MB) * LD];
+    __shared__ double gs[W][HR];
+    double(*Vl)[LD] = reinterpret_cast<double(*)[LD]>(sh);
+    double(*Yl)[LD] = reinterpret_cast<double(*)[LD]>(sh + 16 * NBK * LD);
     const int n = P.n, m = P.m, ncol = n + m + 1;
-    const int i = blockIdx.y, c0 = blockIdx.z * kCols;
-    const int p = (i + 1 == n) ? 0 : i + 1;
-    const int64_t N = P.N, N1 = P.N1;
-    double acc[kCols];
-#pragma unroll
-    for (int c = 0; c < kCols; c++) acc[c] = 0.0;
-    const int64_t NU = P.NU;
+    // w and h are the same across a wave: readfirstlane lets the compiler
+    // keep what derives from them (row and column pointers) in scalar
+    // registers
+    const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int slot = t & (CH - 1), h = __builtin_amdgcn_readfirstlane(t >> 7);  // staging: node slot, half
+    const int j16 = lane & 15, kq = lane >> 4;
+    const int64_t N = P.N, N1 = P.N1, NU = P.NU;
     const bool euler = P.scheme != 0;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k <= N; k += (int64_t)G * kBlock) {
-        const double *yi = y + i * N + k;
-        // node multiplier: F at node k enters rows (i, k-1) and (i, k), or
-        // only (i, k) under forward Euler
-        const double yt = euler ? (k < N ? yi[0] : 0.0) : (k >= 1 ? yi[-1] : 0.0) + (k < N ? yi[0] : 0.0);
+    d4 acc[MB][NBK];
 #pragma unroll
-        for (int c = 0; c < kCols; c++) {
-            const int col = c0 + c;
-            if (col < n) acc[c] += yt * sin(z[col * N1 + k]);
-            else if (col < n + m) {
-                if (k < NU) acc[c] += yt * z[n * N1 + (col - n) * NU + k];
-            } else if (col == n + m) acc[c] += yt * (z[i * N1 + k] * z[p * N1 + k]);
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int cb = 0; cb < NBK; cb++) acc[mb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+    double gam[HR];
+#pragma unroll
+    for (int rr = 0; rr < HR; rr++) gam[rr] = 0.0;
+    // (1) Staging.  Every load is unconditional, from an index clamped into
+    // its row, and all are issued before the first LDS store, so that they
+    // are in flight together; values past a row's end (and the last chunk's
+    // tail) are scaled to 0 when stored (a multiply, not a select, which the
+    // compiler would turn into a branch per load).  The rows of y are
+    // staged shifted by one slot: Yl[r][s + 1] = y_{r, base + s} (0 from node
+    // N on) and Yl[r][0] = y_{r, base - 1}, so that yt = Yl[r][s + 1] +
+    // Yl[r][s] for the trapezoid.
+    double xv[HC], yv[HR], hv[HR];
+    // Each load is a uniform row pointer at the chunk's first node (or at
+    // the row's start when the row ends before the chunk) plus a 32-bit lane
+    // offset clamped to the row's last node, so that no per-lane 64-bit
+    // address has to stay live across the chunk loop.
+    auto issue = [&](int64_t b0) {
+#pragma unroll
+        for (int jj = 0; jj < HC; jj++) {
+            const int c = HC * h + jj;
+            const bool isx = c < n, isu = !isx && c < n + m;
+            const double *src = isx ? z + c * N1 : isu ? z + n * N1 + (c - n) * NU : z;
+            const int64_t last = isx ? N : isu ? NU - 1 : -1;
+            const int64_t span = last - b0;  // lanes slot <= span hold nodes of the row
+            const double *pb = span >= 0 ? src + b0 : src;
+            const uint32_t lim = span >= 0 ? (uint32_t)(span < CH - 1 ? span : CH - 1) : 0u;
+            xv[jj] = pb[(uint32_t)slot < lim ? (uint32_t)slot : lim];
         }
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        const int64_t rspan = N - 1 - b0;  // lanes slot <= rspan hold nodes k < N
+        const uint32_t rlim = rspan >= 0 ? (uint32_t)(rspan < CH - 1 ? rspan : CH - 1) : 0u;
+        const uint32_t ri = (uint32_t)slot < rlim ? (uint32_t)slot : rlim;
 #pragma unroll
-    for (int c = 0; c < kCols; c++) {
-        const double t = wave_sum(acc[c]);
-        if (lane == 0) ws[c][wid] = t;
+        for (int rr = 0; rr < HR; rr++) {
+            const int r = HR * h + rr;
+            const double *yi = y + (int64_t)(r < n ? r : 0) * N;
+            yv[rr] = (rspan >= 0 ? yi + b0 : yi)[ri];
+            hv[rr] = yi[b0 >= 1 ? b0 - 1 : 0];
+        }
+    };
+    auto stage = [&](int64_t b0) {
+        const int64_t k = b0 + slot;
+#pragma unroll
+        for (int jj = 0; jj < HC; jj++) {
+            const int c = HC * h + jj;
+            const int64_t last = c < n ? N : c < n + m ? NU - 1 : -1;
+            Vl[c][slot] = xv[jj] * (k <= last ? 1.0 : 0.0);
+        }
+        const double fr = k < N ? 1.0 : 0.0, fh = b0 >= 1 ? 1.0 : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < HR; rr++) {
+            const int r = HR * h + rr;
+            const double live = r < n ? 1.0 : 0.0;
+            Yl[r][slot + 1] = yv[rr] * (fr * live);
+            if (slot == 0) Yl[r][0] = hv[rr] * (fh * live);
+        }
+    };
+    for (int64_t base = (int64_t)blockIdx.x * CH; base <= N; base += (int64_t)G * CH) {
+        issue(base);
+        asm volatile("" ::: "memory");  // every load issued before the first store
+        stage(base);
+        __syncthreads();
+        const double fl = euler ? 0.0 : 1.0;  // weight of the left neighbour
+        // (2) gamma terms X_i X_p(i) yt_i of this lane's node
+#pragma unroll
+        for (int rr = 0; rr < HR; rr++) {
+            const int i = HR * h + rr;
+            if (i >= n) break;
+            const int p = (i + 1 == n) ? 0 : i + 1;
+            const double yt = __builtin_fma(fl, Yl[i][slot], Yl[i][slot + 1]);
+            gam[rr] = __builtin_fma(yt, Vl[i][slot] * Vl[p][slot], gam[rr]);
+        }
+        __syncthreads();
+        // (3) the sines, spread over all lanes
+#pragma unroll 1
+        for (int e = t; e < n * CH; e += kBlock) Vl[e / CH][e % CH] = sin(Vl[e / CH][e % CH]);
+        __syncthreads();
+        // (4) the contraction
+#pragma unroll 2
+        for (int st = 0; st < CH / (4 * W); st++) {
+            const int s = w * (CH / W) + 4 * st + kq;
+            double a[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; mb++)
+                a[mb] = __builtin_fma(fl, Yl[mb * 16 + j16][s], Yl[mb * 16 + j16][s + 1]);
+#pragma unroll
+            for (int cb = 0; cb < NBK; cb++) {
+                const double b = Vl[cb * 16 + j16][s];
+#pragma unroll
+                for (int mb = 0; mb < MB; mb++)
+                    acc[mb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], b, acc[mb][cb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D[i][j] of a block sits in lane 16 (i mod 4) + j, element i / 4
+    double(*red)[MB][NBK][256] = reinterpret_cast<double(*)[MB][NBK][256]>(sh);
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int cb = 0; cb < NBK; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) red[w][mb][cb][(4 * r + kq) * 16 + j16] = acc[mb][cb][r];
+#pragma unroll
+    for (int rr = 0; rr < HR; rr++) {
+        if (HR * h + rr >= n) break;
+        const double v = wave_sum(gam[rr]);
+        if (lane == 0) gs[w][rr] = v;
     }
     __syncthreads();
-    if (threadIdx.x < kCols) {
-        const int col = c0 + threadIdx.x;
-        if (col < ncol) {
-            double t = 0.0;
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; w++) t += ws[threadIdx.x][w];
-            cpart[((int64_t)i * ncol + col) * G + blockIdx.x] = t;
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int cb = 0; cb < NBK; cb++) {
+            const int i = mb * 16 + (t >> 4), col = cb * 16 + (t & 15);
+            if (i >= n || col >= n + m) continue;
+            double sum = red[0][mb][cb][t];
+#pragma unroll
+            for (int v = 1; v < W; v++) sum += red[v][mb][cb][t];
+            cpart[((int64_t)i * ncol + col) * G + blockIdx.x] = sum;
         }
+    if (t < n) {
+        const int hh = t / HR, rr = t - hh * HR;
+        cpart[((int64_t)t * ncol + n + m) * G + blockIdx.x] = gs[2 * hh][rr] + gs[2 * hh + 1][rr];
     }
 }
 
@@ -515,9 +636,22 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
     if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_grad: null array");
     const int n = p->d.n, m = p->d.m, ncol = n + m + 1;
-    const int G = (int)std::min<int64_t>(kCoefBlocks, blocks_for(p->d.N1, kBlock));
-    const dim3 grid(G, n, (ncol + kCols - 1) / kCols);
-    hipLaunchKernelGGL(coef_partial_kernel, grid, dim3(kBlock), 0, stream, p->kp, z, y, G, p->cpart);
+    const int G = coef_blocks(p->d.N1);
+    // 16-row blocks of yt (n <= 32) and 16-column blocks of [sin X | U] (n + m <= 64)
+    const int mb = (n + 15) / 16, nbk = (n + m + 15) / 16;
+#define OCP_COEF_LAUNCH(MB_, NBK_)                                                                      \
+    hipLaunchKernelGGL((coef_partial_kernel<MB_, NBK_>), dim3(G), dim3(kBlock), 0, stream, p->kp, z, y, \
+                       G, p->cpart)
+    if (mb == 1) {
+        if (nbk == 1) OCP_COEF_LAUNCH(1, 1);
+        else if (nbk == 2) OCP_COEF_LAUNCH(1, 2);
+        else OCP_COEF_LAUNCH(1, 3);
+    } else {
+        if (nbk == 2) OCP_COEF_LAUNCH(2, 2);
+        else if (nbk == 3) OCP_COEF_LAUNCH(2, 3);
+        else OCP_COEF_LAUNCH(2, 4);
+    }
+#undef OCP_COEF_LAUNCH
     if (int rc = check_launch("ocp_eval_coef_grad")) return rc;
     hipLaunchKernelGGL(coef_final_kernel, dim3(n * ncol), dim3(kBlock), 0, stream, p->kp, p->cpart, G,
                        gA, gB, ggamma);

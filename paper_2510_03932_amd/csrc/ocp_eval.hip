@@ -436,7 +436,7 @@ int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const
     if (e != hipSuccess) { delete p; return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e)); }
     e = hipMalloc(&p->partials, kObjBlocks * sizeof(double));
     if (e == hipSuccess)
-        e = hipMalloc(&p->cpart, (size_t)n * (n + m + 1) * kCoefBlocks * sizeof(double));
+        e = hipMalloc(&p->cpart, (size_t)n * (n + m + 1) * coef_blocks(d.N1) * sizeof(double));
     if (e != hipSuccess) {
         ocp_destroy(p);
         return fail(OCP_ERR_ALLOC, std::string("ocp_create: hipMalloc: ") + hipGetErrorString(e));

@@ -12,14 +12,23 @@
 // Most partial sums of the one-pass-per-workgroup reductions (objective,
 // Lagrangian value), and workgroups per row of the coefficient-gradient sum.
 constexpr int kObjBlocks = 4096;
-constexpr int kCoefBlocks = 256;
+constexpr int kCoefBlocks = 1024;
+
+// Nodes per chunk of the coefficient-gradient sum, and its workgroups over
+// N1 nodes: one per chunk, at most kCoefBlocks.
+constexpr int kCoefChunk = 128;
+inline int coef_blocks(int64_t N1)
+{
+    const int64_t chunks = (N1 + kCoefChunk - 1) / kCoefChunk;
+    return (int)(chunks < kCoefBlocks ? chunks : kCoefBlocks);
+}
 
 struct ocp_problem {
     ocp::Dims d;
     int device;
     double *coef;       // device: A | B | gamma | q | r | AT | BT (padded columns, kLd each)
     double *partials;   // device: kObjBlocks doubles (objective and Lagrangian sums)
-    double *cpart;      // device: n (n+m+1) kCoefBlocks doubles (coefficient-gradient sums)
+    double *cpart;      // device: n (n+m+1) coef_blocks(N1) doubles (coefficient-gradient sums)
     ocp::dev::KP kp;
     int model = 0;        // 0: the synthetic dynamics family; ocp::quad::kModel: the quadrotor
     double quad_g = 0.0;  // quadrotor gravity and control weight

@@ -119,6 +119,25 @@ def test_derivatives_other_schemes_workload(ocp):
     _check_all_ex(ocp, synth.make_instance(N, n, m, seed=0, scheme=1, bnd=2), 1.0, "Euler 2e5")
 
 
+@pytest.mark.parametrize("N,n,m,scheme", [(600_000, 5, 2, 0), (600_001, 3, 0, 1), (270_000, 17, 9, 0)])
+def test_coef_grad_many_chunks_per_workgroup(ocp, N, n, m, scheme):
+    """Sizes where each workgroup of the coefficient-gradient sum takes more
+    than one chunk of nodes (the grid holds at most 1024 of them), with a
+    ragged last chunk and, at n = 17, m = 9, two column tiles."""
+    _say(f"[coef grad] N={N} n={n} m={m} scheme={scheme}")
+    inst = synth.make_instance(N, n, m, seed=11, scheme=scheme)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    gA, gB, gg = (t.cpu().numpy() for t in prob.coef_grad(z, y))
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_grad_ex(inst, scheme, 0)
+    tag = f"{N},{n},{m},{scheme}"
+    check_close(gA.ravel(), oA.ravel(), mA.ravel(), what=f"dL/dA {tag}")
+    check_close(gB.ravel(), oB.ravel(), mB.ravel(), what=f"dL/dB {tag}")
+    check_close(gg, og, mg, what=f"dL/dgamma {tag}")
+    prob.close()
+
+
 def test_differentiation_workload_full_arrays(ocp):
     N, n, m = synth.DIFF
     _say(f"[diff] workload N={N} n={n} m={m}")
