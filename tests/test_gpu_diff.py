@@ -119,6 +119,31 @@ def test_derivatives_other_schemes_workload(ocp):
     _check_all_ex(ocp, synth.make_instance(N, n, m, seed=0, scheme=1, bnd=2), 1.0, "Euler 2e5")
 
 
+# (n, m) for each (row blocks, column blocks) tiling of the coefficient
+# gradient: ceil(n/16) x ceil((n+m)/16) = 1x1, 1x2, 1x3, 2x2, 2x3, 2x4
+COEF_TILINGS = [(7, 5), (16, 1), (12, 30), (17, 15), (24, 16), (32, 31)]
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("n,m", COEF_TILINGS)
+def test_coef_grad_every_tiling(ocp, n, m, scheme):
+    """Every tiling of the coefficient-gradient kernel, at N = 389 (three
+    128-node chunks and a ragged fourth)."""
+    N = 389
+    _say(f"[coef grad] N={N} n={n} m={m} scheme={scheme}")
+    inst = synth.make_instance(N, n, m, seed=13, scheme=scheme)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    gA, gB, gg = (t.cpu().numpy() for t in prob.coef_grad(z, y))
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_grad_ex(inst, scheme, 0)
+    tag = f"{N},{n},{m},{scheme}"
+    check_close(gA.ravel(), oA.ravel(), mA.ravel(), what=f"dL/dA {tag}")
+    check_close(gB.ravel(), oB.ravel(), mB.ravel(), what=f"dL/dB {tag}")
+    check_close(gg, og, mg, what=f"dL/dgamma {tag}")
+    prob.close()
+
+
 @pytest.mark.parametrize("N,n,m,scheme", [(600_000, 5, 2, 0), (600_001, 3, 0, 1), (270_000, 17, 9, 0)])
 def test_coef_grad_many_chunks_per_workgroup(ocp, N, n, m, scheme):
     """Sizes where each workgroup of the coefficient-gradient sum takes more
