@@ -341,9 +341,10 @@ __global__ __launch_bounds__(kBlock) void bnd_jvp_kernel(KP P, const double *__r
 // block of the product.  At the end the 4 waves' blocks are added in order in
 // LDS and the entries go to cpart[(i (n+m+1) + col) G + b], col n+m holding
 // the gamma sum.  MB = ceil(n / 16) row blocks, NBK = ceil((n+m) / 16)
-// column blocks.
+// column blocks.  The smallest tiling is held to 4 waves per SIMD (a few
+// registers spill), which measured faster than 3 without spills.
 template <int MB, int NBK>
-__global__ __launch_bounds__(kBlock, MB == 1 && NBK <= 2 ? 2 : 1) void coef_partial_kernel(
+__global__ __launch_bounds__(kBlock, MB == 1 && NBK == 1 ? 4 : MB == 1 && NBK == 2 ? 2 : 1) void coef_partial_kernel(
     KP P, const double *__restrict__ z, const double *__restrict__ y, int G, double *__restrict__ cpart)
 {
     constexpr int W = kBlock / 64, CH = kCoefChunk, LD = CH + 2;  // LD: row stride, spreads LDS banks
