@@ -42,8 +42,11 @@
  * Ownership: the caller owns every array.  Arrays passed to ocp_eval_* and
  * ocp_assemble_kkt are device pointers (HBM), contiguous; the index builders
  * fill host arrays.  The problem handle owns device copies of the dynamics and
- * cost coefficients and a small device workspace for the objective reduction;
- * the library never hands out memory for the caller to free.
+ * cost coefficients and two device workspaces, both fixed at create time: the
+ * per-workgroup partial sums of the objective and Lagrangian (at most 4096
+ * doubles) and of the coefficient gradient (n (n+m+1) G doubles, G =
+ * min(1024, ceil((N+1) / 128)) workgroups); the library never hands out
+ * memory for the caller to free.
  *
  * Streams: every device call is asynchronous on the given HIP stream (0 = the
  * null stream) and never synchronizes; the objective lands in a device double.
