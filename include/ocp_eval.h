@@ -45,7 +45,7 @@
  * cost coefficients and two device workspaces, both fixed at create time: the
  * per-workgroup partial sums of the objective and Lagrangian (at most 4096
  * doubles) and of the coefficient gradient (n (n+m+1) G doubles, G =
- * min(1024, ceil((N+1) / 128)) workgroups); the library never hands out
+ * min(1024, ceil((N+1) / 64)) workgroups); the library never hands out
  * memory for the caller to free.
  *
  * Streams: every device call is asynchronous on the given HIP stream (0 = the

@@ -332,26 +332,27 @@ __global__ __launch_bounds__(kBlock) void bnd_jvp_kernel(KP P, const double *__r
 //
 // Workgroup b takes the chunks of kCoefChunk nodes b, b + G, ...  Per chunk:
 // (1) the lanes stage y and the raw columns [X | U] at the chunk's nodes in
-// LDS, one node per lane and half of the columns and rows per half
-// workgroup, with coalesced loads; (2) each lane adds the gamma terms of its
-// node for the rows of its half; (3) the sines are taken in place, once per
+// LDS: the workgroup is split into kBlock / kCoefChunk parts of one node
+// per lane, each part staging its share of the columns and rows with
+// coalesced loads; (2) each lane adds the gamma terms of its node for the
+// rows of its part; (3) the sines are taken in place, once per
 // entry, spread over all lanes; (4) wave w feeds its kCoefChunk / 4 nodes to
 // v_mfma_f64_16x16x4f64, 4 nodes per instruction (lane l supplies row or
 // column l mod 16 at node l / 16 of the step), accumulating every 16 x 16
 // block of the product.  At the end the 4 waves' blocks are added in order in
 // LDS and the entries go to cpart[(i (n+m+1) + col) G + b], col n+m holding
 // the gamma sum.  MB = ceil(n / 16) row blocks, NBK = ceil((n+m) / 16)
-// column blocks.  The smallest tiling is held to 4 waves per SIMD (a few
-// registers spill), which measured faster than 3 without spills.
+// column blocks.
 template <int MB, int NBK>
-__global__ __launch_bounds__(kBlock, MB == 1 && NBK == 1 ? 4 : MB == 1 && NBK == 2 ? 2 : 1) void coef_partial_kernel(
+__global__ __launch_bounds__(kBlock) void coef_partial_kernel(
     KP P, const double *__restrict__ z, const double *__restrict__ y, int G, double *__restrict__ cpart)
 {
     constexpr int W = kBlock / 64, CH = kCoefChunk, LD = CH + 2;  // LD: row stride, spreads LDS banks
-    constexpr int HR = 8 * MB, HC = 8 * NBK;                     // rows and columns per half workgroup
-    static_assert(kBlock == 2 * CH, "two lanes per node in the staging pass");
-    static_assert(W * MB * NBK * 256 <= (16 * NBK + 16 * MB) * LD, "block sums fit the staging area");
-    __shared__ double sh[(16 * NBK + 16 * MB) * LD];
+    constexpr int Q = kBlock / CH;                               // staging parts (lanes per node)
+    constexpr int HR = 16 * MB / Q, HC = 16 * NBK / Q;           // rows and columns per part
+    static_assert(kBlock % CH == 0 && CH % 64 == 0 && (16 % Q) == 0, "whole waves per staging part");
+    constexpr int STAGE = (16 * NBK + 16 * MB) * LD, RED = W * MB * NBK * 256;
+    __shared__ double sh[STAGE > RED ? STAGE : RED];  // staging area, then the block sums
     __shared__ double gs[W][HR];
     double(*Vl)[LD] = reinterpret_cast<double(*)[LD]>(sh);
     double(*Yl)[LD] = reinterpret_cast<double(*)[LD]>(sh + 16 * NBK * LD);
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(kBlock, MB == 1 && NBK == 1 ? 4 : MB == 1 && NBK ==
     // keep what derives from them (row and column pointers) in scalar
     // registers
     const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int slot = t & (CH - 1), h = __builtin_amdgcn_readfirstlane(t >> 7);  // staging: node slot, half
+    const int slot = t % CH, h = __builtin_amdgcn_readfirstlane(t / CH);  // staging: node slot, part
     const int j16 = lane & 15, kq = lane >> 4;
     const int64_t N = P.N, N1 = P.N1, NU = P.NU;
     const bool euler = P.scheme != 0;
@@ -490,8 +491,12 @@ __global__ __launch_bounds__(kBlock, MB == 1 && NBK == 1 ? 4 : MB == 1 && NBK ==
             cpart[((int64_t)i * ncol + col) * G + blockIdx.x] = sum;
         }
     if (t < n) {
+        constexpr int WP = W / Q;  // waves per staging part
         const int hh = t / HR, rr = t - hh * HR;
-        cpart[((int64_t)t * ncol + n + m) * G + blockIdx.x] = gs[2 * hh][rr] + gs[2 * hh + 1][rr];
+        double sum = gs[WP * hh][rr];
+#pragma unroll
+        for (int v = 1; v < WP; v++) sum += gs[WP * hh + v][rr];
+        cpart[((int64_t)t * ncol + n + m) * G + blockIdx.x] = sum;
     }
 }
 

@@ -16,7 +16,7 @@ constexpr int kCoefBlocks = 1024;
 
 // Nodes per chunk of the coefficient-gradient sum, and its workgroups over
 // N1 nodes: one per chunk, at most kCoefBlocks.
-constexpr int kCoefChunk = 128;
+constexpr int kCoefChunk = 64;
 inline int coef_blocks(int64_t N1)
 {
     const int64_t chunks = (N1 + kCoefChunk - 1) / kCoefChunk;

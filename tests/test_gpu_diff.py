@@ -127,8 +127,8 @@ COEF_TILINGS = [(7, 5), (16, 1), (12, 30), (17, 15), (24, 16), (32, 31)]
 @pytest.mark.parametrize("scheme", [0, 1])
 @pytest.mark.parametrize("n,m", COEF_TILINGS)
 def test_coef_grad_every_tiling(ocp, n, m, scheme):
-    """Every tiling of the coefficient-gradient kernel, at N = 389 (three
-    128-node chunks and a ragged fourth)."""
+    """Every tiling of the coefficient-gradient kernel, at N = 389 (390
+    nodes: several chunks and a ragged last one)."""
     N = 389
     _say(f"[coef grad] N={N} n={n} m={m} scheme={scheme}")
     inst = synth.make_instance(N, n, m, seed=13, scheme=scheme)
