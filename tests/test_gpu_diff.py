@@ -148,13 +148,17 @@ def test_coef_grad_every_tiling(ocp, n, m, scheme):
 def test_coef_grad_many_chunks_per_workgroup(ocp, N, n, m, scheme):
     """Sizes where each workgroup of the coefficient-gradient sum takes more
     than one chunk of nodes (the grid holds at most 1024 of them), with a
-    ragged last chunk and, at n = 17, m = 9, two column tiles."""
+    ragged last chunk and, at n = 17, m = 9, two row and two column blocks.
+    A second call must give the same bits (fixed summation order)."""
     _say(f"[coef grad] N={N} n={n} m={m} scheme={scheme}")
     inst = synth.make_instance(N, n, m, seed=11, scheme=scheme)
     dev = torch.device("cuda", 0)
     prob = ocp.Problem.from_instance(inst, dev)
     z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
     gA, gB, gg = (t.cpu().numpy() for t in prob.coef_grad(z, y))
+    again = [t.cpu().numpy() for t in prob.coef_grad(z, y)]
+    for first, second in zip((gA, gB, gg), again):
+        assert np.array_equal(first.view(np.int64), second.view(np.int64))
     (oA, oB, og), (mA, mB, mg) = oracle.coef_grad_ex(inst, scheme, 0)
     tag = f"{N},{n},{m},{scheme}"
     check_close(gA.ravel(), oA.ravel(), mA.ravel(), what=f"dL/dA {tag}")
