@@ -334,6 +334,26 @@ int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double 
 int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA,
                        double *gB, double *ggamma, hipStream_t stream);
 
+/* Allocation-free ocp_eval_coef_grad, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same kernels, same arguments and bitwise the same
+ * results as ocp_eval_coef_grad, but the per-workgroup partial sums live in a
+ * fixed device array of the library (OCP_NOALLOC_SCRATCH doubles = 4 MiB;
+ * each device holds its own copy until the process ends) instead of the
+ * handle's workspace.  The call allocates nothing and calls no allocating
+ * routine.  Limit: n (n+m+1) G <= OCP_NOALLOC_SCRATCH, G = min(1024,
+ * ceil((N+1) / 64)) workgroups (every N at n <= 16, m <= 8); a larger
+ * problem returns OCP_ERR_ARG before any HIP call.  The current device must
+ * be the handle's (OCP_ERR_ARG otherwise).  Every call on one device shares
+ * that device's array, which keeps the last call's contents: calls that
+ * overlap on one device race (serialize them, e.g. on one stream).  Each call
+ * writes every partial it reads before reading it, so nothing needs clearing.
+ * The array's device address is looked up when a handle is created on the
+ * device (OCP_ERR_HIP if that lookup failed). */
+#define OCP_NOALLOC_SCRATCH 524288
+int ocp_eval_coef_grad_noalloc(const ocp_problem *p, const double *z, const double *y, double *gA,
+                               double *gB, double *ggamma, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * The quadrotor model of the paper's benchmark set (Appendix A), transcribed
  * with the trapezoidal scheme (Sec. 5) on t in [0, 1], h = 1/N.

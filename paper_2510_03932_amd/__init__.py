@@ -119,6 +119,7 @@ def lib():
         L.ocp_eval_hvp.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.ocp_eval_jvp.argtypes = [vp, vp, vp, vp, vp]
         L.ocp_eval_coef_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_eval_coef_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ocp_batch_create.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.ocp_batch_destroy.argtypes = [vp]
         L.ocp_batch_destroy.restype = None
@@ -484,18 +485,21 @@ class Problem:
         _check(lib().ocp_eval_jvp(self._h, zp, vp, op, self._stream()), "ocp_eval_jvp")
         return out
 
-    def coef_grad(self, z, y):
-        """(dL/dA (n, n), dL/dB (n, m), dL/dgamma (n,)) as device tensors."""
+    def coef_grad(self, z, y, noalloc=False):
+        """(dL/dA (n, n), dL/dB (n, m), dL/dgamma (n,)) as device tensors.
+        noalloc=True calls the allocation-free entry point (its partial sums
+        in the library's fixed scratch array instead of the handle's
+        workspace; bitwise the same result)."""
         torch = _torch()
         n, m = self.n, self.m
         zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
         yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
         f64 = dict(dtype=torch.float64, device=self.device)
         gA, gB, gg = torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64)
-        _check(lib().ocp_eval_coef_grad(self._h, zp, yp, ctypes.c_void_p(gA.data_ptr()),
-                                        ctypes.c_void_p(gB.data_ptr()) if m else None,
-                                        ctypes.c_void_p(gg.data_ptr()), self._stream()),
-               "ocp_eval_coef_grad")
+        fn = "ocp_eval_coef_grad_noalloc" if noalloc else "ocp_eval_coef_grad"
+        _check(getattr(lib(), fn)(self._h, zp, yp, ctypes.c_void_p(gA.data_ptr()),
+                                  ctypes.c_void_p(gB.data_ptr()) if m else None,
+                                  ctypes.c_void_p(gg.data_ptr()), self._stream()), fn)
         return gA, gB, gg
 
 

@@ -31,7 +31,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "ocp_device.h"
 #include "ocp_internal.h"
@@ -539,6 +541,42 @@ __global__ __launch_bounds__(kBlock) void pack_columns_kernel(int n, int m, cons
 
 }  // namespace
 
+// The allocation-free coefficient gradient keeps its per-workgroup partial
+// sums in this array instead of the handle's workspace.  Each device holds
+// its own copy (for the life of the process); host code never passes the
+// array's name to a kernel, only the device address that
+// hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) double scratch[OCP_NOALLOC_SCRATCH];
+
+namespace {
+std::mutex scratch_mu;
+std::vector<double *> scratch_addr;  // by device ordinal; null until looked up
+}  // namespace
+
+double *noalloc_scratch(int device)
+{
+    if (device < 0) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if ((size_t)device >= scratch_addr.size()) scratch_addr.resize((size_t)device + 1, nullptr);
+    if (!scratch_addr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        void *addr = nullptr;
+        if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) {
+            (void)hipGetLastError();  // leave no sticky error for the next launch check
+            return nullptr;
+        }
+        scratch_addr[device] = static_cast<double *>(addr);
+    }
+    return scratch_addr[device];
+}
+
+static int launch_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA, double *gB,
+                            double *ggamma, double *cpart, hipStream_t stream, const char *fn);
+
 #define OCP_DISPATCH_NB(n, KERNEL, grid, ...)                                                   \
     do {                                                                                        \
         switch (nb_of(n)) {                                                                     \
@@ -641,13 +679,44 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
     if (int rc = check_coefficients(p, "ocp_eval_coef_grad")) return rc;
     if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_grad: null array");
+    return launch_coef_grad(p, z, y, gA, gB, ggamma, p->cpart, stream, "ocp_eval_coef_grad");
+}
+
+int ocp_eval_coef_grad_noalloc(const ocp_problem *p, const double *z, const double *y, double *gA,
+                               double *gB, double *ggamma, hipStream_t stream)
+{
+    const char *fn = "ocp_eval_coef_grad_noalloc";
+    clear_error();
+    if (int rc = check_handle(p, fn)) return rc;
+    if (int rc = check_coefficients(p, fn)) return rc;
+    if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB)) return fail(OCP_ERR_ARG, std::string(fn) + ": null array");
+    const int64_t need = (int64_t)p->d.n * (p->d.n + p->d.m + 1) * coef_blocks(p->d.N1);
+    if (need > OCP_NOALLOC_SCRATCH)
+        return fail(OCP_ERR_ARG, std::string(fn) + ": the partial sums need " + std::to_string(need) +
+                                     " doubles, more than the " + std::to_string(OCP_NOALLOC_SCRATCH) +
+                                     " of the fixed scratch array");
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("ocp_eval_coef_grad_noalloc: hipGetDevice", e);
+    if (dev != p->device)
+        return fail(OCP_ERR_ARG, std::string(fn) + ": the current device is not the handle's");
+    double *ws = noalloc_scratch(dev);
+    if (!ws) return fail(OCP_ERR_HIP, std::string(fn) + ": the scratch array's device address is unknown");
+    return launch_coef_grad(p, z, y, gA, gB, ggamma, ws, stream, fn);
+}
+
+}  // extern "C"
+
+static int launch_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA, double *gB,
+                            double *ggamma, double *cpart, hipStream_t stream, const char *fn)
+{
     const int n = p->d.n, m = p->d.m, ncol = n + m + 1;
     const int G = coef_blocks(p->d.N1);
     // 16-row blocks of yt (n <= 32) and 16-column blocks of [sin X | U] (n + m <= 64)
     const int mb = (n + 15) / 16, nbk = (n + m + 15) / 16;
 #define OCP_COEF_LAUNCH(MB_, NBK_)                                                                      \
     hipLaunchKernelGGL((coef_partial_kernel<MB_, NBK_>), dim3(G), dim3(kBlock), 0, stream, p->kp, z, y, \
-                       G, p->cpart)
+                       G, cpart)
     if (mb == 1) {
         if (nbk == 1) OCP_COEF_LAUNCH(1, 1);
         else if (nbk == 2) OCP_COEF_LAUNCH(1, 2);
@@ -658,10 +727,8 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
         else OCP_COEF_LAUNCH(2, 4);
     }
 #undef OCP_COEF_LAUNCH
-    if (int rc = check_launch("ocp_eval_coef_grad")) return rc;
-    hipLaunchKernelGGL(coef_final_kernel, dim3(n * ncol), dim3(kBlock), 0, stream, p->kp, p->cpart, G,
+    if (int rc = check_launch(fn)) return rc;
+    hipLaunchKernelGGL(coef_final_kernel, dim3(n * ncol), dim3(kBlock), 0, stream, p->kp, cpart, G,
                        gA, gB, ggamma);
-    return check_launch("ocp_eval_coef_grad");
+    return check_launch(fn);
 }
-
-}  // extern "C"

@@ -429,6 +429,9 @@ int ocp_create_ex(int64_t N, int32_t n, int32_t m, const ocp_options *opt, const
     p->d = d;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { delete p; return hip_fail("ocp_create: hipGetDevice", e); }
+    // locate this device's scratch array of the allocation-free entry point
+    // now, outside any stream capture (a failure only disables that entry)
+    (void)noalloc_scratch(p->device);
     static_assert(kLd == OCP_MAX_DIM, "padded coefficient columns hold up to OCP_MAX_DIM rows");
     const size_t nplain = (size_t)n * n + (size_t)n * m + 3 * (size_t)n + (size_t)m;
     const size_t ncoef = nplain + (size_t)(n + m) * kLd;

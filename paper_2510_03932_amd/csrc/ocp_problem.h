@@ -23,6 +23,11 @@ inline int coef_blocks(int64_t N1)
     return (int)(chunks < kCoefBlocks ? chunks : kCoefBlocks);
 }
 
+// Device address of the allocation-free entry point's fixed scratch array on
+// `device` (which must be the current device on the first call for it), looked
+// up once per device and kept; null if the lookup fails.
+double *noalloc_scratch(int device);
+
 struct ocp_problem {
     ocp::Dims d;
     int device;
