@@ -420,18 +420,28 @@ int ocp_quad_create(int64_t N, int32_t boundary, double g, double r, ocp_problem
  * across grid nodes (Sec. 3) and real-time use; a batch extends the same
  * node-parallel evaluation across instances.
  *
- * Packed layout: instance b's z, y/c, Jacobian and Hessian values are the
- * single-instance arrays of that instance (same layouts as above, with its
- * own N_b), stored back to back in instance order.  ocp_batch_offsets gives
- * the int64 start of each instance in each packed array.
+ * Packed layout: instance b's z, y/c, gradient, Jacobian, Hessian and KKT
+ * values and its regularization are the single-instance arrays of that
+ * instance (same layouts as above, with its own N_b, under the batch's
+ * scheme and boundary option), stored back to back in instance order;
+ * objectives are one double per instance.  ocp_batch_offsets and
+ * ocp_batch_offsets_ex give the int64 start of each instance in each packed
+ * array.  An interior-point step over the batch (Sec. 6: derivative
+ * evaluations and the KKT assembly, every iteration, on the device) is one
+ * ocp_batch_eval_io call.
  * ------------------------------------------------------------------------- */
 
 typedef struct ocp_batch ocp_batch;
 typedef struct ocp_graph ocp_graph;
 
 /* What a batched evaluation computes (bit mask). */
-#define OCP_EVAL_JAC 1
-#define OCP_EVAL_HESS 2
+#define OCP_EVAL_JAC 1    /* Jacobian values (COO order of each instance) */
+#define OCP_EVAL_HESS 2   /* Hessian-of-Lagrangian values (COO order) */
+#define OCP_EVAL_OBJ 4    /* objective of each instance */
+#define OCP_EVAL_GRAD 8   /* objective gradient */
+#define OCP_EVAL_CONS 16  /* defects and boundary rows */
+#define OCP_EVAL_KKT 32   /* fused KKT values (ocp_eval_kkt of each instance) */
+#define OCP_EVAL_ALL 63
 
 /* How a batched evaluation runs. */
 #define OCP_BATCH_PERSISTENT 0    /* one persistent launch over a static tile list */
@@ -461,6 +471,13 @@ int ocp_batch_create(int32_t count, const int64_t *Ns, int32_t n, int32_t m, con
                      const double *B, const double *gamma, const double *q, const double *r,
                      ocp_batch **out);
 
+/* ocp_batch_create with options: every instance uses opt's scheme and
+ * boundary option (NULL: the defaults), as ocp_create_ex does for one
+ * instance. */
+int ocp_batch_create_ex(int32_t count, const int64_t *Ns, int32_t n, int32_t m, const ocp_options *opt,
+                        const double *A, const double *B, const double *gamma, const double *q,
+                        const double *r, ocp_batch **out);
+
 /* Release a batch.  NULL-safe.  No work using it may be in flight. */
 void ocp_batch_destroy(ocp_batch *b);
 
@@ -469,6 +486,11 @@ void ocp_batch_destroy(ocp_batch *b);
  * Entry `count` holds the total length of the packed array. */
 int ocp_batch_offsets(const ocp_batch *b, int64_t *z_off, int64_t *c_off, int64_t *jac_off,
                       int64_t *hess_off);
+
+/* Packed offsets of the KKT values (kkt_off, nnzk_b per instance) and of the
+ * regularization (dim_off, dim_b), count+1 host int64 entries each (either
+ * may be NULL); entry `count` is the total. */
+int ocp_batch_offsets_ex(const ocp_batch *b, int64_t *kkt_off, int64_t *dim_off);
 
 /* Current tile shape, and setting a new one.  Setting rebuilds the tile list
  * and synchronizes the device first (no evaluation with the batch may be in
@@ -486,6 +508,47 @@ int ocp_batch_set_config(ocp_batch *b, const ocp_batch_config *cfg);
 int ocp_batch_eval(const ocp_batch *b, int32_t what, int32_t mode, const double *z,
                    const double *y, double sigma, double *jac, double *hess, hipStream_t stream);
 
+/* Arrays of one batched evaluation (all device pointers into packed arrays;
+ * an output not requested by `what` may be NULL and is not touched). */
+typedef struct ocp_batch_io {
+    const double *z;    /* packed z (always read) */
+    const double *y;    /* packed multipliers (OCP_EVAL_HESS, OCP_EVAL_KKT) */
+    const double *reg;  /* packed KKT regularization, dim_b per instance (OCP_EVAL_KKT; NULL: none) */
+    double sigma;       /* objective weight of the Lagrangian (OCP_EVAL_HESS, OCP_EVAL_KKT) */
+    double *obj;        /* count doubles: instance b's objective at obj[b] (OCP_EVAL_OBJ) */
+    double *grad;       /* packed, nvar_b per instance, offsets z_off (OCP_EVAL_GRAD) */
+    double *cons;       /* packed, ncon_b, offsets c_off (OCP_EVAL_CONS) */
+    double *jac;        /* packed, nnzj_b, offsets jac_off (OCP_EVAL_JAC) */
+    double *hess;       /* packed, nnzh_b, offsets hess_off (OCP_EVAL_HESS) */
+    double *kkt;        /* packed, nnzk_b, offsets kkt_off: each instance's lower CSR KKT values in
+                           the layout of ocp_build_kkt_ex, as ocp_eval_kkt writes them (OCP_EVAL_KKT) */
+} ocp_batch_io;
+
+/* Evaluate the requested parts (`what`, any non-empty mask of OCP_EVAL_*) of
+ * every instance: in persistent mode one launch walks the tile list of that
+ * mask; in per-instance mode the single-instance kernels run instance after
+ * instance.  Both give bitwise the same values, independent of the tile
+ * shape; the objective is bitwise the per-instance (ocp_eval_obj) value for
+ * N_b < 2^20 (beyond that the single-instance reduction takes several nodes
+ * per lane and the two agree to rounding).  The values are those of the
+ * single-instance entry points (Sec. 5 formulas; the KKT values those of
+ * ocp_eval_kkt with the instance's part of reg).  The first evaluation with a
+ * mask builds that mask's tile list (a device allocation and a copy; see
+ * ocp_batch_prepare).  Objective evaluations on one batch share its per-
+ * instance partial sums and counters: evaluations with OCP_EVAL_OBJ must not
+ * overlap (serialize them, e.g. on one stream).  Asynchronous on `stream`.
+ * Errors: OCP_ERR_ARG (NULL batch or io, empty or unknown mask, a requested
+ * array NULL, sigma not finite when used), OCP_ERR_ALLOC, OCP_ERR_HIP. */
+int ocp_batch_eval_io(const ocp_batch *b, int32_t what, int32_t mode, const ocp_batch_io *io,
+                      hipStream_t stream);
+
+/* Build and keep the persistent tile list of mask `what` for the current
+ * tile shape now (a device allocation and a host-to-device copy), so that a
+ * later evaluation or capture with that mask allocates nothing.  Lists are
+ * rebuilt when the shape changes.  Not thread-safe with a concurrent
+ * ocp_batch_set_config on the same batch. */
+int ocp_batch_prepare(const ocp_batch *b, int32_t what);
+
 /* Capture one ocp_batch_eval (same arguments, pointers bound at capture) into
  * a HIP graph on a private stream and instantiate it.  The graph owns a copy of
  * the tile list, so later configuration changes do not affect it.  It still
@@ -496,6 +559,11 @@ int ocp_batch_eval(const ocp_batch *b, int32_t what, int32_t mode, const double 
 int ocp_batch_graph_create(const ocp_batch *b, int32_t what, int32_t mode, const double *z,
                            const double *y, double sigma, double *jac, double *hess,
                            ocp_graph **out);
+
+/* Capture one ocp_batch_eval_io (same arguments; the arrays of io are bound
+ * at capture) into a HIP graph, as ocp_batch_graph_create does. */
+int ocp_batch_graph_create_io(const ocp_batch *b, int32_t what, int32_t mode, const ocp_batch_io *io,
+                              ocp_graph **out);
 
 /* Replay a captured evaluation on `stream` (asynchronous).  The arrays bound
  * at capture must still be alive. */
@@ -516,6 +584,11 @@ void ocp_graph_destroy(ocp_graph *g);
 int ocp_batch_autotune(ocp_batch *b, int32_t what, const double *z, const double *y, double sigma,
                        double *jac, double *hess, int32_t reps, hipStream_t stream,
                        ocp_batch_config *best, float *best_ms, float *all_ms);
+
+/* The autotuner over a whole-step mask: as ocp_batch_autotune, timing
+ * ocp_batch_eval_io(b, what, OCP_BATCH_PERSISTENT, io). */
+int ocp_batch_autotune_io(ocp_batch *b, int32_t what, const ocp_batch_io *io, int32_t reps,
+                          hipStream_t stream, ocp_batch_config *best, float *best_ms, float *all_ms);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char *ocp_last_error(void);

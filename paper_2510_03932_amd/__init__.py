@@ -66,7 +66,18 @@ class BatchConfig(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-EVAL_JAC, EVAL_HESS = 1, 2
+EVAL_JAC, EVAL_HESS, EVAL_OBJ, EVAL_GRAD, EVAL_CONS, EVAL_KKT = 1, 2, 4, 8, 16, 32
+EVAL_ALL = 63
+
+
+class BatchIO(ctypes.Structure):
+    """ocp_batch_io: the device arrays of one batched evaluation."""
+    _fields_ = [("z", ctypes.c_void_p), ("y", ctypes.c_void_p), ("reg", ctypes.c_void_p),
+                ("sigma", ctypes.c_double), ("obj", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("cons", ctypes.c_void_p), ("jac", ctypes.c_void_p), ("hess", ctypes.c_void_p),
+                ("kkt", ctypes.c_void_p)]
+
+
 AUTOTUNE_SHAPES = [{"block": b, "pair": p, "wgs_per_cu": w, "order": o}
                    for b in (128, 256) for p in (0, 1) for w in (1, 2, 4, 8, 16, 32, 0) for o in (0, 1)]
 MODES = {"persistent": 0, "per_instance": 1}
@@ -134,6 +145,14 @@ def lib():
         L.ocp_batch_autotune.argtypes = [vp, i32, vp, vp, dbl, vp, vp, i32, vp,
                                          ctypes.POINTER(BatchConfig), ctypes.POINTER(ctypes.c_float),
                                          vp]
+        L.ocp_batch_create_ex.argtypes = [i32, vp, i32, i32, ctypes.POINTER(Options), vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(vp)]
+        L.ocp_batch_offsets_ex.argtypes = [vp, vp, vp]
+        L.ocp_batch_prepare.argtypes = [vp, i32]
+        L.ocp_batch_eval_io.argtypes = [vp, i32, i32, ctypes.POINTER(BatchIO), vp]
+        L.ocp_batch_graph_create_io.argtypes = [vp, i32, i32, ctypes.POINTER(BatchIO), ctypes.POINTER(vp)]
+        L.ocp_batch_autotune_io.argtypes = [vp, i32, ctypes.POINTER(BatchIO), i32, vp,
+                                            ctypes.POINTER(BatchConfig), ctypes.POINTER(ctypes.c_float), vp]
         missing = [name for name in exported_names() if not hasattr(L, name)]
         if missing:
             raise OcpError(OCP_ERR_HIP, f"{LIB_PATH} lacks {missing}: rebuild it")
@@ -568,12 +587,13 @@ class Batch:
     evaluated together.  Packed arrays hold each instance's single-instance
     array back to back; ``offsets`` gives the starts."""
 
-    def __init__(self, Ns, n, m, A, B, gamma, q, r, device=None):
+    def __init__(self, Ns, n, m, A, B, gamma, q, r, device=None, scheme=0, boundary=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise OcpError(OCP_ERR_HIP, "no GPU visible: this library runs only on gfx950 devices")
         Ns = np.ascontiguousarray(np.asarray(Ns, np.int64))
         self.count, self.n, self.m = int(len(Ns)), int(n), int(m)
+        self.options = _opts(scheme, boundary)
         self.Ns = Ns
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
@@ -585,21 +605,23 @@ class Batch:
         r = f64(r, (c, m)) if m else np.zeros((c, 0))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib().ocp_batch_create(c, _hp(Ns), self.n, self.m, _hp(A), _hp(B) if m else None,
-                                          _hp(gamma), _hp(q), _hp(r) if m else None,
-                                          ctypes.byref(h)), "ocp_batch_create")
+            _check(lib().ocp_batch_create_ex(c, _hp(Ns), self.n, self.m, ctypes.byref(self.options), _hp(A),
+                                             _hp(B) if m else None, _hp(gamma), _hp(q),
+                                             _hp(r) if m else None, ctypes.byref(h)), "ocp_batch_create")
         self._h = h
-        offs = [np.zeros(c + 1, np.int64) for _ in range(4)]
-        _check(lib().ocp_batch_offsets(self._h, *(_hp(o) for o in offs)), "ocp_batch_offsets")
-        self.offsets = dict(zip(("z", "c", "jac", "hess"), offs))
+        offs = [np.zeros(c + 1, np.int64) for _ in range(6)]
+        _check(lib().ocp_batch_offsets(self._h, *(_hp(o) for o in offs[:4])), "ocp_batch_offsets")
+        _check(lib().ocp_batch_offsets_ex(self._h, _hp(offs[4]), _hp(offs[5])), "ocp_batch_offsets_ex")
+        self.offsets = dict(zip(("z", "c", "jac", "hess", "kkt", "dim"), offs))
         self.tuning = None  # the autotuner's table of (shape, ms), once tuned
 
     @classmethod
-    def from_instances(cls, insts, device=None):
+    def from_instances(cls, insts, device=None, scheme=0, boundary=0):
         n, m = insts[0].n, insts[0].m
         return cls([i.N for i in insts], n, m, np.stack([i.A for i in insts]),
                    np.stack([i.B for i in insts]), np.stack([i.gamma for i in insts]),
-                   np.stack([i.q for i in insts]), np.stack([i.r for i in insts]), device)
+                   np.stack([i.q for i in insts]), np.stack([i.r for i in insts]), device,
+                   scheme=scheme, boundary=boundary)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -658,6 +680,80 @@ class Batch:
                                                 hp, ctypes.byref(g)), "ocp_batch_graph_create")
         # the graph also reads this batch's coefficients and offset table
         return Graph(g, self.device, (z, y, jac, hess), owner=self), jac, hess
+
+    # -- whole interior-point step ---------------------------------------------
+    _STEP_OUT = (("obj", EVAL_OBJ, None), ("grad", EVAL_GRAD, "z"), ("cons", EVAL_CONS, "c"),
+                 ("jac", EVAL_JAC, "jac"), ("hess", EVAL_HESS, "hess"), ("kkt", EVAL_KKT, "kkt"))
+
+    def _io(self, z, y, sigma, reg, what, out):
+        """The BatchIO of one step and the output tensors (allocated where
+        `out` lacks them; None for parts not requested)."""
+        torch = _torch()
+        tot = {k: int(v[-1]) for k, v in self.offsets.items()}
+        chk = self._dev
+        io = BatchIO()
+        io.z = chk(z, tot["z"], torch.float64, "z")
+        if what & (EVAL_HESS | EVAL_KKT) or y is not None:
+            io.y = chk(y, tot["c"], torch.float64, "y") if y is not None else None
+        if reg is not None:
+            io.reg = chk(reg, tot["dim"], torch.float64, "reg")
+        io.sigma = float(sigma)
+        out = dict(out or {})
+        res = {}
+        for name, bit, key in self._STEP_OUT:
+            if not what & bit:
+                res[name] = None
+                continue
+            size = self.count if key is None else tot[key]
+            t = out.get(name)
+            if t is None:
+                t = torch.empty(size, dtype=torch.float64, device=self.device)
+            setattr(io, name, chk(t, size, torch.float64, name))
+            res[name] = t
+        return io, res
+
+    def step(self, z, y=None, sigma=1.0, reg=None, what=EVAL_ALL, mode="persistent", out=None):
+        """Evaluate the parts of an interior-point step that `what` selects
+        (EVAL_OBJ, EVAL_GRAD, EVAL_CONS, EVAL_JAC, EVAL_HESS, EVAL_KKT) for
+        every instance; returns {"obj", "grad", "cons", "jac", "hess", "kkt"}
+        (packed device tensors, None where not requested)."""
+        io, res = self._io(z, y, sigma, reg, what, out)
+        stream = ctypes.c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
+        _check(lib().ocp_batch_eval_io(self._h, int(what), MODES[mode], ctypes.byref(io), stream),
+               "ocp_batch_eval_io")
+        return res
+
+    def prepare(self, what=EVAL_ALL):
+        """Build the persistent tile lists of `what` now (so that a later
+        evaluation or capture allocates nothing)."""
+        _check(lib().ocp_batch_prepare(self._h, int(what)), "ocp_batch_prepare")
+
+    def step_graph(self, z, y=None, sigma=1.0, reg=None, what=EVAL_ALL, mode="persistent", out=None):
+        """Capture one step into a HIP graph: returns the Graph (its outputs
+        are the tensors of `out`, allocated where missing, in graph.outputs)."""
+        io, res = self._io(z, y, sigma, reg, what, out)
+        g = ctypes.c_void_p()
+        with _torch().cuda.device(self.device):
+            _check(lib().ocp_batch_graph_create_io(self._h, int(what), MODES[mode], ctypes.byref(io),
+                                                   ctypes.byref(g)), "ocp_batch_graph_create_io")
+        graph = Graph(g, self.device, (z, y, reg, *res.values()), owner=self)
+        graph.outputs = res
+        return graph
+
+    def autotune_step(self, z, y=None, sigma=1.0, reg=None, what=EVAL_ALL, reps=5, out=None):
+        """Time every tile shape on the step `what` and keep the fastest:
+        returns (config, ms per step, table)."""
+        torch = _torch()
+        io, res = self._io(z, y, sigma, reg, what, out)
+        best = BatchConfig()
+        ms = ctypes.c_float()
+        table = np.zeros(len(AUTOTUNE_SHAPES), np.float32)
+        stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(lib().ocp_batch_autotune_io(self._h, int(what), ctypes.byref(io), int(reps), stream,
+                                           ctypes.byref(best), ctypes.byref(ms), _hp(table)),
+               "ocp_batch_autotune_io")
+        tab = [dict(shape, ms=float(t)) for shape, t in zip(AUTOTUNE_SHAPES, table)]
+        return best.as_dict(), float(ms.value), tab
 
     def autotune(self, z, y=None, sigma=1.0, jac=None, hess=None, what=EVAL_JAC | EVAL_HESS,
                  reps=5, cache: str | None = None, use_cache=True):

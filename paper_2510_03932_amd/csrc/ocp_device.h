@@ -272,7 +272,7 @@ __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__
     for (int i = 0; i < NB; i++) {
         if (i < n) {
             const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
-            F[i] += P.gam[i] * x[i] * xp;
+            F[i] = __builtin_fma(P.gam[i] * x[i], xp, F[i]);  // explicit: same bits in every kernel
         }
     }
 }
@@ -402,12 +402,19 @@ __device__ __forceinline__ void hess_node_euler(const KP &P, const double *__res
     }
 }
 
-// Host-side launchers of the single-instance Jacobian and Hessian kernels
-// (ocp_eval.hip); the batched path uses them for its per-instance mode.
-// `pair_ok`: the Jacobian output is 16-byte aligned.
+// Host-side launchers of the single-instance kernels (ocp_eval.hip,
+// ocp_fused.hip); the batched path uses them for its per-instance mode.
+// `pair_ok`: the Jacobian output is 16-byte aligned.  launch_obj's
+// `partials` holds min(4096, ceil((N+1) / 256)) doubles.  Each covers the
+// problem's boundary rows too.
 hipError_t launch_jac(const KP &P, const double *z, double *jac, bool pair_ok, hipStream_t stream);
 hipError_t launch_hess(const KP &P, const double *z, const double *y, double sigma, double *hv,
                        hipStream_t stream);
+hipError_t launch_obj(const KP &P, const double *z, double *partials, double *obj, hipStream_t stream);
+hipError_t launch_grad(const KP &P, const double *z, double *g, hipStream_t stream);
+hipError_t launch_cons(const KP &P, const double *z, double *c, hipStream_t stream);
+hipError_t launch_eval_kkt(const KP &P, const double *z, const double *y, double sigma, const double *reg,
+                           double *kkt, hipStream_t stream);
 
 }  // namespace dev
 }  // namespace ocp

@@ -15,6 +15,7 @@
 #include "ocp_internal.h"
 #include "ocp_problem.h"
 #include "ocp_quad.h"
+#include "ocp_step_device.h"
 
 using namespace ocp;
 using namespace ocp::dev;
@@ -73,8 +74,8 @@ __global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__rest
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             if (i < n) {
-                Ms[i][tid] = x[i] - P.hh * F[i];
-                Pk[i] = x[i] + P.hh * F[i];
+                Ms[i][tid] = __builtin_fma(-P.hh, F[i], x[i]);
+                Pk[i] = __builtin_fma(P.hh, F[i], x[i]);
             }
         }
     }
@@ -96,13 +97,7 @@ __global__ __launch_bounds__(kBlock) void cons_euler_kernel(KP P, const double *
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= P.N) return;
-    const int n = P.n;
-    const int64_t N = P.N, N1 = P.N1;
-    double x[NB], F[NB];
-    dyn_node<NB>(P, z, k, x, F);
-#pragma unroll
-    for (int i = 0; i < NB; i++)
-        if (i < n) st_nt(c + i * N + k, (z[i * N1 + k + 1] - x[i]) - P.h * F[i]);
+    cons_euler_interval<NB>(P, z, c, k);
 }
 
 // Boundary rows after the n N defect rows: row b holds X_{b mod n} at node 0
@@ -113,9 +108,7 @@ __global__ __launch_bounds__(kBlock) void bnd_cons_kernel(KP P, const double *__
 {
     const int b = blockIdx.x * kBlock + threadIdx.x;
     if (b >= P.nb) return;
-    const int i = b % P.n;
-    const int64_t node = b < P.n ? 0 : P.N;
-    c[(int64_t)P.n * P.N + b] = z[(int64_t)i * P.N1 + node];
+    c[(int64_t)P.n * P.N + b] = bnd_value(P, z, b);
 }
 
 __global__ __launch_bounds__(kBlock) void bnd_jac_kernel(KP P, double *__restrict__ jac)
@@ -153,11 +146,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(KP P, const double *__rest
     const int comp = blockIdx.y;
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k > P.N || (comp >= P.n && k >= P.NU)) return;
-    const double coef = comp < P.n ? P.q[comp] : P.r[comp - P.n];
-    const int64_t e = comp < P.n ? (int64_t)comp * P.N1 + k
-                                 : (int64_t)P.n * P.N1 + (int64_t)(comp - P.n) * P.NU + k;
-    const double w = node_weight(P, k);
-    st_nt(g + e, 2.0 * w * coef * z[e]);
+    grad_entry(P, z, g, comp, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,31 +160,10 @@ template <int NB>
 __global__ __launch_bounds__(kBlock) void obj_partial_kernel(KP P, const double *__restrict__ z,
                                                              double *__restrict__ partials)
 {
-    const int n = P.n, m = P.m;
-    const int64_t N1 = P.N1, NU = P.NU;
-    const double *U = z + (int64_t)n * N1;
+    const int64_t N1 = P.N1;
     double acc = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N1;
-         k += (int64_t)gridDim.x * kBlock) {
-        // every load of a group is issued before its products are summed
-        double v[NB];
-#pragma unroll
-        for (int c = 0; c < NB; c++) v[c] = c < n ? z[c * N1 + k] : 0.0;
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NB; c++)
-            if (c < n) s += P.q[c] * v[c] * v[c];
-        if (k < NU) {  // controls exist on NU nodes
-            for (int l0 = 0; l0 < m; l0 += NB) {
-#pragma unroll
-                for (int u = 0; u < NB; u++) v[u] = l0 + u < m ? U[(l0 + u) * NU + k] : 0.0;
-#pragma unroll
-                for (int u = 0; u < NB; u++)
-                    if (l0 + u < m) s += P.r[l0 + u] * v[u] * v[u];
-            }
-        }
-        acc += node_weight(P, (int)k) * s;
-    }
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N1; k += (int64_t)gridDim.x * kBlock)
+        acc += obj_node<NB>(P, z, k);
     const double t = block_sum<kBlock>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
@@ -397,6 +365,49 @@ hipError_t launch_hess(const KP &P, const double *z, const double *y, double sig
     return hipGetLastError();
 }
 
+hipError_t launch_obj(const KP &P, const double *z, double *partials, double *obj, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<int64_t>(kObjBlocks, blocks_for(P.N1, kBlock));
+    if (P.n <= 4) hipLaunchKernelGGL(obj_partial_kernel<4>, dim3(g), dim3(kBlock), 0, stream, P, z, partials);
+    else if (P.n <= 8) hipLaunchKernelGGL(obj_partial_kernel<8>, dim3(g), dim3(kBlock), 0, stream, P, z, partials);
+    else if (P.n <= 16) hipLaunchKernelGGL(obj_partial_kernel<16>, dim3(g), dim3(kBlock), 0, stream, P, z, partials);
+    else hipLaunchKernelGGL(obj_partial_kernel<32>, dim3(g), dim3(kBlock), 0, stream, P, z, partials);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, partials, (int)g, obj);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const KP &P, const double *z, double *g, hipStream_t stream)
+{
+    dim3 grid(blocks_for(P.N1, kBlock), P.n + P.m);
+    hipLaunchKernelGGL(grad_kernel, grid, dim3(kBlock), 0, stream, P, z, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_cons(const KP &P, const double *z, double *c, hipStream_t stream)
+{
+    const int n = P.n;
+    if (P.scheme == 0) {
+        const unsigned g = blocks_for(P.N, kBlock - 1);
+        if (n <= 4) hipLaunchKernelGGL(cons_kernel<4>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        else if (n <= 8) hipLaunchKernelGGL(cons_kernel<8>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        else if (n <= 16) hipLaunchKernelGGL(cons_kernel<16>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        else hipLaunchKernelGGL(cons_kernel<32>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+    } else {
+        const unsigned g = blocks_for(P.N, kBlock);
+        if (n <= 4) hipLaunchKernelGGL(cons_euler_kernel<4>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        else if (n <= 8) hipLaunchKernelGGL(cons_euler_kernel<8>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        else if (n <= 16) hipLaunchKernelGGL(cons_euler_kernel<16>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        else hipLaunchKernelGGL(cons_euler_kernel<32>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (P.nb > 0)
+        hipLaunchKernelGGL(bnd_cons_kernel, dim3(blocks_for(P.nb, kBlock)), dim3(kBlock), 0, stream, P, z, c);
+    return hipGetLastError();
+}
+
 }  // namespace dev
 }  // namespace ocp
 
@@ -506,15 +517,9 @@ int ocp_eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t
     if (int rc = check_handle(p, "ocp_eval_obj")) return rc;
     if (!z || !obj) return fail(OCP_ERR_ARG, "ocp_eval_obj: null array");
     if (p->model == quad::kModel) return quad::eval_obj(p, z, obj, stream);
-    const unsigned g = (unsigned)std::min<int64_t>(kObjBlocks, blocks_for(p->d.N1, kBlock));
-    const int n = p->d.n;
-    if (n <= 4) hipLaunchKernelGGL(obj_partial_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
-    else if (n <= 8) hipLaunchKernelGGL(obj_partial_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
-    else if (n <= 16) hipLaunchKernelGGL(obj_partial_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
-    else hipLaunchKernelGGL(obj_partial_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, p->partials);
-    if (int rc = check_launch("ocp_eval_obj")) return rc;
-    hipLaunchKernelGGL(obj_final_kernel, dim3(1), dim3(kBlock), 0, stream, p->partials, (int)g, obj);
-    return check_launch("ocp_eval_obj");
+    const hipError_t e = launch_obj(p->kp, z, p->partials, obj, stream);
+    if (e != hipSuccess) return hip_fail("ocp_eval_obj", e);
+    return OCP_OK;
 }
 
 int ocp_eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t stream)
@@ -523,9 +528,9 @@ int ocp_eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t 
     if (int rc = check_handle(p, "ocp_eval_grad")) return rc;
     if (!z || !g) return fail(OCP_ERR_ARG, "ocp_eval_grad: null array");
     if (p->model == quad::kModel) return quad::eval_grad(p, z, g, stream);
-    dim3 grid(blocks_for(p->d.N1, kBlock), p->d.n + p->d.m);
-    hipLaunchKernelGGL(grad_kernel, grid, dim3(kBlock), 0, stream, p->kp, z, g);
-    return check_launch("ocp_eval_grad");
+    const hipError_t e = launch_grad(p->kp, z, g, stream);
+    if (e != hipSuccess) return hip_fail("ocp_eval_grad", e);
+    return OCP_OK;
 }
 
 int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t stream)
@@ -534,24 +539,9 @@ int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t 
     if (int rc = check_handle(p, "ocp_eval_cons")) return rc;
     if (!z || !c) return fail(OCP_ERR_ARG, "ocp_eval_cons: null array");
     if (p->model == quad::kModel) return quad::eval_cons(p, z, c, stream);
-    const int n = p->d.n;
-    if (p->d.scheme == OCP_SCHEME_TRAPEZOIDAL) {
-        const unsigned g = blocks_for(p->d.N, kBlock - 1);
-        if (n <= 4) hipLaunchKernelGGL(cons_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-        else if (n <= 8) hipLaunchKernelGGL(cons_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-        else if (n <= 16) hipLaunchKernelGGL(cons_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-        else hipLaunchKernelGGL(cons_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-    } else {
-        const unsigned g = blocks_for(p->d.N, kBlock);
-        if (n <= 4) hipLaunchKernelGGL(cons_euler_kernel<4>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-        else if (n <= 8) hipLaunchKernelGGL(cons_euler_kernel<8>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-        else if (n <= 16) hipLaunchKernelGGL(cons_euler_kernel<16>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-        else hipLaunchKernelGGL(cons_euler_kernel<32>, dim3(g), dim3(kBlock), 0, stream, p->kp, z, c);
-    }
-    if (p->d.nb > 0)
-        hipLaunchKernelGGL(bnd_cons_kernel, dim3(blocks_for(p->d.nb, kBlock)), dim3(kBlock), 0, stream,
-                           p->kp, z, c);
-    return check_launch("ocp_eval_cons");
+    const hipError_t e = launch_cons(p->kp, z, c, stream);
+    if (e != hipSuccess) return hip_fail("ocp_eval_cons", e);
+    return OCP_OK;
 }
 
 int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream_t stream)

@@ -114,12 +114,14 @@ def device_point(torch, device, N: int, n: int, m: int, seed: int):
     return torch.cat([X, U]), y
 
 
-def make_batch(count: int = 512, n: int = 6, m: int = 3, seed: int = 0, Ns=None):
+def make_batch(count: int = 512, n: int = 6, m: int = 3, seed: int = 0, Ns=None, scheme: int = 0,
+               bnd: int = 0):
     """Instances of the batched workload: N_b from ``batched_sizes`` (unless
     given), instance b drawn from ``default_rng([seed, b])`` in the
-    single-instance order (A, B, gamma, X, U, y)."""
+    single-instance order (A, B, gamma, X, U, y), with the given scheme and
+    boundary option."""
     Ns = batched_sizes(count, seed=seed) if Ns is None else Ns
-    return [make_instance(int(N), n, m, seed=[seed, b]) for b, N in enumerate(Ns)]
+    return [make_instance(int(N), n, m, seed=[seed, b], scheme=scheme, bnd=bnd) for b, N in enumerate(Ns)]
 
 
 def pack(insts):
