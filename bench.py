@@ -65,54 +65,82 @@ def algorithmic_bytes(s, N, n, m):
     }
 
 
-def cpu_baseline(inst, target_s=12.0):
-    """The oracle's Jacobian + Hessian on a bounded slice of the workload,
-    timed on the host cores: intervals [0, K) for the Jacobian and nodes
-    [0, K) for the Hessian, K chosen so the run takes about target_s."""
+def cpu_model() -> str:
+    """The host CPU's model name, from lscpu (falling back to /proc/cpuinfo)."""
+    import subprocess
+    names = []
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        names += [ln.split(":", 1)[1].strip() for ln in out.splitlines() if ln.startswith("Model name")]
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names += [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")][:1]
+    except OSError:
+        pass
+    return max(names, key=len) if names else "unknown"
+
+
+def cpu_baseline(inst, synth, target_s=4.0):
+    """The oracle's Jacobian + Hessian timed on the host cores (wall time,
+    median of repetitions):
+      - the large workload (N = 1e6, n = 16, m = 8) on a bounded slice,
+        intervals [0, K) for the Jacobian and nodes [0, K) for the Hessian,
+        K chosen so one repetition takes about target_s; median of 3, on all
+        OpenMP threads and on one thread;
+      - the 1000-interval parity workload and the 1e5-interval
+        interior-point-loop workload in full, median of 10, all threads."""
     import oracle
     oracle.build(force=False)
     threads = oracle.get_threads()
     N = inst.N
-    K = 2000
-    t0 = time.perf_counter()
-    oracle.jac(inst, 0, K)
-    oracle.hess(inst, 0, K)
-    dt = time.perf_counter() - t0
-    K = int(min(N, max(K, K * target_s / max(dt, 1e-6))))
     T = 2 * inst.n + 2 * inst.m
     S = oracle.sizes(inst.N, inst.n, inst.m)["S"]
-    t0 = time.perf_counter()
-    oracle.jac(inst, 0, K)
-    oracle.hess(inst, 0, K)
-    dt = time.perf_counter() - t0
+
+    def run(K, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.jac(inst, 0, K)
+            oracle.hess(inst, 0, K)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    K = 2000
+    dt = run(K, 1)
+    K = int(min(N, max(K, K * target_s / max(dt, 1e-6))))
+    dt = run(K, 3)
     nnz = K * inst.n * T + K * S
     # the same on one thread, over a slice sized for about a tenth of target_s
     K1 = max(1000, min(N, int(K * (target_s / 10) / max(dt * threads, 1e-6))))
     oracle.set_threads(1)
     try:
-        t0 = time.perf_counter()
-        oracle.jac(inst, 0, K1)
-        oracle.hess(inst, 0, K1)
-        dt1 = time.perf_counter() - t0
+        dt1 = run(K1, 3)
     finally:
         oracle.set_threads(threads)
     nnz1 = K1 * inst.n * T + K1 * S
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    small = {}
+    for name, (Ns, ns, ms) in (("parity_N1e3_n4_m2", synth.PARITY), ("ipm_loop_N1e5_n8_m4", synth.IPM_LOOP)):
+        si = synth.make_instance(Ns, ns, ms, seed=0)
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            oracle.jac(si)
+            oracle.hess(si)
+            ts.append(time.perf_counter() - t0)
+        sz = oracle.sizes(Ns, ns, ms)
+        small[name] = {"median_s": round(float(np.median(ts)), 6),
+                       "nnz_per_s": (sz["nnzj"] + sz["nnzh"]) / float(np.median(ts)), "reps": 10}
     return {"value": nnz / dt, "unit": "nonzeros/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle jac on intervals [0,{K}) + hess on nodes [0,{K}) of the "
-                      f"N={N} n={inst.n} m={inst.m} workload ({nnz} nonzeros, {dt:.2f} s, "
-                      f"OpenMP threads={threads})",
+                      f"N={N} n={inst.n} m={inst.m} workload ({nnz} nonzeros), median of 3 "
+                      f"repetitions ({dt:.2f} s each), OpenMP threads={threads}",
             "single_thread_value": nnz1 / dt1,
-            "single_thread_sample": f"intervals/nodes [0,{K1}), {nnz1} nonzeros, {dt1:.2f} s",
-            "cpu_model": model,
+            "single_thread_sample": f"intervals/nodes [0,{K1}), {nnz1} nonzeros, median of 3 "
+                                    f"repetitions ({dt1:.2f} s each)",
+            "full_workloads": small,
+            "cpu_model": cpu_model(),
             "seconds": dt}
 
 
@@ -189,11 +217,15 @@ def ipm_loop(torch, ocp, synth, iters=50):
 
 
 def batched(torch, ocp, synth, reps=10):
-    """The batched workload: 512 instances, N_b ~ U{200..20000}, n = 6, m = 3,
-    Jacobian + Hessian values of all of them.  Four ways: one single-instance
+    """The batched workload: 512 instances, N_b ~ U{200..20000}, n = 6, m = 3.
+
+    Jacobian + Hessian values of all of them, four ways: one single-instance
     launch per instance and evaluation (1024 launches), the same captured in a
-    HIP graph, the persistent launch over the tile list (after autotuning its
-    tile shape), and the persistent launch replayed from a graph."""
+    HIP graph, the batched launch over the tile list (after autotuning its tile
+    shape), and that launch replayed from a graph.  Then the whole
+    interior-point step (objective, gradient, defects and the fused KKT
+    values of every instance) batched against per-instance launches, and the
+    same with the COO Jacobian and Hessian values added."""
     import tempfile
     insts = synth.make_batch(512, 6, 3, seed=0)
     dev = torch.device("cuda", 0)
@@ -205,7 +237,8 @@ def batched(torch, ocp, synth, reps=10):
     jac = torch.empty(tot["jac"], dtype=torch.float64, device=dev)
     hess = torch.empty(tot["hess"], dtype=torch.float64, device=dev)
     nnz = tot["jac"] + tot["hess"]
-    nbytes = 8 * nnz + 8 * sum(i.n * (i.N + 1) for i in insts) * 2 + 8 * tot["c"]
+    nx = sum(i.n * (i.N + 1) for i in insts)
+    nbytes = 8 * nnz + 8 * nx * 2 + 8 * tot["c"]
 
     def timed(fn):
         fn()
@@ -227,24 +260,70 @@ def batched(torch, ocp, synth, reps=10):
         cfg, tune_ms = batch.autotune(z, y, 1.0, jac, hess, reps=3, cache=os.path.join(td, "t.json"))
     table = batch.tuning
     looped = min((t for t in table if t["wgs_per_cu"] > 0), key=lambda t: t["ms"])
-    res["persistent_ms"] = timed(lambda: batch.eval(z, y, 1.0, jac, hess))
+    res["batched_ms"] = timed(lambda: batch.eval(z, y, 1.0, jac, hess))
     g2, _, _ = batch.graph(z, y, 1.0, jac, hess)
-    res["persistent_graph_ms"] = timed(g2.launch)
+    res["batched_graph_ms"] = timed(g2.launch)
     g2.close()
-    batch.close()
     out = {"workload": "512 instances, N_b ~ U{200..20000} (sum %d), n=6, m=3, jac+hess" % sum(
                i.N for i in insts),
            "nnz": nnz, "autotuned_config": cfg,
-           "best_looping_shape": looped,
+           "autotuned_grid": ("one workgroup per tile (the tile loop runs once)" if cfg["wgs_per_cu"] == 0
+                              else "persistent: %d workgroups per CU loop over the tiles" % cfg["wgs_per_cu"]),
+           "best_persistent_looping_shape": looped,
            "autotune_table_ms": {"%d/%d/%d/%d" % (t["block"], t["pair"], t["wgs_per_cu"], t["order"]):
                                  round(t["ms"], 4) for t in table}}
     for k, v in res.items():
         out[k] = round(v, 4)
         out[k.replace("_ms", "_nnz_per_s")] = nnz / (v * 1e-3)
-    out["persistent_graph_hbm_frac"] = round(nbytes / (res["persistent_graph_ms"] * 1e-3) / HBM_PEAK, 4)
-    out["speedup_persistent_graph_vs_per_instance"] = round(res["per_instance_ms"] / res["persistent_graph_ms"], 3)
-    out["speedup_persistent_graph_vs_per_instance_graph"] = round(
-        res["per_instance_graph_ms"] / res["persistent_graph_ms"], 3)
+    out["batched_graph_hbm_frac"] = round(nbytes / (res["batched_graph_ms"] * 1e-3) / HBM_PEAK, 4)
+    out["speedup_batched_graph_vs_per_instance"] = round(res["per_instance_ms"] / res["batched_graph_ms"], 3)
+    out["speedup_batched_graph_vs_per_instance_graph"] = round(
+        res["per_instance_graph_ms"] / res["batched_graph_ms"], 3)
+    del jac, hess
+
+    # the whole interior-point step: objective, gradient, defects and the
+    # fused KKT values (the matrix a step factorizes), and the same plus the
+    # COO Jacobian and Hessian values
+    nvar, ncon, dim = tot["z"], tot["c"], tot["dim"]
+    reg = torch.full((dim,), 1e-8, dtype=torch.float64, device=dev)
+    step_bytes = {  # algorithmic bytes of each part, summed over the instances
+        ocp.EVAL_OBJ: 8 * nvar, ocp.EVAL_GRAD: 16 * nvar, ocp.EVAL_CONS: 8 * (nvar + ncon),
+        ocp.EVAL_KKT: 8 * (nx + ncon + dim + tot["kkt"]),
+        ocp.EVAL_JAC: 8 * (tot["jac"] + nx), ocp.EVAL_HESS: 8 * (tot["hess"] + nx + ncon)}
+    masks = {"step_fused_kkt": ocp.EVAL_OBJ | ocp.EVAL_GRAD | ocp.EVAL_CONS | ocp.EVAL_KKT,
+             "step_all": ocp.EVAL_ALL}
+    for name, what in masks.items():
+        outs = batch.step(z, y, 1.0, reg, what=what)  # allocates the outputs once
+        sb = sum(v for bit, v in step_bytes.items() if what & bit)
+        per = timed(lambda: batch.step(z, y, 1.0, reg, what=what, mode="per_instance", out=outs))
+        gp = batch.step_graph(z, y, 1.0, reg, what=what, mode="per_instance", out=outs)
+        per_g = timed(gp.launch)
+        gp.close()
+        cfg_s, _, tab = batch.autotune_step(z, y, 1.0, reg, what=what, reps=3, out=outs)
+        bat = timed(lambda: batch.step(z, y, 1.0, reg, what=what, out=outs))
+        gb = batch.step_graph(z, y, 1.0, reg, what=what, out=outs)
+        bat_g = timed(gb.launch)
+        gb.close()
+        loop = min((t for t in tab if t["wgs_per_cu"] > 0), key=lambda t: t["ms"])
+        # the parts of the step on their own, at the step's tuned shape
+        parts = {}
+        for pname, pw in (("obj_grad_cons", ocp.EVAL_OBJ | ocp.EVAL_GRAD | ocp.EVAL_CONS),
+                          ("kkt", ocp.EVAL_KKT), ("jac_hess", ocp.EVAL_JAC | ocp.EVAL_HESS)):
+            if what & pw == pw:
+                pb = sum(v for bit, v in step_bytes.items() if pw & bit)
+                pms = timed(lambda: batch.step(z, y, 1.0, reg, what=pw, out=outs))
+                parts[pname] = {"ms": round(pms, 4), "bytes": pb,
+                                "hbm_frac": round(pb / (pms * 1e-3) / HBM_PEAK, 4)}
+        out[name] = {"what": what, "bytes": sb, "parts": parts,
+                     "per_instance_ms": round(per, 4), "per_instance_graph_ms": round(per_g, 4),
+                     "autotuned_config": cfg_s, "batched_ms": round(bat, 4),
+                     "batched_graph_ms": round(bat_g, 4),
+                     "best_persistent_looping_shape": loop,
+                     "batched_graph_hbm_frac": round(sb / (bat_g * 1e-3) / HBM_PEAK, 4),
+                     "speedup_batched_graph_vs_per_instance": round(per / bat_g, 3),
+                     "speedup_batched_graph_vs_per_instance_graph": round(per_g / bat_g, 3)}
+        del outs
+    batch.close()
     return out
 
 
@@ -534,7 +613,9 @@ def reordered(torch, ocp, synth, reps=10):
             "natural_then_gather": lambda: (prob.assemble_kkt(t_pj, t_ph, t_rp, jv, hv, None, out=kkt),
                                             torch.index_select(kkt, 0, t_inv, out=kkt2)),
         }
-        r = {"nnzk": s["nnzk"], "host_permute_s": round(t_perm, 2), "bytes": nbytes}
+        r = {"nnzk": s["nnzk"], "host_permute_s": round(t_perm, 2), "bytes": nbytes,
+             "note": "reordered_assemble_kkt_mapped passes no plan: the handle builds one for the maps on "
+                     "its first call and reuses it"}
         for name, fn in calls.items():
             fn()
             torch.cuda.synchronize()
@@ -710,6 +791,33 @@ def main():
             "frac": round(byt[dom] / (avg[dom] * 1e-3) / HBM_PEAK, 4),
             "traffic": traffic}
 
+    # each call on its own, its inputs evicted from the caches by a 1 GiB read
+    # just before it: the in-step figures above also carry the write-back of
+    # the previous call's output (up to the 256 MiB Infinity Cache of dirty
+    # lines), which lands on whichever kernel runs next
+    log("[bench] isolated call timings")
+    flush = torch.ones(2 ** 27, **f64)
+    calls = {"eval_obj": lambda: prob.obj(z, out=obj), "eval_grad": lambda: prob.grad(z, out=g),
+             "eval_cons": lambda: prob.cons(z, out=c), "eval_jac": lambda: prob.jac(z, out=jv),
+             "eval_hess": lambda: prob.hess(z, y, 1.0, out=hv),
+             "assemble_kkt": lambda: prob.assemble_kkt(pj, ph, rp, jv, hv, reg, out=kkt)}
+    iso = {}
+    for nm, fn in calls.items():
+        ts = []
+        for _ in range(max(args.steps // 2, 5)):
+            flush.sum()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        iso[nm] = {"median_ms": round(ms, 4), "GB_per_s": round(byt[nm] / (ms * 1e-3) / 1e9, 1),
+                   "hbm_frac": round(byt[nm] / (ms * 1e-3) / HBM_PEAK, 4)}
+    del flush
+    t_jh_iso = (iso["eval_jac"]["median_ms"] + iso["eval_hess"]["median_ms"]) * 1e-3
+
     # achievable-bandwidth context: plain device streams over 2 GiB buffers
     # (torch's fill kernel = a pure write stream, copy_ = a read + write stream)
     def stream_rate(fn, nbytes, reps=10):
@@ -750,6 +858,8 @@ def main():
         "step_nnz_per_s": nnz_jh / (ms_per_step * 1e-3),
         "roofline": roof,
         "kernels": kern,
+        "kernels_isolated": iso,
+        "jac_hess_isolated_hbm_frac": round((byt["eval_jac"] + byt["eval_hess"]) / t_jh_iso / HBM_PEAK, 4),
         "copy_GB_per_s": round(copy_bw / 1e9, 1),
         "write_stream_GB_per_s": round(write_bw / 1e9, 1),
         "jac_frac_of_write_stream": round(kern["eval_jac"]["GB_per_s"] * 1e9 / write_bw, 4),
@@ -799,7 +909,7 @@ def main():
         out["batched"] = batched(torch, ocp, synth)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cb = cpu_baseline(inst)
+        cb = cpu_baseline(inst, synth)
         cb.pop("seconds")
         out["cpu_baseline"] = cb
     prob.close()

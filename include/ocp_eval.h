@@ -179,20 +179,27 @@ int ocp_problem_sizes(const ocp_problem *p, ocp_sizes_t *out);
  * given N.  Uses the handle's workspace. */
 int ocp_eval_obj(const ocp_problem *p, const double *z, double *obj, hipStream_t stream);
 
-/* Gradient of f into g (nvar doubles, device). */
+/* Gradient of f (the trapezoidal cost of Sec. 5, differentiated per node:
+ * 2 w_k q_j X_jk, 2 w_k r_l U_lk; Sec. 6 lists the objective gradient among
+ * the derivative evaluations of each interior-point iteration) into g (nvar
+ * doubles, device, the layout of z). */
 int ocp_eval_grad(const ocp_problem *p, const double *z, double *g, hipStream_t stream);
 
 /* Defects c(z) (Sec. 5, one generator per state component) into c (ncon
  * doubles, device). */
 int ocp_eval_cons(const ocp_problem *p, const double *z, double *c, hipStream_t stream);
 
-/* Jacobian values at the fixed pattern into jvals (nnzj doubles, device, COO
- * order e = (i T + t) N + k).  Reads only the state block of z. */
+/* Jacobian values of the defects at the fixed pattern (Sec. 4: derivatives
+ * that preserve the sparsity of the transcription; Sec. 6: the Jacobian an
+ * interior-point iteration evaluates on the device) into jvals (nnzj doubles,
+ * device, COO order e = (i T + t) N + k).  Reads only the state block of z. */
 int ocp_eval_jac(const ocp_problem *p, const double *z, double *jvals, hipStream_t stream);
 
-/* Hessian-of-Lagrangian values of L = sigma f + y^T c at the fixed lower
- * pattern into hvals (nnzh doubles, device, COO order e = s (N+1) + k).
- * y: ncon doubles (device). */
+/* Hessian-of-Lagrangian values of L = sigma f + y^T c (Sec. 4 and Sec. 6:
+ * second derivatives on the sparse pattern, block-diagonal per node because
+ * every generator of Sec. 5 couples one interval) at the fixed lower pattern
+ * into hvals (nnzh doubles, device, COO order e = s (N+1) + k).  y: ncon
+ * doubles (device). */
 int ocp_eval_hess(const ocp_problem *p, const double *z, const double *y, double sigma,
                   double *hvals, hipStream_t stream);
 
@@ -262,10 +269,17 @@ int ocp_kkt_permute(int64_t dim, const int32_t *rowptr, const int32_t *colind, i
  * perm_j (nnzj), perm_h (nnzh), diag (dim: the slot of every row's
  * diagonal, as from ocp_kkt_permute), jvals, hvals, reg (dim, nullable,
  * indexed by the original rows) and kkt (nnzk) are device arrays; the slot
- * maps must be injective and together cover [0, nnzk).  plan (nullable) is
- * the output of ocp_mapped_plan for these same maps; it saves a pass over
- * the maps on every call.  A plan made from other maps gives wrong values
- * (never an access outside the arrays).  Works for every handle (both
+ * maps must be injective and together cover [0, nnzk).  plan is the output
+ * of ocp_mapped_plan for these maps; it saves a pass over the maps on every
+ * call.  With plan = NULL the handle keeps a plan of its own for the maps of
+ * its last unplanned call (keyed by the three addresses): the first such call
+ * allocates it on the device (so it cannot be captured in a graph; later
+ * ones can) and fills it on `stream`, later calls with the same addresses
+ * reuse it.  Calls that build it must not overlap other mapped assemblies on
+ * the handle.  A plan made from other maps (a stale cached plan included) is
+ * detected tile by tile (the staged slots must cover the tile's range
+ * exactly) and those tiles store their values one by one: always the right
+ * values, never an access outside the arrays.  Works for every handle (both
  * models and schemes).  Fastest for node-grouped orderings such as
  * ocp_stage_order, whose rows of a run of nodes form one contiguous range of
  * the CSR.  Fully overwrites kkt.  No atomics in global memory. */
@@ -302,10 +316,10 @@ int ocp_mapped_plan(const ocp_problem *p, const int32_t *perm_j, const int32_t *
  * ------------------------------------------------------------------------- */
 
 /* Replace the handle's A (n x n), B (n x m; NULL when m = 0) and gamma (n)
- * with device arrays, by stream-ordered device-to-device copies on `stream`,
- * followed by a small kernel on `stream` that rebuilds the handle's
- * column-major copies of A and B.  Evaluations queued on other streams must
- * be ordered by the caller.  Errors: OCP_ERR_ARG, OCP_ERR_HIP. */
+ * with device arrays: one kernel on `stream` copies them and rebuilds the
+ * handle's column-major copies of A and B (stream-ordered, asynchronous).
+ * Evaluations queued on other streams must be ordered by the caller.
+ * Errors: OCP_ERR_ARG, OCP_ERR_HIP. */
 int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const double *gamma,
                          hipStream_t stream);
 

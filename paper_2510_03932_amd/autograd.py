@@ -18,9 +18,16 @@ import torch
 
 
 def _coefficients(prob, A, B, gamma):
-    """Push the coefficient tensors into the handle; a model without
-    coefficient arrays (the quadrotor) takes A = B = gamma = None."""
+    """Push the coefficient tensors into the handle (one stream-ordered kernel
+    launch); a model without coefficient arrays (the quadrotor) takes
+    A = B = gamma = None.  Skipped inside _Lagrangian.backward, which uploads
+    once for the three Functions it applies.  (Keying a cache on the tensors'
+    identity and version is not safe: writes through ``.data``, as
+    torch.autograd.gradcheck makes them, change values without a version
+    bump.)"""
     if A is None and B is None and gamma is None:
+        return
+    if getattr(prob, "_coef_uploaded", False):
         return
     prob.set_coefficients(A.detach(), B.detach(), gamma.detach())
 
@@ -107,15 +114,33 @@ class _Lagrangian(torch.autograd.Function):
         z, y, A, B, gamma = ctx.saved_tensors
         prob, sigma = ctx.prob, ctx.sigma
         gz = gy = gA = gB = gg = None
-        # each piece goes through a Function of its own so that a create_graph
-        # backward stays differentiable where it is defined
-        if ctx.needs_input_grad[0]:
-            gz = _LagGrad.apply(z, y, A, B, gamma, sigma, prob) * gL
-        if ctx.needs_input_grad[1]:
-            gy = _Cons.apply(z, A, B, gamma, prob) * gL
-        if any(ctx.needs_input_grad[2:5]):
-            dA, dB, dg = _CoefGrad.apply(z, y, A, B, gamma, prob)
-            gA, gB, gg = dA * gL, dB * gL, dg * gL
+        # one upload serves the three Functions below (nothing else runs on
+        # the handle in between)
+        _coefficients(prob, A, B, gamma)
+        if not torch.is_grad_enabled():
+            # a plain backward (no create_graph): the library calls directly,
+            # without the nested Functions' bookkeeping
+            zd, yd = z.detach().contiguous(), y.detach().contiguous()
+            if ctx.needs_input_grad[0]:
+                gz = prob.lag_grad(zd, yd, sigma).mul_(gL)
+            if ctx.needs_input_grad[1]:
+                gy = prob.cons(zd).mul_(gL)
+            if any(ctx.needs_input_grad[2:5]):
+                gA, gB, gg = (t.mul_(gL) for t in prob.coef_grad(zd, yd))
+            return gz, gy, gA, gB, gg, None, None
+        prob._coef_uploaded = True
+        try:
+            # each piece goes through a Function of its own so that a
+            # create_graph backward stays differentiable where it is defined
+            if ctx.needs_input_grad[0]:
+                gz = _LagGrad.apply(z, y, A, B, gamma, sigma, prob) * gL
+            if ctx.needs_input_grad[1]:
+                gy = _Cons.apply(z, A, B, gamma, prob) * gL
+            if any(ctx.needs_input_grad[2:5]):
+                dA, dB, dg = _CoefGrad.apply(z, y, A, B, gamma, prob)
+                gA, gB, gg = dA * gL, dB * gL, dg * gL
+        finally:
+            prob._coef_uploaded = False
         return gz, gy, gA, gB, gg, None, None
 
 

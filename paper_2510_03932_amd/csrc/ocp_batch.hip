@@ -74,6 +74,7 @@ struct TileDesc {
 // Coefficients of the whole batch (device), instance-major, and the shared shape.
 struct BP {
     int n, m, npair, T, S, scheme, nb;
+    int defect_lg;  // defect-row KKT tiles of 2^defect_lg intervals
     const double *A, *B, *gam, *q, *r;
     const double *AT, *BT;  // padded columns: n kLd and m kLd doubles per instance
 };
@@ -86,6 +87,7 @@ struct BIO {
     double *parts;    // objective partials (sum of nparts)
 };
 
+template <int SCHEME>
 __device__ __forceinline__ KP make_kp(const BP &bp, const InstDesc &id, int b)
 {
     KP P;
@@ -97,8 +99,8 @@ __device__ __forceinline__ KP make_kp(const BP &bp, const InstDesc &id, int b)
     P.T = bp.T;
     P.S = bp.S;
     P.nnzk = 0;
-    P.NU = bp.scheme ? id.N : id.N + 1;
-    P.scheme = bp.scheme;
+    P.NU = SCHEME ? id.N : id.N + 1;
+    P.scheme = SCHEME;  // a compile-time constant, so the other scheme's code folds away
     P.nb = bp.nb;
     P.h = id.h;
     P.hh = id.hh;
@@ -112,17 +114,18 @@ __device__ __forceinline__ KP make_kp(const BP &bp, const InstDesc &id, int b)
     return P;
 }
 
-template <int NPT>
+template <int NPT, int SCHEME>
 __device__ __forceinline__ void jac_cols(const KP &P, const double *z, double *jac, int64_t k, int col)
 {
-    if (P.scheme) jac_column_euler<NPT>(P, z, jac, k, col);
+    if constexpr (SCHEME != 0) jac_column_euler<NPT>(P, z, jac, k, col);
     else jac_column<NPT>(P, z, jac, k, col);
 }
 
 // KINDS: the evaluation bits this instantiation handles (tiles of other kinds
 // are not in its lists); fewer kinds keep the register footprint of the
-// Jacobian/Hessian-only launch small.
-template <int NB, int BS, int KINDS>
+// Jacobian/Hessian-only launch small.  SCHEME: the batch's scheme, fixed at
+// compile time so that each instantiation holds one scheme's code.
+template <int NB, int BS, int KINDS, int SCHEME>
 __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const InstDesc *__restrict__ inst,
                                                    const TileDesc *__restrict__ tiles, int ntiles, int what,
                                                    bool pair_ok, BIO io)
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileDesc td = tiles[t];
         const InstDesc id = inst[td.b];
-        const KP P = make_kp(bp, id, td.b);
+        const KP P = make_kp<SCHEME>(bp, id, td.b);
         const double *zb = io.z + id.z_off;
         switch (td.kind) {
         case kJac: {
@@ -146,15 +149,15 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
                 const int64_t k = td.k0 + 2 * (int64_t)tid;
                 if (k < P.N) {
                     if (pair_ok) {
-                        jac_cols<2>(P, zb, jb, k, td.col);
+                        jac_cols<2, SCHEME>(P, zb, jb, k, td.col);
                     } else {
-                        jac_cols<1>(P, zb, jb, k, td.col);
-                        jac_cols<1>(P, zb, jb, k + 1, td.col);
+                        jac_cols<1, SCHEME>(P, zb, jb, k, td.col);
+                        jac_cols<1, SCHEME>(P, zb, jb, k + 1, td.col);
                     }
                 }
             } else {
                 const int64_t k = td.k0 + (int64_t)tid;
-                if (k < P.N) jac_cols<1>(P, zb, jb, k, td.col);
+                if (k < P.N) jac_cols<1, SCHEME>(P, zb, jb, k, td.col);
             }
             break;
         }
@@ -162,7 +165,8 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
             if (!(KINDS & OCP_EVAL_HESS)) break;
             const int k = td.k0 + tid;
             if (k <= P.N) {
-                if (P.scheme) hess_node_euler<NB>(P, zb, io.y + id.c_off, io.sigma, io.hess + id.hess_off, k);
+                if constexpr (SCHEME != 0)
+                    hess_node_euler<NB>(P, zb, io.y + id.c_off, io.sigma, io.hess + id.hess_off, k);
                 else hess_node<NB>(P, zb, io.y + id.c_off, io.sigma, io.hess + id.hess_off, k);
             }
             break;
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
         case kCons: {
             if (!(KINDS & OCP_EVAL_CONS)) break;
             double *cb = io.cons + id.c_off;
-            if (P.scheme) {
+            if constexpr (SCHEME != 0) {
                 const int64_t k = td.k0 + (int64_t)tid;
                 if (k < P.N) cons_euler_interval<NB>(P, zb, cb, k);
             } else {
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
         case kKktDef:
             if (!(KINDS & OCP_EVAL_KKT)) break;
             kkt_defect_tile<BS>(P, Lo, zb, io.reg ? io.reg + id.dim_off : nullptr, io.kkt + id.kkt_off, td.k0,
-                                lds);
+                                bp.defect_lg, lds);
             break;
         case kKktVar:
             if (!(KINDS & OCP_EVAL_KKT)) break;
@@ -319,7 +323,7 @@ static std::vector<TileDesc> build_tiles(const ocp_batch &b, const ocp_batch_con
         if (what & OCP_EVAL_OBJ)
             for (int64_t k0 = 0; k0 <= N; k0 += kObjTile) put(k0, kObj, 1, 0);
         if (what & OCP_EVAL_KKT) {
-            for (int64_t k0 = 0; k0 < N; k0 += kDefectTile) put(k0, kKktDef, 1, 0);
+            for (int64_t k0 = 0; k0 < N; k0 += (int64_t)1 << b.bp.defect_lg) put(k0, kKktDef, 1, 0);
             for (int64_t k0 = 0; k0 <= N; k0 += c.block) put(k0, kKktVar, 1, 0);
         }
         if (b.shape.nb > 0 && (what & (OCP_EVAL_CONS | OCP_EVAL_JAC | OCP_EVAL_KKT))) put(0, kBnd, 1, 0);
@@ -400,23 +404,31 @@ constexpr int kKindsLight = OCP_EVAL_OBJ | OCP_EVAL_GRAD | OCP_EVAL_CONS;
 constexpr int kKindsKKT = OCP_EVAL_KKT;
 constexpr int kGroups[3] = {kKindsJH, kKindsLight, kKindsKKT};
 
-template <int BS, int KINDS>
-static void launch_batch_kinds(const ocp_batch *b, const TileDesc *tiles, int ntiles, int what, const BIO &io,
-                               hipStream_t s)
+template <int BS, int KINDS, int SCHEME>
+static void launch_batch_scheme(const ocp_batch *b, const TileDesc *tiles, int ntiles, int what, const BIO &io,
+                                hipStream_t s)
 {
     const int cap = b->cfg.wgs_per_cu > 0 ? b->cus * b->cfg.wgs_per_cu : ntiles;
     const unsigned grid = (unsigned)std::max(1, std::min(ntiles, cap));
     const bool pair_ok = ((uintptr_t)io.jac % 16 == 0);
-    const size_t lds = (what & OCP_EVAL_KKT) ? kkt_defect_lds(b->n, b->m, b->shape.T) * sizeof(double) : 0;
+    const size_t lds = (what & OCP_EVAL_KKT) ? kkt_defect_lds(b->n, b->m, b->shape.T, 1 << b->bp.defect_lg) * sizeof(double) : 0;
     const int n = b->n;
     if (n <= 4)
-        hipLaunchKernelGGL((batch_kernel<4, BS, KINDS>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
+        hipLaunchKernelGGL((batch_kernel<4, BS, KINDS, SCHEME>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
     else if (n <= 8)
-        hipLaunchKernelGGL((batch_kernel<8, BS, KINDS>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
+        hipLaunchKernelGGL((batch_kernel<8, BS, KINDS, SCHEME>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
     else if (n <= 16)
-        hipLaunchKernelGGL((batch_kernel<16, BS, KINDS>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
+        hipLaunchKernelGGL((batch_kernel<16, BS, KINDS, SCHEME>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
     else
-        hipLaunchKernelGGL((batch_kernel<32, BS, KINDS>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
+        hipLaunchKernelGGL((batch_kernel<32, BS, KINDS, SCHEME>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io);
+}
+
+template <int BS, int KINDS>
+static void launch_batch_kinds(const ocp_batch *b, const TileDesc *tiles, int ntiles, int what, const BIO &io,
+                               hipStream_t s)
+{
+    if (b->scheme == OCP_SCHEME_TRAPEZOIDAL) launch_batch_scheme<BS, KINDS, 0>(b, tiles, ntiles, what, io, s);
+    else launch_batch_scheme<BS, KINDS, 1>(b, tiles, ntiles, what, io, s);
 }
 
 // One group's launch: `what` lies within group g.
@@ -661,6 +673,7 @@ int ocp_batch_create_ex(int32_t count, const int64_t *Ns, int32_t n, int32_t m, 
     b->bp.S = shape.S;
     b->bp.scheme = scheme;
     b->bp.nb = (int)shape.nb;
+    b->bp.defect_lg = __builtin_ctz((unsigned)kkt_defect_kt(n, m, shape.T));
     b->bp.A = b->coef;
     b->bp.B = b->coef + nA;
     b->bp.gam = b->bp.B + nB;

@@ -188,7 +188,9 @@ __device__ __forceinline__ void jac_column(const KP &P, const double *__restrict
 // ---------------------------------------------------------------------------
 // Hessian-of-Lagrangian values at node k <= N.  NB >= n is a compile-time
 // bound so the node's states and multipliers stay in registers; all loads are
-// issued before the arithmetic.
+// issued before the arithmetic, and the control slots (constants) and the
+// bilinear slots (multipliers only) are stored before the state diagonals,
+// so their stores leave while the sines are computed.
 // ---------------------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict__ z,
@@ -209,9 +211,18 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
             if (k < P.N) yr[i] = yi[0];
         }
     }
+    const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
+    for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
     double yt[NB];
 #pragma unroll
     for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
+    if (n >= 3) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_nt(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
+    } else if (n == 2) {
+        st_nt(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+    }
 #pragma unroll
     for (int j = 0; j < NB; j++) {
         if (j < n) {
@@ -225,21 +236,13 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
             st_nt(hv + j * N1 + k, v);
         }
     }
-    if (n >= 3) {
-#pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < n) st_nt(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
-    } else if (n == 2) {
-        st_nt(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
-    }
-    const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
-    for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
 }
 
 // ---------------------------------------------------------------------------
 // Dynamics at node k <= N: the node's states x[i] = X_ik and F_i(k) for every
 // i < n (NB >= n, entries beyond n are zero).  F_i sums j ascending, then l
-// ascending, then the bilinear term.
+// ascending, then the bilinear term.  The states and the first NB controls
+// are loaded before any arithmetic (further controls, when m > NB, after).
 // ---------------------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__ z, int64_t k,
@@ -248,9 +251,11 @@ __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__
     const int n = P.n, m = P.m;
     const int64_t N1 = P.N1;
     const double *U = z + (int64_t)n * N1;
+    double u[NB];
 #pragma unroll
     for (int i = 0; i < NB; i++) {
         x[i] = (i < n) ? z[i * N1 + k] : 0.0;
+        u[i] = (i < m) ? U[(int64_t)i * P.NU + k] : 0.0;
         F[i] = 0.0;
     }
 #pragma unroll
@@ -262,11 +267,19 @@ __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__
             for (int i = 0; i < NB; i++) F[i] = __builtin_fma(a[i], s, F[i]);
         }
     }
-    for (int l = 0; l < m; l++) {
-        const double u = U[(int64_t)l * P.NU + k];
+#pragma unroll
+    for (int l = 0; l < NB; l++) {
+        if (l < m) {
+            const double *b = P.BT + l * kLd;
+#pragma unroll
+            for (int i = 0; i < NB; i++) F[i] = __builtin_fma(b[i], u[l], F[i]);
+        }
+    }
+    for (int l = NB; l < m; l++) {
+        const double ul = U[(int64_t)l * P.NU + k];
         const double *b = P.BT + l * kLd;
 #pragma unroll
-        for (int i = 0; i < NB; i++) F[i] = __builtin_fma(b[i], u, F[i]);
+        for (int i = 0; i < NB; i++) F[i] = __builtin_fma(b[i], ul, F[i]);
     }
 #pragma unroll
     for (int i = 0; i < NB; i++) {

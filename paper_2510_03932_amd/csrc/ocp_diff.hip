@@ -524,19 +524,26 @@ __global__ __launch_bounds__(kBlock) void coef_final_kernel(KP P, const double *
 
 int nb_of(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
-// Rebuild the padded columns AT, BT (kLd rows each, zero below row n) from
-// the row-major A and B, on the device so that a coefficient update stays
-// asynchronous on the caller's stream.
-__global__ __launch_bounds__(kBlock) void pack_columns_kernel(int n, int m, const double *__restrict__ A,
-                                                              const double *__restrict__ B,
-                                                              double *__restrict__ AT,
-                                                              double *__restrict__ BT)
+// A coefficient update in one launch: the row-major copies of A, B and gamma
+// and the padded columns AT, BT (kLd rows each, zero below row n), built from
+// the caller's device arrays, on the caller's stream (asynchronous).
+__global__ __launch_bounds__(kBlock) void set_coefficients_kernel(int n, int m, const double *__restrict__ A,
+                                                                  const double *__restrict__ B,
+                                                                  const double *__restrict__ gam,
+                                                                  double *__restrict__ hA, double *__restrict__ hB,
+                                                                  double *__restrict__ hgam,
+                                                                  double *__restrict__ AT,
+                                                                  double *__restrict__ BT)
 {
     const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= (n + m) * kLd) return;
-    const int c = e / kLd, i = e % kLd;
-    if (c < n) AT[e] = i < n ? A[i * n + c] : 0.0;
-    else BT[e - n * kLd] = i < n ? B[i * m + (c - n)] : 0.0;
+    if (e < (n + m) * kLd) {
+        const int c = e / kLd, i = e % kLd;
+        if (c < n) AT[e] = i < n ? A[i * n + c] : 0.0;
+        else BT[e - n * kLd] = i < n ? B[i * m + (c - n)] : 0.0;
+    }
+    if (e < n * n) hA[e] = A[e];
+    if (e < n * m) hB[e] = B[e];
+    if (e < n) hgam[e] = gam[e];
 }
 
 }  // namespace
@@ -598,18 +605,11 @@ int ocp_set_coefficients(ocp_problem *p, const double *A, const double *B, const
         return fail(OCP_ERR_ARG, "ocp_set_coefficients: the handle's model has no coefficients");
     if (!A || !gamma || (p->d.m > 0 && !B)) return fail(OCP_ERR_ARG, "ocp_set_coefficients: NULL array");
     const int n = p->d.n, m = p->d.m;
-    hipError_t e = hipMemcpyAsync(const_cast<double *>(p->kp.A), A, sizeof(double) * n * n,
-                                  hipMemcpyDeviceToDevice, stream);
-    if (e == hipSuccess && m)
-        e = hipMemcpyAsync(const_cast<double *>(p->kp.B), B, sizeof(double) * n * m,
-                           hipMemcpyDeviceToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(const_cast<double *>(p->kp.gam), gamma, sizeof(double) * n,
-                           hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return hip_fail("ocp_set_coefficients", e);
-    hipLaunchKernelGGL(pack_columns_kernel, dim3(blocks_for((int64_t)(n + m) * kLd, kBlock)),
-                       dim3(kBlock), 0, stream, n, m, p->kp.A, p->kp.B,
-                       const_cast<double *>(p->kp.AT), const_cast<double *>(p->kp.BT));
+    const int64_t work = std::max<int64_t>((int64_t)(n + m) * kLd, (int64_t)n * n);
+    hipLaunchKernelGGL(set_coefficients_kernel, dim3(blocks_for(work, kBlock)), dim3(kBlock), 0, stream, n, m, A,
+                       B, gamma, const_cast<double *>(p->kp.A), const_cast<double *>(p->kp.B),
+                       const_cast<double *>(p->kp.gam), const_cast<double *>(p->kp.AT),
+                       const_cast<double *>(p->kp.BT));
     return check_launch("ocp_set_coefficients");
 }
 

@@ -499,6 +499,7 @@ void ocp_destroy(ocp_problem *p)
     if (p->coef) (void)hipFree(p->coef);
     if (p->partials) (void)hipFree(p->partials);
     if (p->cpart) (void)hipFree(p->cpart);
+    if (p->mplan) (void)hipFree(p->mplan);
     delete p;
 }
 

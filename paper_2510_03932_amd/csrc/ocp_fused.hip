@@ -10,11 +10,12 @@
 // the COO kernels and the assembly.  The tile bodies (ocp_step_device.h) are
 // shared with the batched evaluation.
 //
-// Defect rows: workgroup b owns intervals [b KT, b KT + KT).  It stages the
-// states and their cosines at the KT+1 nodes, the rows' regularization and
-// the scaled coefficients -hh A, -hh B, -hh gamma in LDS (a wavefront spans
-// four slots of a row, so coefficient reads from global memory would be
-// per-lane loads, each waited for); then, for each state
+// Defect rows: workgroup b owns intervals [b KT, b KT + KT), KT = 16, 32 or
+// 64 so that one row block (KT rows of T+1 entries) holds 500 to 1000 values.
+// It stages the states and their cosines at the KT+1 nodes, the rows'
+// regularization and the scaled coefficients -hh A, -hh B, -hh gamma in LDS
+// (a wavefront spans several slots of a row, so coefficient reads from global
+// memory would be per-lane loads, each waited for); then, for each state
 // component i, it computes the tile's KT rows (T Jacobian entries and the
 // diagonal each) slot by slot into an LDS tile and writes the rows'
 // contiguous CSR range with full-line stores.
@@ -36,12 +37,12 @@ using namespace ocp::dev;
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, const double *__restrict__ z,
+__global__ __launch_bounds__(kBlock) void kkt_defect_kernel(KP P, KKTLayout Lo, int LG, const double *__restrict__ z,
                                                             const double *__restrict__ reg,
                                                             double *__restrict__ kkt)
 {
     extern __shared__ double lds[];
-    kkt_defect_tile<kBlock>(P, Lo, z, reg, kkt, (int64_t)blockIdx.x * kDefectTile, lds);
+    kkt_defect_tile<kBlock>(P, Lo, z, reg, kkt, (int64_t)blockIdx.x << LG, LG, lds);
 }
 
 template <int NB>
@@ -72,11 +73,14 @@ hipError_t launch_eval_kkt(const KP &P, const double *z, const double *y, double
                            double *kkt, hipStream_t stream)
 {
     const KKTLayout Lo = kkt_layout(P.n);
-    // defect-row tiles of kDefectTile intervals; LDS holds the tile's states,
-    // their cosines and the output rows of one state component
-    const size_t lds = kkt_defect_lds(P.n, P.m, P.T) * sizeof(double);
-    hipLaunchKernelGGL(kkt_defect_kernel, dim3(blocks_for(P.N, kDefectTile)), dim3(kBlock), lds, stream, P, Lo,
-                       z, reg, kkt);
+    // defect-row tiles of KT = 2^LG intervals; LDS holds the tile's states,
+    // their cosines, the rows' regularization, the scaled coefficients and the
+    // output row block
+    const int KT = kkt_defect_kt(P.n, P.m, P.T);
+    const int LG = __builtin_ctz((unsigned)KT);
+    const size_t lds = kkt_defect_lds(P.n, P.m, P.T, KT) * sizeof(double);
+    hipLaunchKernelGGL(kkt_defect_kernel, dim3(blocks_for(P.N, KT)), dim3(kBlock), lds, stream, P, Lo, LG, z, reg,
+                       kkt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g(blocks_for(P.N1, kBlock));

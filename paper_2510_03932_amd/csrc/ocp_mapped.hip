@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 #include <string>
 
 #include "ocp_device.h"
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(kBlock) void mapped_assemble_kernel(
     const double *__restrict__ reg, double *__restrict__ kkt)
 {
     extern __shared__ double tile[];  // the tile's entries (host-sized, <= kMapCap)
+    __shared__ int filled;            // tile slots written by this tile's entries
     int base, count;
     if (plan) {
         base = plan[2 * blockIdx.x];
@@ -205,19 +207,35 @@ __global__ __launch_bounds__(kBlock) void mapped_assemble_kernel(
         count = r.y;
     }
     if (base >= 0) {
+        if (threadIdx.x == 0) filled = 0;
+        __syncthreads();
+        int mine = 0;
         tile_visit(P, blockIdx.x, perm_j, perm_h, diag, jv, hv, reg, true, [&](int32_t q, double v) {
             const uint32_t loc = (uint32_t)q - (uint32_t)base;
-            if (loc < (uint32_t)count) tile[loc] = v;
-            else if ((uint32_t)q < (uint32_t)P.nnzk) kkt[q] = v;
+            if (loc < (uint32_t)count) {
+                tile[loc] = v;
+                mine++;
+            } else if ((uint32_t)q < (uint32_t)P.nnzk) {
+                kkt[q] = v;
+            }
         });
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mine += __shfl_down(mine, off, 64);
+        if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&filled, mine);
         __syncthreads();
-        double *out = kkt + base;
-        for (int x = threadIdx.x; x < count; x += kBlock) st_nt(out + x, tile[x]);
-    } else {
-        tile_visit(P, blockIdx.x, perm_j, perm_h, diag, jv, hv, reg, true, [&](int32_t q, double v) {
-            if ((uint32_t)q < (uint32_t)P.nnzk) kkt[q] = v;
-        });
+        if (filled == count) {
+            // the tile's slots (distinct, the maps being injective) cover the
+            // range exactly: write it with contiguous stores
+            double *out = kkt + base;
+            for (int x = threadIdx.x; x < count; x += kBlock) st_nt(out + x, tile[x]);
+            return;
+        }
+        // else a plan made from other slot maps: the staged values go to
+        // their slots one by one below (values stored above are stored again)
     }
+    tile_visit(P, blockIdx.x, perm_j, perm_h, diag, jv, hv, reg, true, [&](int32_t q, double v) {
+        if ((uint32_t)q < (uint32_t)P.nnzk) kkt[q] = v;
+    });
 }
 
 // Tile shape for a handle: the largest power of two of nodes whose entries
@@ -290,6 +308,31 @@ int ocp_assemble_kkt_mapped(const ocp_problem *p, const int32_t *perm_j, const i
     if (!perm_j || !perm_h || !diag || !jvals || !hvals || !kkt)
         return fail(OCP_ERR_ARG, "ocp_assemble_kkt_mapped: null array");
     const MP P = make_mp(p);
+    if (!plan) {
+        // the handle keeps the plan of the slot maps it last assembled from
+        // (keyed by their addresses; a stale plan is caught per tile by the
+        // kernel's exact-cover check and costs speed, not correctness)
+        std::lock_guard<std::mutex> lock(p->mplan_mu);
+        const int64_t len = 2 * (int64_t)blocks_for(p->d.N1, P.KT);
+        if (!p->mplan) {
+            if (hipMalloc(&p->mplan, (size_t)len * sizeof(int32_t)) != hipSuccess) {
+                (void)hipGetLastError();  // no plan: every tile finds its own range
+                p->mplan = nullptr;
+            }
+            p->mplan_key[0] = p->mplan_key[1] = p->mplan_key[2] = nullptr;
+        }
+        if (p->mplan) {
+            if (p->mplan_key[0] != perm_j || p->mplan_key[1] != perm_h || p->mplan_key[2] != diag) {
+                hipLaunchKernelGGL(mapped_plan_kernel, dim3(blocks_for(p->d.N1, P.KT)), dim3(kBlock), 0, stream,
+                                   P, perm_j, perm_h, diag, p->mplan);
+                if (int rc = check_launch("ocp_assemble_kkt_mapped: plan")) return rc;
+                p->mplan_key[0] = perm_j;
+                p->mplan_key[1] = perm_h;
+                p->mplan_key[2] = diag;
+            }
+            plan = p->mplan;
+        }
+    }
     hipLaunchKernelGGL(mapped_assemble_kernel, dim3(blocks_for(p->d.N1, P.KT)), dim3(kBlock),
                        (size_t)P.cap * sizeof(double), stream, P, plan, perm_j, perm_h, diag, jvals, hvals, reg, kkt);
     return check_launch("ocp_assemble_kkt_mapped");

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "ocp_device.h"
@@ -38,6 +39,11 @@ struct ocp_problem {
     int model = 0;        // 0: the synthetic dynamics family; ocp::quad::kModel: the quadrotor
     double quad_g = 0.0;  // quadrotor gravity and control weight
     double quad_r = 0.0;
+    // plan of the slot maps of the last unplanned ocp_assemble_kkt_mapped
+    // (device, allocated on first use), keyed by the maps' addresses
+    mutable std::mutex mplan_mu;
+    mutable int32_t *mplan = nullptr;
+    mutable const void *mplan_key[3] = {nullptr, nullptr, nullptr};
 };
 
 static inline int hip_fail(const char *what, hipError_t e)

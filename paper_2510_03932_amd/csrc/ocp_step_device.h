@@ -85,7 +85,8 @@ __device__ __forceinline__ void grad_entry(const KP &P, const double *__restrict
 
 // The objective's term of node k: w_k (sum_j q_j X_jk^2 + sum_l r_l U_lk^2),
 // states first (every load issued before the sum), then the controls in
-// groups of NB, each in component order.
+// groups of NB, each in component order.  (Loading the controls together
+// with the states measured no faster at n = 16, m = 8 and costs occupancy.)
 template <int NB>
 __device__ __forceinline__ double obj_node(const KP &P, const double *__restrict__ z, int64_t k)
 {
@@ -175,32 +176,99 @@ __device__ __forceinline__ int64_t kkt_bnd_start(const KP &P, const KKTLayout &L
     return kkt_cons_start(P, Lo) + (int64_t)P.n * P.N * (P.T + 1);
 }
 
-constexpr int kDefectTile = 16;  // intervals per defect-row tile
+// Defect-row tiles: KT intervals per tile (a power of two, 16 to 64), chosen
+// per problem by kkt_defect_kt; each row block is computed slot-major into an
+// LDS tile and copied out (see kkt_defect_tile).
+constexpr int kDefectKTMax = 64;
+constexpr size_t kDefectLdsMax = 64 * 1024;  // bytes of LDS a tile may take
 
-// LDS doubles of one defect-row tile (n states, T Jacobian slots per row).
-inline size_t kkt_defect_lds(int n, int m, int T)
+// LDS doubles of one defect-row tile of KT intervals (n states, m controls,
+// T Jacobian slots per row): states and cosines at KT+1 nodes, the rows'
+// diagonals, the scaled coefficients, and the output tile.
+inline size_t kkt_defect_lds(int n, int m, int T, int KT)
 {
-    return (size_t)kDefectTile * (T + 1) + 2 * (size_t)n * (kDefectTile + 1) + (size_t)n * kDefectTile +
-           (size_t)n * (n + m) + (size_t)n;
+    return 2 * (size_t)n * (KT + 1) + (size_t)n * KT + (size_t)n * (n + m) + (size_t)n + (size_t)KT * (T + 1);
 }
 
-// Defect rows of intervals [k0, k0 + kDefectTile): the tile's states, their
-// cosines, the rows' regularization and the scaled coefficients -hh A, -hh B,
-// -hh gamma are staged in LDS (a wavefront spans four slots of a row, so
-// coefficient reads from global memory would be per-lane loads); then, for
-// each state component i, the tile's rows (T Jacobian entries and the
-// diagonal each) are computed slot by slot into an LDS tile and written as
-// the rows' contiguous CSR range with full-line stores.  reg: the problem's
-// dim-entry regularization or null.  Ends with a barrier.
+// Intervals per defect-row tile: a row block of KT (T+1) entries of about 500
+// to 1000 doubles (measured best at n = 16, m = 8: KT = 16, 784 entries; at
+// n = 6, m = 3: KT = 32, 608 entries), within the LDS bound.
+inline int kkt_defect_kt(int n, int m, int T)
+{
+    int KT = T + 1 >= 33 ? 16 : (T + 1 >= 17 ? 32 : 64);
+    while (KT > 16 && kkt_defect_lds(n, m, T, KT) * sizeof(double) > kDefectLdsMax) KT /= 2;
+    return KT;
+}
+
+// Entry t of defect row (i, k0 + kk): T Jacobian slots then the diagonal,
+// from the tile's LDS arrays (states xs and cosines cs at W = KT + 1 nodes,
+// coefficients cf = -w A | -w B, gs = -w gamma, diagonals rg; w = h/2, or h
+// under forward Euler).
+__device__ __forceinline__ double defect_entry(int i, int t, int kk, int n, int m, int T, int W, int KT,
+                                               bool euler, const double *cf, const double *gs,
+                                               const double *xs, const double *cs, const double *rg)
+{
+#pragma clang fp contract(off)
+    double v;
+    if (euler) {
+        // row i: X_0..X_i at k, X_i at k+1, X_{i+1}..X_{n-1} at k, U at k
+        if (t == i + 1) {
+            v = 1.0;
+        } else if (t <= n) {
+            const int j = t <= i ? t : t - 1;
+            const int jn = (j + 1 == n) ? 0 : j + 1;
+            const int jp = (j == 0) ? n - 1 : j - 1;
+            v = cf[i * (n + m) + j] * cs[j * W + kk];
+            if (i == j) v += gs[j] * xs[jn * W + kk] - 1.0;
+            if (i == jp) v += gs[jp] * xs[jp * W + kk];
+        } else if (t < T) {
+            v = cf[i * (n + m) + n + (t - n - 1)];
+        } else {
+            v = rg[i * KT + kk];
+        }
+    } else if (t < 2 * n) {
+        const int j = t >> 1, s = t & 1, u = kk + s;
+        const int jn = (j + 1 == n) ? 0 : j + 1;
+        const int jp = (j == 0) ? n - 1 : j - 1;
+        v = cf[i * (n + m) + j] * cs[j * W + u];
+        if (i == j) {
+            const double dg = gs[j] * xs[jn * W + u];
+            v += s ? dg + 1.0 : dg - 1.0;
+        }
+        if (i == jp) v += gs[jp] * xs[jp * W + u];
+    } else if (t < T) {
+        v = cf[i * (n + m) + n + ((t - 2 * n) >> 1)];
+    } else {
+        v = rg[i * KT + kk];
+    }
+    return v;
+}
+
+// Defect rows of intervals [k0, k0 + KT): the tile's states and their cosines
+// at nodes k0 .. k0 + KT, the rows' regularization and the scaled
+// coefficients -hh A, -hh B, -hh gamma are staged in LDS (the lanes of a
+// wavefront span several slots of a row, so coefficient reads from global
+// memory would be per-lane loads); then, for each state component i, the rows
+// (i, k0 .. k0 + kn - 1) -- one contiguous CSR range of kn (T + 1) entries,
+// each row its T Jacobian entries and its diagonal -- are computed slot-major
+// (KT lanes share a slot, so a wavefront reads few coefficients and
+// conflict-free state columns) into an LDS tile and copied out with
+// contiguous stores, two barriers per row block.  (Alternating two tiles, one
+// barrier per block, measured 9 % slower at n = 16, m = 8 and 5 % at n = 6,
+// m = 3; storing in output order straight from the sweep, no barrier at all,
+// 15 % slower: the lanes of a wavefront then mix slot kinds and diverge.)
+// KT = 2^LG <= 64 intervals (the caller's grid uses the same KT); reg: the
+// problem's dim-entry regularization or null.  Ends with a barrier, so a
+// following tile may restage the LDS.
 template <int BS>
 __device__ __forceinline__ void kkt_defect_tile(const KP &P, const KKTLayout &Lo, const double *__restrict__ z,
                                                 const double *__restrict__ reg, double *__restrict__ kkt,
-                                                int64_t k0, double *lds)
+                                                int64_t k0, int LG, double *lds)
 {
     // no implicit contraction: the single-instance and the batched kernels
     // inline this body into different code and must produce the same bits
 #pragma clang fp contract(off)
-    constexpr int KT = kDefectTile, LG = 4, W = KT + 1;  // intervals k0 .. k0+KT-1, nodes k0 .. k0+KT
+    const int KT = 1 << LG, W = KT + 1;  // intervals k0 .. k0+KT-1, nodes k0 .. k0+KT
     const int n = P.n, m = P.m, T = P.T, T1 = P.T + 1;
     const int64_t N = P.N, N1 = P.N1;
     const int64_t nvar = (int64_t)n * N1 + (int64_t)m * P.NU;  // controls on NU nodes
@@ -210,14 +278,10 @@ __device__ __forceinline__ void kkt_defect_tile(const KP &P, const KKTLayout &Lo
     double *rg = lds + 2 * n * W;         // [n][KT] the tile's defect-row diagonals (reg or 0)
     double *cf = rg + n * KT;             // [n][n+m] -hh A | -hh B, then [n] -hh gamma
     double *gs = cf + n * (n + m);
-    double *tile = gs + n;                // [KT][T1] output rows
+    double *tile = gs + n;                // [KT][T1] output row block
     const bool euler = P.scheme != 0;
     const double hh = euler ? P.h : P.hh;  // the weight of F in a defect row
-    for (int x = threadIdx.x; x < n * (n + m); x += BS) {
-        const int i = x / (n + m), j = x - i * (n + m);
-        cf[x] = -hh * (j < n ? P.A[i * n + j] : P.B[i * m + (j - n)]);
-    }
-    for (int x = threadIdx.x; x < n; x += BS) gs[x] = -hh * P.gam[x];
+    // every global load is issued here, before the row loop
     for (int x = threadIdx.x; x < n * W; x += BS) {
         const int j = x / W, u = x - j * W;
         const int64_t k = k0 + u;
@@ -225,53 +289,21 @@ __device__ __forceinline__ void kkt_defect_tile(const KP &P, const KKTLayout &Lo
         xs[x] = v;
         cs[x] = cos(v);
     }
-    // every global load is issued here, before the per-component loop, so no
-    // wavefront stalls on memory between that loop's barriers
     for (int x = threadIdx.x; x < n * KT; x += BS) {
         const int i = x >> LG, kk = x & (KT - 1);
         rg[x] = (reg && kk < kn) ? reg[nvar + i * N + k0 + kk] : 0.0;
     }
+    for (int x = threadIdx.x; x < n * (n + m); x += BS) {
+        const int i = x / (n + m), j = x - i * (n + m);
+        cf[x] = -hh * (j < n ? P.A[i * n + j] : P.B[i * m + (j - n)]);
+    }
+    for (int x = threadIdx.x; x < n; x += BS) gs[x] = -hh * P.gam[x];
     __syncthreads();
     const int64_t cons_start = kkt_cons_start(P, Lo);
     for (int i = 0; i < n; i++) {
-        // slot t of the tile's rows, interval fastest: 16 lanes share t, so
-        // a wavefront covers four slots; its coefficients come from LDS
         for (int w = threadIdx.x; w < T1 << LG; w += BS) {
             const int t = w >> LG, kk = w & (KT - 1);
-            if (kk >= kn) continue;
-            double v;
-            if (euler) {
-                // row i: X_0..X_i at k, X_i at k+1, X_{i+1}..X_{n-1} at k, U at k
-                if (t == i + 1) {
-                    v = 1.0;
-                } else if (t <= n) {
-                    const int j = t <= i ? t : t - 1;
-                    const int jn = (j + 1 == n) ? 0 : j + 1;
-                    const int jp = (j == 0) ? n - 1 : j - 1;
-                    v = cf[i * (n + m) + j] * cs[j * W + kk];
-                    if (i == j) v += gs[j] * xs[jn * W + kk] - 1.0;
-                    if (i == jp) v += gs[jp] * xs[jp * W + kk];
-                } else if (t < T) {
-                    v = cf[i * (n + m) + n + (t - n - 1)];
-                } else {
-                    v = rg[(i << LG) + kk];
-                }
-            } else if (t < 2 * n) {
-                const int j = t >> 1, s = t & 1, u = kk + s;
-                const int jn = (j + 1 == n) ? 0 : j + 1;
-                const int jp = (j == 0) ? n - 1 : j - 1;
-                v = cf[i * (n + m) + j] * cs[j * W + u];
-                if (i == j) {
-                    const double dg = gs[j] * xs[jn * W + u];
-                    v += s ? dg + 1.0 : dg - 1.0;
-                }
-                if (i == jp) v += gs[jp] * xs[jp * W + u];
-            } else if (t < T) {
-                v = cf[i * (n + m) + n + ((t - 2 * n) >> 1)];
-            } else {
-                v = rg[(i << LG) + kk];
-            }
-            tile[kk * T1 + t] = v;
+            if (kk < kn) tile[kk * T1 + t] = defect_entry(i, t, kk, n, m, T, W, KT, euler, cf, gs, xs, cs, rg);
         }
         __syncthreads();
         double *out = kkt + cons_start + (i * N + k0) * T1;

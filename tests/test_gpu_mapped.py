@@ -1,5 +1,6 @@
 """GPU parity of the KKT assembly through slot maps (ocp_assemble_kkt_mapped,
-with and without a plan from ocp_mapped_plan) against the oracle's slot-map
+with and without a plan from ocp_mapped_plan, with the handle's own cached
+plan, and with a plan made from other maps) against the oracle's slot-map
 assembly, bit for bit: under the node-grouped
 fill-reducing ordering (every tile staged), under a random ordering (every
 tile falls back to direct stores) and under the natural ordering (where it
@@ -146,3 +147,48 @@ def test_mapped_assembly_large(ocp):
     want = oracle.assemble_mapped(rp2[-1], dg2, pj2, jv.cpu().numpy(), ph2, hv.cpu().numpy(), None)
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
     prob.close()
+
+
+def test_stale_plan_gives_oracle_values(ocp):
+    """A plan made from other slot maps (another ordering, or the handle's
+    cached plan when new maps reuse the old addresses) is caught per tile:
+    the values are still the oracle's, bit for bit."""
+    dev = torch.device("cuda", 0)
+    for N, n, m, scheme, bnd in [(300, 5, 3, 0, 2), (1000, 16, 8, 1, 1)]:
+        _say(f"[mapped stale plan] N={N} n={n} m={m}")
+        inst = synth.make_instance(N, n, m, seed=34, scheme=scheme, bnd=bnd)
+        prob = ocp.Problem.from_instance(inst, dev)
+        z, y = _dev(inst.z, inst.y)
+        jv, hv = prob.jac(z), prob.hess(z, y, 1.0)
+        rp, ci, pj, ph = ocp.kkt_pattern(N, n, m, scheme=scheme, boundary=bnd)
+        dim = len(rp) - 1
+        reg = np.random.default_rng(5).normal(size=dim)
+        stage = ocp.stage_order(N, n, m, scheme, bnd)
+        rng = np.random.default_rng(6)
+        # the stage order with its node runs shuffled: still node-grouped, but
+        # every tile's range moves, so a plan of the stage order is stale
+        shuffled = stage.copy()
+        swap = rng.choice(dim, size=dim // 50, replace=False)
+        shuffled[np.sort(swap)] = shuffled[swap]
+        mapsA = ocp.kkt_permute(rp, ci, pj, ph, stage)
+        mapsB = ocp.kkt_permute(rp, ci, pj, ph, shuffled)
+        dA = _dev(*mapsA[2:5])
+        planA = prob.mapped_plan(*dA)
+        dB = _dev(*mapsB[2:5])
+        want = oracle.assemble_mapped(mapsB[0][-1], mapsB[4], mapsB[2], jv.cpu().numpy(), mapsB[3],
+                                      hv.cpu().numpy(), reg)
+        got = prob.assemble_kkt_mapped(*dB, jv, hv, _dev(reg)[0], plan=planA).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), "explicit stale plan"
+        # the handle's cached plan: first keyed to A's maps, then B's maps are
+        # written into A's arrays (same addresses, stale plan)
+        prob.assemble_kkt_mapped(*dA, jv, hv, _dev(reg)[0])
+        for a, b in zip(dA, dB):
+            a.copy_(b)
+        got = prob.assemble_kkt_mapped(*dA, jv, hv, _dev(reg)[0]).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), "stale cached plan"
+        # and the cached plan of the right maps
+        got = prob.assemble_kkt_mapped(*dB, jv, hv, _dev(reg)[0]).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), "cached plan"
+        got = prob.assemble_kkt_mapped(*dB, jv, hv, _dev(reg)[0]).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), "cached plan, reused"
+        prob.close()
