@@ -10,7 +10,13 @@ Second order: grad_z L is itself differentiable in (z, y), so
 ``torch.autograd.grad(L, z, create_graph=True)`` followed by a backward with a
 vector v gives the Hessian-vector product (Hessian of L) v for z and J v for y.
 Second derivatives that mix the coefficients (A, B, gamma) are not provided
-and raise.
+and raise, also when only z's second derivative is asked for while A, B or
+gamma require grad (autograd cannot tell the backward which inputs the caller
+wants).  For Hessian-vector products, build the graph with the coefficients
+detached (or not requiring grad), as in::
+
+    gz = lagrangian_grad(prob, z, y, A.detach(), B.detach(), gamma.detach())
+    hv, = torch.autograd.grad(gz, z, v)
 """
 from __future__ import annotations
 

@@ -286,6 +286,23 @@ def test_autograd_gradcheck(ocp, N, n, m, scheme, bnd):
     prob.close()
 
 
+def test_hvp_with_detached_coefficients(ocp):
+    """The documented way to a Hessian-vector product while the coefficients
+    require grad elsewhere: build grad_z L with them detached."""
+    from paper_2510_03932_amd.autograd import lagrangian_grad
+    inst = synth.make_instance(3000, 5, 2, seed=9, scheme=1, bnd=1)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    v = np.random.default_rng(3).normal(size=len(inst.z))
+    gz = lagrangian_grad(prob, z, y, A.detach(), B.detach(), g.detach(), 0.8)
+    (hv,) = torch.autograd.grad(gz, z, torch.from_numpy(v).to(dev))
+    want, mu = oracle.hvp_ex(inst, v, 1, 1, sigma=0.8)
+    check_close(hv.detach().cpu().numpy(), want, mu, what="H v through autograd, detached coefficients")
+    assert A.grad is None and B.grad is None and g.grad is None
+    prob.close()
+
+
 def test_second_order_in_coefficients_raises(ocp):
     from paper_2510_03932_amd.autograd import lagrangian
     inst = synth.make_instance(10, 3, 1, seed=8)
