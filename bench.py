@@ -327,9 +327,40 @@ def batched(torch, ocp, synth, reps=10):
     return out
 
 
+def _call_times(torch, fn, reps):
+    """(eager ms, graph ms) per call: `reps` calls issued from Python between
+    two HIP events, then the same `reps` calls captured in one HIP graph and
+    replayed.  At small sizes the eager figure is bounded by Python's
+    per-call dispatch (ctypes, argument checks); the graph figure is the
+    device's time per call."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    eager = e0.elapsed_time(e1) / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph = e0.elapsed_time(e1) / reps
+    del g
+    return eager, graph
+
+
 def differentiation(torch, ocp, synth, reps=20):
     """The differentiation workload: N = 2e5, n = 8, m = 4.  Each Lagrangian
-    entry point timed on its own (HIP events, mean of `reps`), then one
+    entry point timed on its own (HIP events, mean of `reps`; eager calls and
+    a replayed graph of the same calls, hbm_frac from the latter), then one
     autograd forward + backward of L(z, y) with gradients for z, y, A, B and
     gamma, and one Hessian-vector product."""
     from paper_2510_03932_amd.autograd import lagrangian
@@ -344,27 +375,21 @@ def differentiation(torch, ocp, synth, reps=20):
     f64 = dict(dtype=torch.float64, device=dev)
     L, g, hv = torch.empty(1, **f64), torch.empty(s["nvar"], **f64), torch.empty(s["nvar"], **f64)
     jv = torch.empty(s["ncon"], **f64)
+    cg = (torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64))
     nx, nv, nc = n * (N + 1), s["nvar"], s["ncon"]
     calls = {
         "lagrangian": (lambda: prob.lagrangian(z, y, 1.0, out=L), 8 * (nv + nc)),
         "lag_grad": (lambda: prob.lag_grad(z, y, 1.0, out=g), 8 * (2 * nv + nc)),
         "hvp": (lambda: prob.hvp(z, y, v, 1.0, out=hv), 8 * (nx + nc + 2 * nv)),
         "jvp": (lambda: prob.jvp(z, v, out=jv), 8 * (nx + nv + nc)),
-        "coef_grad": (lambda: prob.coef_grad(z, y), 8 * (nv + nc)),
+        "coef_grad": (lambda: prob.coef_grad(z, y, out=cg), 8 * (nv + nc)),
     }
     out = {"workload": f"N={N} n={n} m={m}, seed 0"}
     for name, (fn, nbytes) in calls.items():
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name] = {"ms": round(ms, 4), "bytes": nbytes,
-                     "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+        ms, gms = _call_times(torch, fn, reps)
+        out[name] = {"ms": round(ms, 4), "graph_ms": round(gms, 4), "bytes": nbytes,
+                     "hbm_frac": round(nbytes / (gms * 1e-3) / HBM_PEAK, 4),
+                     "eager_hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
     leaf = lambda a: torch.from_numpy(np.array(a)).to(dev).requires_grad_(True)
     zt, yt, At, Bt, gt = (leaf(a) for a in (inst.z, inst.y, inst.A, inst.B, inst.gamma))
 
@@ -400,17 +425,10 @@ def differentiation(torch, ocp, synth, reps=20):
     }
     qout = {"workload": f"quadrotor, x(0) rows, N={q.N}, seed 0"}
     for name, (fn, nbytes) in qcalls.items():
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        qout[name] = {"ms": round(ms, 4), "bytes": nbytes,
-                      "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+        ms, gms = _call_times(torch, fn, reps)
+        qout[name] = {"ms": round(ms, 4), "graph_ms": round(gms, 4), "bytes": nbytes,
+                      "hbm_frac": round(nbytes / (gms * 1e-3) / HBM_PEAK, 4),
+                      "eager_hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
     qp.close()
     out["quadrotor"] = qout
     return out

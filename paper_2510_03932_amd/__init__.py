@@ -504,17 +504,25 @@ class Problem:
         _check(lib().ocp_eval_jvp(self._h, zp, vp, op, self._stream()), "ocp_eval_jvp")
         return out
 
-    def coef_grad(self, z, y, noalloc=False):
+    def coef_grad(self, z, y, noalloc=False, out=None):
         """(dL/dA (n, n), dL/dB (n, m), dL/dgamma (n,)) as device tensors.
         noalloc=True calls the allocation-free entry point (its partial sums
         in the library's fixed scratch array instead of the handle's
-        workspace; bitwise the same result)."""
+        workspace; bitwise the same result).  out: optional (gA, gB, gamma)
+        contiguous float64 tensors of n * n, n * m and n elements on the
+        problem's device, written in place and returned."""
         torch = _torch()
         n, m = self.n, self.m
         zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
         yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
-        f64 = dict(dtype=torch.float64, device=self.device)
-        gA, gB, gg = torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64)
+        if out is None:
+            f64 = dict(dtype=torch.float64, device=self.device)
+            gA, gB, gg = torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64)
+        else:
+            gA, gB, gg = out
+            self._dev(gA, n * n, torch.float64, "out[0]")
+            self._dev(gB, n * m, torch.float64, "out[1]")
+            self._dev(gg, n, torch.float64, "out[2]")
         fn = "ocp_eval_coef_grad_noalloc" if noalloc else "ocp_eval_coef_grad"
         _check(getattr(lib(), fn)(self._h, zp, yp, ctypes.c_void_p(gA.data_ptr()),
                                   ctypes.c_void_p(gB.data_ptr()) if m else None,

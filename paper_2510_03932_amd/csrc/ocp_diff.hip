@@ -77,6 +77,13 @@ __global__ __launch_bounds__(kBlock) void lag_partial_kernel(KP P, const double 
     double acc = 0.0;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int64_t k = (int64_t)ch * (kBlock - 1) + tid;
+        // the multipliers of this lane's interval, loaded up front so that
+        // they arrive while the node's dynamics are evaluated (index clamped
+        // into the row; used only for k < N)
+        double yv[NB];
+        const int64_t ky = k < N ? k : N - 1;
+#pragma unroll
+        for (int i = 0; i < NB; i++) yv[i] = y[(int64_t)(i < n ? i : 0) * N + ky];
         double Pk[NB];
         if (k <= N) {
             double x[NB], F[NB];
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void lag_partial_kernel(KP P, const double 
         if (tid < kBlock - 1 && k < N) {
 #pragma unroll
             for (int i = 0; i < NB; i++)
-                if (i < n) acc += y[i * N + k] * (Ms[i][tid + 1] - Pk[i]);
+                if (i < n) acc += yv[i] * (Ms[i][tid + 1] - Pk[i]);
         }
         __syncthreads();
     }
@@ -332,19 +339,23 @@ __global__ __launch_bounds__(kBlock) void bnd_jvp_kernel(KP P, const double *__r
 // matrix cores.  The gamma sums S_i = sum_k yt_i X_i X_p(i) are one per row
 // and are summed on the vector units.
 //
-// Workgroup b takes the chunks of kCoefChunk nodes b, b + G, ...  Per chunk:
-// (1) the lanes stage y and the raw columns [X | U] at the chunk's nodes in
-// LDS: the workgroup is split into kBlock / kCoefChunk parts of one node
-// per lane, each part staging its share of the columns and rows with
-// coalesced loads; (2) each lane adds the gamma terms of its node for the
-// rows of its part; (3) the sines are taken in place, once per
-// entry, spread over all lanes; (4) wave w feeds its kCoefChunk / 4 nodes to
+// Workgroup b takes the chunks of kCoefChunk nodes b, b + G, ...  Per chunk,
+// two phases split by one barrier:
+// (1) staging: the workgroup is split into Q = kBlock / kCoefChunk parts of
+// one node per lane; part h loads columns h, h + Q, h + 2Q, ... of [X | U]
+// (so that every part holds about the same number of state columns) and a
+// run of the rows of y, all loads coalesced and issued together.  The lanes
+// take the sines of their state entries in registers and store sin X | U,
+// the raw X rows (for the gamma terms) and y to LDS;
+// (2) each lane adds the gamma terms X_i X_p(i) yt_i of its node for the
+// rows of its part, and wave w feeds its kCoefChunk / 4 nodes to
 // v_mfma_f64_16x16x4f64, 4 nodes per instruction (lane l supplies row or
 // column l mod 16 at node l / 16 of the step), accumulating every 16 x 16
-// block of the product.  At the end the 4 waves' blocks are added in order in
-// LDS and the entries go to cpart[(i (n+m+1) + col) G + b], col n+m holding
-// the gamma sum.  MB = ceil(n / 16) row blocks, NBK = ceil((n+m) / 16)
-// column blocks.
+// block of the product.
+// At the end the 4 waves' blocks are added in order in LDS and workgroup b
+// writes its n (n+m+1) sums as one contiguous run, cpart[b n (n+m+1) +
+// i (n+m+1) + col] (col n+m: the gamma sum).  MB = ceil(n / 16) row blocks,
+// NBK = ceil((n+m) / 16) column blocks.
 template <int MB, int NBK>
 __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
     KP P, const double *__restrict__ z, const double *__restrict__ y, int G, double *__restrict__ cpart)
@@ -353,11 +364,13 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
     constexpr int Q = kBlock / CH;                               // staging parts (lanes per node)
     constexpr int HR = 16 * MB / Q, HC = 16 * NBK / Q;           // rows and columns per part
     static_assert(kBlock % CH == 0 && CH % 64 == 0 && (16 % Q) == 0, "whole waves per staging part");
-    constexpr int STAGE = (16 * NBK + 16 * MB) * LD, RED = W * MB * NBK * 256;
+    // staging: [sin X | U] (16 NBK rows), raw X (16 MB rows), y (16 MB rows)
+    constexpr int STAGE = (16 * NBK + 32 * MB) * LD, RED = W * MB * NBK * 256;
     __shared__ double sh[STAGE > RED ? STAGE : RED];  // staging area, then the block sums
     __shared__ double gs[W][HR];
     double(*Vl)[LD] = reinterpret_cast<double(*)[LD]>(sh);
-    double(*Yl)[LD] = reinterpret_cast<double(*)[LD]>(sh + 16 * NBK * LD);
+    double(*Xl)[LD] = reinterpret_cast<double(*)[LD]>(sh + 16 * NBK * LD);
+    double(*Yl)[LD] = reinterpret_cast<double(*)[LD]>(sh + (16 * NBK + 16 * MB) * LD);
     const int n = P.n, m = P.m, ncol = n + m + 1;
     // w and h are the same across a wave: readfirstlane lets the compiler
     // keep what derives from them (row and column pointers) in scalar
@@ -375,14 +388,14 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
     double gam[HR];
 #pragma unroll
     for (int rr = 0; rr < HR; rr++) gam[rr] = 0.0;
-    // (1) Staging.  Every load is unconditional, from an index clamped into
-    // its row, and all are issued before the first LDS store, so that they
-    // are in flight together; values past a row's end (and the last chunk's
-    // tail) are scaled to 0 when stored (a multiply, not a select, which the
-    // compiler would turn into a branch per load).  The rows of y are
-    // staged shifted by one slot: Yl[r][s + 1] = y_{r, base + s} (0 from node
-    // N on) and Yl[r][0] = y_{r, base - 1}, so that yt = Yl[r][s + 1] +
-    // Yl[r][s] for the trapezoid.
+    // Every load is unconditional, from an index clamped into its row, and
+    // all are issued before the first LDS store, so that they are in flight
+    // together; values past a row's end (and the last chunk's tail) are
+    // scaled to 0 when stored (a multiply, not a select, which the compiler
+    // would turn into a branch per load).  The rows of y are staged shifted
+    // by one slot: Yl[r][s + 1] = y_{r, base + s} (0 from node N on) and
+    // Yl[r][0] = y_{r, base - 1}, so that yt = Yl[r][s + 1] + Yl[r][s] for
+    // the trapezoid.
     double xv[HC], yv[HR], hv[HR];
     // Each load is a uniform row pointer at the chunk's first node (or at
     // the row's start when the row ends before the chunk) plus a 32-bit lane
@@ -391,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
     auto issue = [&](int64_t b0) {
 #pragma unroll
         for (int jj = 0; jj < HC; jj++) {
-            const int c = HC * h + jj;
+            const int c = Q * jj + h;
             const bool isx = c < n, isu = !isx && c < n + m;
             const double *src = isx ? z + c * N1 : isu ? z + n * N1 + (c - n) * NU : z;
             const int64_t last = isx ? N : isu ? NU - 1 : -1;
@@ -415,9 +428,15 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
         const int64_t k = b0 + slot;
 #pragma unroll
         for (int jj = 0; jj < HC; jj++) {
-            const int c = HC * h + jj;
+            const int c = Q * jj + h;
             const int64_t last = c < n ? N : c < n + m ? NU - 1 : -1;
-            Vl[c][slot] = xv[jj] * (k <= last ? 1.0 : 0.0);
+            const double v = xv[jj] * (k <= last ? 1.0 : 0.0);
+            if (c < n) {
+                Xl[c][slot] = v;
+                Vl[c][slot] = sin(v);
+            } else {
+                Vl[c][slot] = v;
+            }
         }
         const double fr = k < N ? 1.0 : 0.0, fh = b0 >= 1 ? 1.0 : 0.0;
 #pragma unroll
@@ -428,27 +447,23 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
             if (slot == 0) Yl[r][0] = hv[rr] * (fh * live);
         }
     };
+    const double fl = euler ? 0.0 : 1.0;  // weight of the left neighbour
     for (int64_t base = (int64_t)blockIdx.x * CH; base <= N; base += (int64_t)G * CH) {
         issue(base);
         asm volatile("" ::: "memory");  // every load issued before the first store
         stage(base);
         __syncthreads();
-        const double fl = euler ? 0.0 : 1.0;  // weight of the left neighbour
-        // (2) gamma terms X_i X_p(i) yt_i of this lane's node
+        // gamma terms X_i X_p(i) yt_i of this lane's node
 #pragma unroll
         for (int rr = 0; rr < HR; rr++) {
             const int i = HR * h + rr;
-            if (i >= n) break;
-            const int p = (i + 1 == n) ? 0 : i + 1;
-            const double yt = __builtin_fma(fl, Yl[i][slot], Yl[i][slot + 1]);
-            gam[rr] = __builtin_fma(yt, Vl[i][slot] * Vl[p][slot], gam[rr]);
+            if (i < n) {
+                const int p = (i + 1 == n) ? 0 : i + 1;
+                const double yt = __builtin_fma(fl, Yl[i][slot], Yl[i][slot + 1]);
+                gam[rr] = __builtin_fma(yt, Xl[i][slot] * Xl[p][slot], gam[rr]);
+            }
         }
-        __syncthreads();
-        // (3) the sines, spread over all lanes
-#pragma unroll 1
-        for (int e = t; e < n * CH; e += kBlock) Vl[e / CH][e % CH] = sin(Vl[e / CH][e % CH]);
-        __syncthreads();
-        // (4) the contraction
+        // the contraction
 #pragma unroll 2
         for (int st = 0; st < CH / (4 * W); st++) {
             const int s = w * (CH / W) + 4 * st + kq;
@@ -476,11 +491,13 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
             for (int r = 0; r < 4; r++) red[w][mb][cb][(4 * r + kq) * 16 + j16] = acc[mb][cb][r];
 #pragma unroll
     for (int rr = 0; rr < HR; rr++) {
-        if (HR * h + rr >= n) break;
-        const double v = wave_sum(gam[rr]);
-        if (lane == 0) gs[w][rr] = v;
+        if (HR * h + rr < n) {
+            const double v = wave_sum(gam[rr]);
+            if (lane == 0) gs[w][rr] = v;
+        }
     }
     __syncthreads();
+    double *out = cpart + (int64_t)blockIdx.x * n * ncol;
 #pragma unroll
     for (int mb = 0; mb < MB; mb++)
 #pragma unroll
@@ -490,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
             double sum = red[0][mb][cb][t];
 #pragma unroll
             for (int v = 1; v < W; v++) sum += red[v][mb][cb][t];
-            cpart[((int64_t)i * ncol + col) * G + blockIdx.x] = sum;
+            out[i * ncol + col] = sum;
         }
     if (t < n) {
         constexpr int WP = W / Q;  // waves per staging part
@@ -498,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
         double sum = gs[WP * hh][rr];
 #pragma unroll
         for (int v = 1; v < WP; v++) sum += gs[WP * hh + v][rr];
-        cpart[((int64_t)t * ncol + n + m) * G + blockIdx.x] = sum;
+        out[t * ncol + n + m] = sum;
     }
 }
 
@@ -509,10 +526,10 @@ __global__ __launch_bounds__(kBlock) void coef_final_kernel(KP P, const double *
                                                             double *__restrict__ gB,
                                                             double *__restrict__ gg)
 {
-    const int n = P.n, m = P.m, ncol = n + m + 1;
+    const int n = P.n, m = P.m, ncol = n + m + 1, nc = n * ncol;
     const int idx = blockIdx.x;
     double s = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock) s += cpart[(int64_t)idx * G + b];
+    for (int b = threadIdx.x; b < G; b += kBlock) s += cpart[(int64_t)b * nc + idx];
     s = block_sum<kBlock>(s);
     if (threadIdx.x != 0) return;
     const double val = -(P.scheme != 0 ? P.h : P.hh) * s;
