@@ -314,6 +314,47 @@ class Oracle:
         gg, mg = -w * np.sum(Y * PG, axis=1), w * np.sum(Ya * PGm, axis=1)
         return (gA, gB, gg), (mA, mB, mg)
 
+    def coef_mixed_ex(self, inst, v, scheme=0, bnd=0, y=None):
+        """The derivative of (dL/dA, dL/dB, dL/dgamma) along the direction v
+        of z -- the mixed second derivatives d2L/(dtheta dz) contracted with
+        v -- and their mu arrays.  With V_X and V_U the state and control
+        parts of v (laid out as in z), C = cos X * V_X and Q_i = V_X,i X_p +
+        X_i V_X,p (p = (i+1) mod n), it is coef_grad_ex with sin X, U and
+        X_i X_p replaced by their derivatives along v, C, V_U and Q:
+          trapezoidal  -h/2 sum_k y_ik (C_jk + C_j,k+1), -h/2 sum_k y_ik (V_U,lk + V_U,l,k+1),
+                       -h/2 sum_k y_ik (Q_ik + Q_i,k+1);
+          Euler        -h sum_k y_ik C_jk, -h sum_k y_ik V_U,lk, -h sum_k y_ik Q_ik.
+        Boundary rows do not depend on the coefficients (paper Sec. 8 names
+        differentiable programming as future work; the defects follow Sec. 3)."""
+        N, n, m = inst.N, inst.n, inst.m
+        y = _d(inst.y if y is None else y)
+        v = _d(v)
+        NU = N + 1 if scheme == 0 else N
+        X = _d(inst.z[:n * (N + 1)]).reshape(n, N + 1)
+        VX = v[:n * (N + 1)].reshape(n, N + 1)
+        VU = v[n * (N + 1):].reshape(m, NU)
+        Y = y[:n * N].reshape(n, N)
+        p = (np.arange(n) + 1) % n
+        C = np.cos(X) * VX
+        Q = VX * X[p] + X * VX[p]
+        Cm = np.abs(np.cos(X) * VX)
+        Qm = np.abs(VX * X[p]) + np.abs(X * VX[p])
+        if scheme == 0:
+            w = 0.5 * (1.0 / N)
+            CA, VB, QG = C[:, :N] + C[:, 1:], VU[:, :N] + VU[:, 1:], Q[:, :N] + Q[:, 1:]
+            CAm = Cm[:, :N] + Cm[:, 1:]
+            VBm = np.abs(VU[:, :N]) + np.abs(VU[:, 1:])
+            QGm = Qm[:, :N] + Qm[:, 1:]
+        else:
+            w = 1.0 / N
+            CA, VB, QG = C[:, :N], VU, Q[:, :N]
+            CAm, VBm, QGm = Cm[:, :N], np.abs(VU), Qm[:, :N]
+        Ya = np.abs(Y)
+        gA, mA = -w * (Y @ CA.T), w * (Ya @ CAm.T)
+        gB, mB = -w * (Y @ VB.T), w * (Ya @ VBm.T)
+        gg, mg = -w * np.sum(Y * QG, axis=1), w * np.sum(Ya * QGm, axis=1)
+        return (gA, gB, gg), (mA, mB, mg)
+
     # ---- schemes (0 trapezoidal, 1 forward Euler) and boundary rows --------
     def sizes_ex(self, N, n, m, scheme=0, bnd=0) -> dict:
         out = np.zeros(10, np.int64)

@@ -85,6 +85,38 @@ def _coef_mutant(kind):
     return coef_grad_ex
 
 
+def _mixed_mutant(kind):
+    """A copy of coef_mixed_ex with one planted mistake."""
+    def coef_mixed_ex(self, inst, v, scheme=0, bnd=0, y=None):
+        N, n, m = inst.N, inst.n, inst.m
+        y = np.asarray(inst.y if y is None else y, dtype=float)
+        v = np.asarray(v, dtype=float)
+        NU = N + 1 if scheme == 0 else N
+        Xv = np.asarray(inst.z[:n * (N + 1)], dtype=float).reshape(n, N + 1)
+        VX = v[:n * (N + 1)].reshape(n, N + 1)
+        VU = v[n * (N + 1):].reshape(m, NU)
+        Y = y[:n * N].reshape(n, N)
+        p = (np.arange(n) + 1) % n
+        C = (np.sin(Xv) if kind == "sine" else np.cos(Xv)) * VX
+        Q = VX * Xv[p] if kind == "one product term" else VX * Xv[p] + Xv * VX[p]
+        if scheme == 0:
+            w = 0.5 * (1.0 / N)
+            CA = C[:, 1:] if kind == "right node only" else C[:, :N] + C[:, 1:]
+            VB, QG = VU[:, :N] + VU[:, 1:], Q[:, :N] + Q[:, 1:]
+        else:
+            w = 1.0 / N
+            CA, VB, QG = C[:, :N], VU, Q[:, :N]
+            if kind == "euler next node":
+                CA = C[:, 1:]
+        Ya = np.abs(Y)
+        big = lambda a: w * (Ya @ np.abs(a).T) + 1e-300
+        gA, mA = -w * (Y @ CA.T), big(CA)
+        gB, mB = -w * (Y @ VB.T), big(VB)
+        gg, mg = -w * np.sum(Y * QG, axis=1), w * np.sum(Ya * np.abs(QG), axis=1) + 1e-300
+        return (gA, gB, gg), (mA, mB, mg)
+    return coef_mixed_ex
+
+
 # (name, attribute of the oracle module or of its Oracle class, replacement)
 MUTATIONS = [
     ("grad_z L without sigma", "_grad_plus_jt_y", _jt_y_no_sigma),
@@ -96,6 +128,10 @@ MUTATIONS = [
     ("coefficient gradient without the right node", "Oracle.coef_grad_ex", _coef_mutant("trapezoid right node")),
     ("coefficient gradient with the trapezoid weight under Euler", "Oracle.coef_grad_ex", _coef_mutant("euler weight")),
     ("coefficient gradient with gamma's own state as partner", "Oracle.coef_grad_ex", _coef_mutant("gamma partner")),
+    ("mixed derivative with sin for cos", "Oracle.coef_mixed_ex", _mixed_mutant("sine")),
+    ("mixed derivative with one product-rule term", "Oracle.coef_mixed_ex", _mixed_mutant("one product term")),
+    ("mixed derivative without the left node", "Oracle.coef_mixed_ex", _mixed_mutant("right node only")),
+    ("mixed derivative at the next node under Euler", "Oracle.coef_mixed_ex", _mixed_mutant("euler next node")),
 ]
 
 # pins, each a call that raises when the oracle is wrong
@@ -107,6 +143,8 @@ PINS = [
     lambda orc: X.test_hvp_ex_mixed_difference(orc, 2, 3, 1, 1, 0),
     lambda orc: X.test_coef_grad_ex_complex_step(orc, 5, 3, 2, 0, 0),
     lambda orc: X.test_coef_grad_ex_complex_step(orc, 5, 3, 2, 1, 2),
+    lambda orc: X.test_coef_mixed_ex_high_precision_differences(orc, 4, 3, 2, 0, 1),
+    lambda orc: X.test_coef_mixed_ex_high_precision_differences(orc, 4, 3, 2, 1, 0),
     lambda orc: X.test_quad_lag_grad_complex_step(orc, 2, 1),
     lambda orc: X.test_quad_hvp_mixed_difference(orc, 2, 1),
     lambda orc: X.test_quad_jvp_complex_step(orc, 2, 1),

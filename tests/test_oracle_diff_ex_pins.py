@@ -128,6 +128,75 @@ def test_coef_grad_ex_complex_step(orc, N, n, m, scheme, bnd):
         assert abs(gg[i] - want) <= 1e-13 * mg[i] + 1e-300, ("gamma", i)
 
 
+@pytest.mark.parametrize("scheme,bnd", CASES)
+@pytest.mark.parametrize("N,n,m", [(4, 3, 2), (3, 1, 1), (3, 2, 0)])
+def test_coef_mixed_ex_high_precision_differences(orc, N, n, m, scheme, bnd):
+    """d/dtheta_p (v . grad_z L) from 50-digit evaluations of the definition
+    module: L is affine in theta, so L(theta + e_p) - L(theta) is the
+    coefficient's derivative g_p exactly, and the central difference of g_p
+    along v at step 1e-20 is exact to far below double rounding."""
+    import mpmath
+    mpmath.mp.dps = 50
+    inst = _inst(N, n, m, 260 + 7 * N + n, scheme, bnd)
+    v = np.random.default_rng(31 + N).normal(size=len(inst.z))
+    (gA, gB, gg), (mA, mB, mg) = orc.coef_mixed_ex(inst, v, scheme, bnd)
+    mp = mpmath.mpf
+    A, B, g, q, r = defn.as_lists(inst)
+    cv = lambda x: [mp(float(t)) for t in x]
+    eps = mp("1e-20")
+    zp = [mp(float(a)) + eps * mp(float(b)) for a, b in zip(inst.z, v)]
+    zm = [mp(float(a)) - eps * mp(float(b)) for a, b in zip(inst.z, v)]
+    yy, qq, rr = cv(inst.y), cv(q), cv(r)
+    A0, B0, g0 = [cv(a) for a in A], [cv(b) for b in B], cv(g)
+
+    def L(z, A_, B_, g_):
+        return defn.lagrangian_ex(z, yy, mp(float(inst.sigma)), N, n, m, A_, B_, g_, qq, rr, scheme, bnd,
+                                  sin=mpmath.sin, dt=mp(1) / N)
+
+    base = L(zp, A0, B0, g0) - L(zm, A0, B0, g0)
+
+    def want(A_, B_, g_):
+        return float((L(zp, A_, B_, g_) - L(zm, A_, B_, g_) - base) / (2 * eps))
+
+    for i in range(n):
+        for j in range(n):
+            A1 = [row[:] for row in A0]
+            A1[i][j] += 1
+            assert abs(gA[i, j] - want(A1, B0, g0)) <= 1e-13 * mA[i, j] + 1e-300, ("A", i, j)
+        for l in range(m):
+            B1 = [row[:] for row in B0]
+            B1[i][l] += 1
+            assert abs(gB[i, l] - want(A0, B1, g0)) <= 1e-13 * mB[i, l] + 1e-300, ("B", i, l)
+        g1 = g0[:]
+        g1[i] += 1
+        assert abs(gg[i] - want(A0, B0, g1)) <= 1e-13 * mg[i] + 1e-300, ("gamma", i)
+
+
+def test_coef_mixed_ex_linear_in_v_and_zero_without_state_direction(orc):
+    """The mixed derivative is linear in v; a direction that moves only the
+    controls leaves the A and gamma parts zero (they depend on the states
+    alone) and gives B's part as the coefficient gradient of a problem whose
+    controls are v's control part (dL/dB is linear in U)."""
+    inst = _inst(30, 4, 2, 271, 0, 1)
+    rng = np.random.default_rng(8)
+    v1, v2 = rng.normal(size=len(inst.z)), rng.normal(size=len(inst.z))
+    (a1, b1, g1), (ma1, mb1, mg1) = orc.coef_mixed_ex(inst, v1, 0, 1)
+    (a2, b2, g2), (ma2, mb2, mg2) = orc.coef_mixed_ex(inst, v2, 0, 1)
+    (a3, b3, g3), _ = orc.coef_mixed_ex(inst, 2.0 * v1 - 3.0 * v2, 0, 1)
+    check_close(a3.ravel(), (2 * a1 - 3 * a2).ravel(), (2 * ma1 + 3 * ma2).ravel(), rel=1e-13, what="A linear")
+    check_close(b3.ravel(), (2 * b1 - 3 * b2).ravel(), (2 * mb1 + 3 * mb2).ravel(), rel=1e-13, what="B linear")
+    check_close(g3, 2 * g1 - 3 * g2, 2 * mg1 + 3 * mg2, rel=1e-13, what="gamma linear")
+    nx = inst.n * (inst.N + 1)
+    vu = np.zeros(len(inst.z))
+    vu[nx:] = v1[nx:]
+    (a, b, g), _ = orc.coef_mixed_ex(inst, vu, 0, 1)
+    assert np.all(a == 0.0) and np.all(g == 0.0)
+    swapped = types.SimpleNamespace(**{k: getattr(inst, k) for k in ("N", "n", "m", "y", "A", "B", "gamma")})
+    swapped.z = np.concatenate([np.asarray(inst.z[:nx], dtype=float), vu[nx:]])
+    (_, bw, _), (_, mbw, _) = orc.coef_grad_ex(swapped, 0, 1)
+    check_close(b.ravel(), bw.ravel(), mbw.ravel(), rel=1e-13, what="B part = dL/dB with U := V_U")
+
+
 @pytest.mark.parametrize("N,n,m", [(300, 4, 2), (1, 1, 0), (64, 6, 3)])
 def test_trapezoidal_composites_equal_c_oracle(orc, N, n, m):
     """Without boundary rows the trapezoidal composites and the C oracle's
