@@ -383,6 +383,7 @@ def differentiation(torch, ocp, synth, reps=20):
         "hvp": (lambda: prob.hvp(z, y, v, 1.0, out=hv), 8 * (nx + nc + 2 * nv)),
         "jvp": (lambda: prob.jvp(z, v, out=jv), 8 * (nx + nv + nc)),
         "coef_grad": (lambda: prob.coef_grad(z, y, out=cg), 8 * (nv + nc)),
+        "coef_mixed": (lambda: prob.coef_mixed(z, y, v, out=cg), 8 * (nx + nv + nc)),
     }
     out = {"workload": f"N={N} n={n} m={m}, seed 0"}
     for name, (fn, nbytes) in calls.items():

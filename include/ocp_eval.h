@@ -311,8 +311,8 @@ int ocp_mapped_plan(const ocp_problem *p, const int32_t *perm_j, const int32_t *
  * arrays are device pointers; every sum over nodes uses a fixed reduction
  * order (bitwise reproducible).  A quadrotor handle is accepted by
  * ocp_eval_lagrangian, ocp_eval_lag_grad, ocp_eval_hvp and ocp_eval_jvp (its
- * own layouts); the model has no coefficient arrays, so ocp_set_coefficients
- * and ocp_eval_coef_grad reject it (OCP_ERR_ARG).
+ * own layouts); the model has no coefficient arrays, so ocp_set_coefficients,
+ * ocp_eval_coef_grad and ocp_eval_coef_mixed reject it (OCP_ERR_ARG).
  * ------------------------------------------------------------------------- */
 
 /* Replace the handle's A (n x n), B (n x m; NULL when m = 0) and gamma (n)
@@ -347,6 +347,20 @@ int ocp_eval_jvp(const ocp_problem *p, const double *z, const double *v, double 
  * calls on one handle race). */
 int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA,
                        double *gB, double *ggamma, hipStream_t stream);
+
+/* The derivative of the coefficient gradient along a direction v of z (nvar
+ * doubles, the layout of z): the mixed second derivatives of L contracted
+ * with v, d/dtheta (v^T grad_z L) for theta = (A, B, gamma), into gA (n x n
+ * row-major), gB (n x m; may be NULL when m = 0) and ggamma (n).  With
+ * C = cos X * v_X and Q_i = v_X,i X_p(i) + X_i v_X,p(i) (p(i) = (i+1) mod n)
+ * these are the sums of ocp_eval_coef_grad with sin X, U and X_i X_p(i)
+ * replaced by C, v_U and Q -- what a Hessian-vector product through the
+ * Lagrangian gradient returns for the coefficients (differentiable
+ * programming, named as future work in Sec. 8; the defects of Sec. 3).
+ * Same workspace and reduction order rules as ocp_eval_coef_grad.
+ * Errors: OCP_ERR_ARG (null array, quadrotor handle), OCP_ERR_HIP. */
+int ocp_eval_coef_mixed(const ocp_problem *p, const double *z, const double *y, const double *v, double *gA,
+                        double *gB, double *ggamma, hipStream_t stream);
 
 /* Allocation-free ocp_eval_coef_grad, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that

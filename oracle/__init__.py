@@ -601,6 +601,7 @@ lag_grad_ex = DEFAULT.lag_grad_ex
 hvp_ex = DEFAULT.hvp_ex
 jvp_ex = DEFAULT.jvp_ex
 coef_grad_ex = DEFAULT.coef_grad_ex
+coef_mixed_ex = DEFAULT.coef_mixed_ex
 sizes_ex = DEFAULT.sizes_ex
 obj_ex = DEFAULT.obj_ex
 grad_ex = DEFAULT.grad_ex

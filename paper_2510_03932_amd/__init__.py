@@ -131,6 +131,7 @@ def lib():
         L.ocp_eval_jvp.argtypes = [vp, vp, vp, vp, vp]
         L.ocp_eval_coef_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ocp_eval_coef_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_eval_coef_mixed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_batch_create.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.ocp_batch_destroy.argtypes = [vp]
         L.ocp_batch_destroy.restype = None
@@ -527,6 +528,29 @@ class Problem:
         _check(getattr(lib(), fn)(self._h, zp, yp, ctypes.c_void_p(gA.data_ptr()),
                                   ctypes.c_void_p(gB.data_ptr()) if m else None,
                                   ctypes.c_void_p(gg.data_ptr()), self._stream()), fn)
+        return gA, gB, gg
+
+    def coef_mixed(self, z, y, v, out=None):
+        """The derivative of coef_grad(z, y) along the direction v of z (nvar
+        doubles): d/d(A, B, gamma) of v^T grad_z L, as (n, n), (n, m) and (n,)
+        device tensors (or written into out, as for coef_grad)."""
+        torch = _torch()
+        n, m = self.n, self.m
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        vp_ = self._dev(v, self.sizes["nvar"], torch.float64, "v")
+        if out is None:
+            f64 = dict(dtype=torch.float64, device=self.device)
+            gA, gB, gg = torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64)
+        else:
+            gA, gB, gg = out
+            self._dev(gA, n * n, torch.float64, "out[0]")
+            self._dev(gB, n * m, torch.float64, "out[1]")
+            self._dev(gg, n, torch.float64, "out[2]")
+        _check(lib().ocp_eval_coef_mixed(self._h, zp, yp, vp_, ctypes.c_void_p(gA.data_ptr()),
+                                          ctypes.c_void_p(gB.data_ptr()) if m else None,
+                                          ctypes.c_void_p(gg.data_ptr()), self._stream()),
+               "ocp_eval_coef_mixed")
         return gA, gB, gg
 
 

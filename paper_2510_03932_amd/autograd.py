@@ -6,17 +6,20 @@ ABI); PyTorch supplies the tensors, streams and the autograd graph.
     L = lagrangian(prob, z, y, A, B, gamma, sigma)       # 0-dim tensor
     L.backward()   # z.grad = grad_z L, y.grad = c(z), A.grad = dL/dA, ...
 
-Second order: grad_z L is itself differentiable in (z, y), so
+Second order: grad_z L is itself differentiable in (z, y, A, B, gamma), so
 ``torch.autograd.grad(L, z, create_graph=True)`` followed by a backward with a
-vector v gives the Hessian-vector product (Hessian of L) v for z and J v for y.
-Second derivatives that mix the coefficients (A, B, gamma) are not provided
-and raise, also when only z's second derivative is asked for while A, B or
-gamma require grad (autograd cannot tell the backward which inputs the caller
-wants).  For Hessian-vector products, build the graph with the coefficients
-detached (or not requiring grad), as in::
+vector v gives the Hessian-vector product (Hessian of L) v for z, J v for y
+and the mixed second derivatives d/dtheta (v^T grad_z L) for the
+coefficients theta = (A, B, gamma) (library call ocp_eval_coef_mixed)::
 
-    gz = lagrangian_grad(prob, z, y, A.detach(), B.detach(), gamma.detach())
-    hv, = torch.autograd.grad(gz, z, v)
+    gz = lagrangian_grad(prob, z, y, A, B, gamma)
+    hv, hA, hB, hg = torch.autograd.grad(gz, (z, A, B, gamma), v)
+
+The coefficient gradient dL/dtheta is differentiable only to first order:
+differentiating it again (``torch.autograd.grad(L, A, create_graph=True)``
+followed by a backward) raises NotImplementedError.  L is affine in theta,
+so the second derivatives in theta alone are zero; the ones that mix theta
+with z are reached through grad_z L as above.
 """
 from __future__ import annotations
 
@@ -40,7 +43,8 @@ def _coefficients(prob, A, B, gamma):
 
 class _LagGrad(torch.autograd.Function):
     """grad_z L as a function of (z, y, A, B, gamma); its backward gives
-    (Hessian of L) v for z and J v for y."""
+    (Hessian of L) v for z, J v for y and d/dtheta (v^T grad_z L) for the
+    coefficients."""
 
     @staticmethod
     def forward(ctx, z, y, A, B, gamma, sigma, prob):
@@ -53,17 +57,17 @@ class _LagGrad(torch.autograd.Function):
     def backward(ctx, v):
         z, y, A, B, gamma = ctx.saved_tensors
         prob = ctx.prob
-        if any(ctx.needs_input_grad[2:5]):
-            raise NotImplementedError("second derivatives in the dynamics coefficients "
-                                      "(A, B, gamma) are not provided")
         _coefficients(prob, A, B, gamma)
-        v = v.contiguous()
-        gz = gy = None
+        v = v.detach().contiguous()
+        zd, yd = z.detach().contiguous(), y.detach().contiguous()
+        gz = gy = gA = gB = gg = None
         if ctx.needs_input_grad[0]:
-            gz = prob.hvp(z.detach().contiguous(), y.detach().contiguous(), v, ctx.sigma)
+            gz = prob.hvp(zd, yd, v, ctx.sigma)
         if ctx.needs_input_grad[1]:
-            gy = prob.jvp(z.detach().contiguous(), v)
-        return gz, gy, None, None, None, None, None
+            gy = prob.jvp(zd, v)
+        if any(ctx.needs_input_grad[2:5]):
+            gA, gB, gg = prob.coef_mixed(zd, yd, v)
+        return gz, gy, gA, gB, gg, None, None
 
 
 class _Cons(torch.autograd.Function):
@@ -94,7 +98,8 @@ class _Cons(torch.autograd.Function):
 
 
 class _CoefGrad(torch.autograd.Function):
-    """dL/d(A, B, gamma) as a function of (z, y); second derivatives raise."""
+    """dL/d(A, B, gamma) as a function of (z, y); differentiating it again
+    raises (the mixed terms are available through grad_z L instead)."""
 
     @staticmethod
     def forward(ctx, z, y, A, B, gamma, prob):
@@ -103,8 +108,9 @@ class _CoefGrad(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, *grads):
-        raise NotImplementedError("second derivatives in the dynamics coefficients "
-                                  "(A, B, gamma) are not provided")
+        raise NotImplementedError("the coefficient gradient dL/d(A, B, gamma) is differentiable only "
+                                  "to first order; reach the mixed second derivatives through "
+                                  "lagrangian_grad (grad_z L) instead")
 
 
 class _Lagrangian(torch.autograd.Function):
@@ -159,7 +165,7 @@ def lagrangian(prob, z, y, A=None, B=None, gamma=None, sigma: float = 1.0):
 
 
 def lagrangian_grad(prob, z, y, A=None, B=None, gamma=None, sigma: float = 1.0):
-    """grad_z L as a differentiable function of (z, y)."""
+    """grad_z L as a differentiable function of (z, y, A, B, gamma)."""
     return _LagGrad.apply(z, y, A, B, gamma, float(sigma), prob)
 
 

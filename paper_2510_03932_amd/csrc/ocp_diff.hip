@@ -356,21 +356,30 @@ __global__ __launch_bounds__(kBlock) void bnd_jvp_kernel(KP P, const double *__r
 // writes its n (n+m+1) sums as one contiguous run, cpart[b n (n+m+1) +
 // i (n+m+1) + col] (col n+m: the gamma sum).  MB = ceil(n / 16) row blocks,
 // NBK = ceil((n+m) / 16) column blocks.
-template <int MB, int NBK>
+//
+// MIXED: the derivative of the same sums along a direction v of z (the mixed
+// second derivatives d2L/(dtheta dz) v): the columns become [cos X * V_X |
+// V_U] and the gamma terms yt_i (V_X,i X_p(i) + X_i V_X,p(i)); the parts load
+// the state rows of X and the rows of v (the control rows of z are not
+// needed), and stage the raw V_X rows beside the raw X rows.
+template <int MB, int NBK, bool MIXED>
 __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
-    KP P, const double *__restrict__ z, const double *__restrict__ y, int G, double *__restrict__ cpart)
+    KP P, const double *__restrict__ z, const double *__restrict__ y, const double *__restrict__ v, int G,
+    double *__restrict__ cpart)
 {
     constexpr int W = kBlock / 64, CH = kCoefChunk, LD = CH + 2;  // LD: row stride, spreads LDS banks
     constexpr int Q = kBlock / CH;                               // staging parts (lanes per node)
     constexpr int HR = 16 * MB / Q, HC = 16 * NBK / Q;           // rows and columns per part
     static_assert(kBlock % CH == 0 && CH % 64 == 0 && (16 % Q) == 0, "whole waves per staging part");
-    // staging: [sin X | U] (16 NBK rows), raw X (16 MB rows), y (16 MB rows)
-    constexpr int STAGE = (16 * NBK + 32 * MB) * LD, RED = W * MB * NBK * 256;
+    // staging: [sin X | U] (16 NBK rows), raw X (16 MB rows), y (16 MB rows);
+    // MIXED: raw V_X (16 MB rows) after y
+    constexpr int STAGE = (16 * NBK + (MIXED ? 48 : 32) * MB) * LD, RED = W * MB * NBK * 256;
     __shared__ double sh[STAGE > RED ? STAGE : RED];  // staging area, then the block sums
     __shared__ double gs[W][HR];
     double(*Vl)[LD] = reinterpret_cast<double(*)[LD]>(sh);
     double(*Xl)[LD] = reinterpret_cast<double(*)[LD]>(sh + 16 * NBK * LD);
     double(*Yl)[LD] = reinterpret_cast<double(*)[LD]>(sh + (16 * NBK + 16 * MB) * LD);
+    double(*Wl)[LD] = reinterpret_cast<double(*)[LD]>(sh + (16 * NBK + 32 * MB) * LD);
     const int n = P.n, m = P.m, ncol = n + m + 1;
     // w and h are the same across a wave: readfirstlane lets the compiler
     // keep what derives from them (row and column pointers) in scalar
@@ -396,22 +405,31 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
     // by one slot: Yl[r][s + 1] = y_{r, base + s} (0 from node N on) and
     // Yl[r][0] = y_{r, base - 1}, so that yt = Yl[r][s + 1] + Yl[r][s] for
     // the trapezoid.
-    double xv[HC], yv[HR], hv[HR];
+    double xv[HC], vv[MIXED ? HC : 1], yv[HR], hv[HR];
     // Each load is a uniform row pointer at the chunk's first node (or at
     // the row's start when the row ends before the chunk) plus a 32-bit lane
     // offset clamped to the row's last node, so that no per-lane 64-bit
     // address has to stay live across the chunk loop.
+    auto row_load = [&](const double *src, int64_t last, int64_t b0) {
+        const int64_t span = last - b0;  // lanes slot <= span hold nodes of the row
+        const double *pb = span >= 0 ? src + b0 : src;
+        const uint32_t lim = span >= 0 ? (uint32_t)(span < CH - 1 ? span : CH - 1) : 0u;
+        return pb[(uint32_t)slot < lim ? (uint32_t)slot : lim];
+    };
     auto issue = [&](int64_t b0) {
 #pragma unroll
         for (int jj = 0; jj < HC; jj++) {
             const int c = Q * jj + h;
             const bool isx = c < n, isu = !isx && c < n + m;
-            const double *src = isx ? z + c * N1 : isu ? z + n * N1 + (c - n) * NU : z;
             const int64_t last = isx ? N : isu ? NU - 1 : -1;
-            const int64_t span = last - b0;  // lanes slot <= span hold nodes of the row
-            const double *pb = span >= 0 ? src + b0 : src;
-            const uint32_t lim = span >= 0 ? (uint32_t)(span < CH - 1 ? span : CH - 1) : 0u;
-            xv[jj] = pb[(uint32_t)slot < lim ? (uint32_t)slot : lim];
+            if (MIXED) {
+                // the state row itself (a column past the states reloads the
+                // last state row, an L2 hit; its value is unused), and v's row
+                xv[jj] = row_load(z + (isx ? c : n - 1) * N1, N, b0);
+                vv[jj] = row_load(isx ? v + c * N1 : isu ? v + n * N1 + (c - n) * NU : v, last, b0);
+            } else {
+                xv[jj] = row_load(isx ? z + c * N1 : isu ? z + n * N1 + (c - n) * NU : z, last, b0);
+            }
         }
         const int64_t rspan = N - 1 - b0;  // lanes slot <= rspan hold nodes k < N
         const uint32_t rlim = rspan >= 0 ? (uint32_t)(rspan < CH - 1 ? rspan : CH - 1) : 0u;
@@ -430,12 +448,24 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
         for (int jj = 0; jj < HC; jj++) {
             const int c = Q * jj + h;
             const int64_t last = c < n ? N : c < n + m ? NU - 1 : -1;
-            const double v = xv[jj] * (k <= last ? 1.0 : 0.0);
-            if (c < n) {
-                Xl[c][slot] = v;
-                Vl[c][slot] = sin(v);
+            const double live = k <= last ? 1.0 : 0.0;
+            if (MIXED) {
+                const double x = xv[jj] * live, d = vv[jj] * live;
+                if (c < n) {
+                    Xl[c][slot] = x;
+                    Wl[c][slot] = d;
+                    Vl[c][slot] = cos(x) * d;
+                } else {
+                    Vl[c][slot] = d;
+                }
             } else {
-                Vl[c][slot] = v;
+                const double x = xv[jj] * live;
+                if (c < n) {
+                    Xl[c][slot] = x;
+                    Vl[c][slot] = sin(x);
+                } else {
+                    Vl[c][slot] = x;
+                }
             }
         }
         const double fr = k < N ? 1.0 : 0.0, fh = b0 >= 1 ? 1.0 : 0.0;
@@ -460,7 +490,9 @@ __global__ __launch_bounds__(kBlock) void coef_partial_kernel(
             if (i < n) {
                 const int p = (i + 1 == n) ? 0 : i + 1;
                 const double yt = __builtin_fma(fl, Yl[i][slot], Yl[i][slot + 1]);
-                gam[rr] = __builtin_fma(yt, Xl[i][slot] * Xl[p][slot], gam[rr]);
+                const double pr = MIXED ? __builtin_fma(Wl[i][slot], Xl[p][slot], Xl[i][slot] * Wl[p][slot])
+                                        : Xl[i][slot] * Xl[p][slot];
+                gam[rr] = __builtin_fma(yt, pr, gam[rr]);
             }
         }
         // the contraction
@@ -598,8 +630,8 @@ double *noalloc_scratch(int device)
     return scratch_addr[device];
 }
 
-static int launch_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA, double *gB,
-                            double *ggamma, double *cpart, hipStream_t stream, const char *fn);
+static int launch_coef_grad(const ocp_problem *p, const double *z, const double *y, const double *v, double *gA,
+                            double *gB, double *ggamma, double *cpart, hipStream_t stream, const char *fn);
 
 #define OCP_DISPATCH_NB(n, KERNEL, grid, ...)                                                   \
     do {                                                                                        \
@@ -696,7 +728,18 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
     if (int rc = check_coefficients(p, "ocp_eval_coef_grad")) return rc;
     if (!z || !y || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_grad: null array");
-    return launch_coef_grad(p, z, y, gA, gB, ggamma, p->cpart, stream, "ocp_eval_coef_grad");
+    return launch_coef_grad(p, z, y, nullptr, gA, gB, ggamma, p->cpart, stream, "ocp_eval_coef_grad");
+}
+
+int ocp_eval_coef_mixed(const ocp_problem *p, const double *z, const double *y, const double *v, double *gA,
+                        double *gB, double *ggamma, hipStream_t stream)
+{
+    clear_error();
+    if (int rc = check_handle(p, "ocp_eval_coef_mixed")) return rc;
+    if (int rc = check_coefficients(p, "ocp_eval_coef_mixed")) return rc;
+    if (!z || !y || !v || !gA || !ggamma || (p->d.m > 0 && !gB))
+        return fail(OCP_ERR_ARG, "ocp_eval_coef_mixed: null array");
+    return launch_coef_grad(p, z, y, v, gA, gB, ggamma, p->cpart, stream, "ocp_eval_coef_mixed");
 }
 
 int ocp_eval_coef_grad_noalloc(const ocp_problem *p, const double *z, const double *y, double *gA,
@@ -719,21 +762,21 @@ int ocp_eval_coef_grad_noalloc(const ocp_problem *p, const double *z, const doub
         return fail(OCP_ERR_ARG, std::string(fn) + ": the current device is not the handle's");
     double *ws = noalloc_scratch(dev);
     if (!ws) return fail(OCP_ERR_HIP, std::string(fn) + ": the scratch array's device address is unknown");
-    return launch_coef_grad(p, z, y, gA, gB, ggamma, ws, stream, fn);
+    return launch_coef_grad(p, z, y, nullptr, gA, gB, ggamma, ws, stream, fn);
 }
 
 }  // extern "C"
 
-static int launch_coef_grad(const ocp_problem *p, const double *z, const double *y, double *gA, double *gB,
-                            double *ggamma, double *cpart, hipStream_t stream, const char *fn)
+template <bool MIXED>
+static void launch_coef_partial(const ocp_problem *p, const double *z, const double *y, const double *v, int G,
+                                double *cpart, hipStream_t stream)
 {
-    const int n = p->d.n, m = p->d.m, ncol = n + m + 1;
-    const int G = coef_blocks(p->d.N1);
+    const int n = p->d.n, m = p->d.m;
     // 16-row blocks of yt (n <= 32) and 16-column blocks of [sin X | U] (n + m <= 64)
     const int mb = (n + 15) / 16, nbk = (n + m + 15) / 16;
-#define OCP_COEF_LAUNCH(MB_, NBK_)                                                                      \
-    hipLaunchKernelGGL((coef_partial_kernel<MB_, NBK_>), dim3(G), dim3(kBlock), 0, stream, p->kp, z, y, \
-                       G, cpart)
+#define OCP_COEF_LAUNCH(MB_, NBK_)                                                                       \
+    hipLaunchKernelGGL((coef_partial_kernel<MB_, NBK_, MIXED>), dim3(G), dim3(kBlock), 0, stream, p->kp, z, \
+                       y, v, G, cpart)
     if (mb == 1) {
         if (nbk == 1) OCP_COEF_LAUNCH(1, 1);
         else if (nbk == 2) OCP_COEF_LAUNCH(1, 2);
@@ -744,6 +787,16 @@ static int launch_coef_grad(const ocp_problem *p, const double *z, const double 
         else OCP_COEF_LAUNCH(2, 4);
     }
 #undef OCP_COEF_LAUNCH
+}
+
+// v == nullptr: the coefficient gradient; otherwise its derivative along v.
+static int launch_coef_grad(const ocp_problem *p, const double *z, const double *y, const double *v, double *gA,
+                            double *gB, double *ggamma, double *cpart, hipStream_t stream, const char *fn)
+{
+    const int n = p->d.n, m = p->d.m, ncol = n + m + 1;
+    const int G = coef_blocks(p->d.N1);
+    if (v) launch_coef_partial<true>(p, z, y, v, G, cpart, stream);
+    else launch_coef_partial<false>(p, z, y, nullptr, G, cpart, stream);
     if (int rc = check_launch(fn)) return rc;
     hipLaunchKernelGGL(coef_final_kernel, dim3(n * ncol), dim3(kBlock), 0, stream, p->kp, cpart, G,
                        gA, gB, ggamma);

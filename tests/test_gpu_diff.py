@@ -276,6 +276,13 @@ def test_autograd_gradcheck(ocp, N, n, m, scheme, bnd):
     fg = lambda z, y: lagrangian_grad(prob, z, y, A, B, g, 1.2)
     assert torch.autograd.gradcheck(fg, (z, y), eps=1e-6, atol=1e-6, rtol=1e-5)
     z, y, A, B, g = _leaf_inputs(inst, dev)
+    # grad_z L in every input, the coefficients included (the mixed terms)
+    if m == 0:
+        fgc = lambda z, y, A, g: lagrangian_grad(prob, z, y, A, B.detach(), g, 1.2)
+        assert torch.autograd.gradcheck(fgc, (z, y, A, g), eps=1e-6, atol=1e-6, rtol=1e-5)
+    else:
+        fgc = lambda z, y, A, B, g: lagrangian_grad(prob, z, y, A, B, g, 1.2)
+        assert torch.autograd.gradcheck(fgc, (z, y, A, B, g), eps=1e-6, atol=1e-6, rtol=1e-5)
     if m == 0:
         B = B.detach()
         fc = lambda z, A, g: constraints(prob, z, A, B, g)
@@ -303,16 +310,92 @@ def test_hvp_with_detached_coefficients(ocp):
     prob.close()
 
 
-def test_second_order_in_coefficients_raises(ocp):
+def test_second_order_through_grad_z_with_coefficients(ocp):
+    """grad_z L built from L with the coefficients requiring grad: a backward
+    with v gives H v, J v and the mixed terms d/dtheta (v^T grad_z L), each
+    against the oracle; differentiating dL/dA itself again raises."""
     from paper_2510_03932_amd.autograd import lagrangian
-    inst = synth.make_instance(10, 3, 1, seed=8)
+    inst = synth.make_instance(700, 5, 3, seed=8, scheme=1, bnd=2)
     dev = torch.device("cuda", 0)
     prob = ocp.Problem.from_instance(inst, dev)
     z, y, A, B, g = _leaf_inputs(inst, dev)
-    L = lagrangian(prob, z, y, A, B, g)
+    v = np.random.default_rng(12).normal(size=len(inst.z))
+    L = lagrangian(prob, z, y, A, B, g, 0.7)
     (gz,) = torch.autograd.grad(L, z, create_graph=True)
+    hv, jv, hA, hB, hg = torch.autograd.grad(gz, (z, y, A, B, g), torch.from_numpy(v).to(dev))
+    want, mu = oracle.hvp_ex(inst, v, 1, 2, sigma=0.7)
+    check_close(hv.cpu().numpy(), want, mu, what="H v")
+    want, mu = oracle.jvp_ex(inst, v, 1, 2)
+    check_close(jv.cpu().numpy(), want, mu, what="J v")
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_mixed_ex(inst, v, 1, 2)
+    check_close(hA.cpu().numpy().ravel(), oA.ravel(), mA.ravel(), what="mixed A")
+    check_close(hB.cpu().numpy().ravel(), oB.ravel(), mB.ravel(), what="mixed B")
+    check_close(hg.cpu().numpy(), og, mg, what="mixed gamma")
+    L = lagrangian(prob, z, y, A, B, g)
+    (gA,) = torch.autograd.grad(L, A, create_graph=True)
     with pytest.raises(NotImplementedError):
-        gz.sum().backward()
+        gA.sum().backward()
+    prob.close()
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("n,m", COEF_TILINGS)
+def test_coef_mixed_every_tiling(ocp, n, m, scheme):
+    """The mixed derivative for every tiling of the coefficient kernel, at
+    N = 389 (several chunks, a ragged last one), with boundary rows."""
+    N = 389
+    _say(f"[coef mixed] N={N} n={n} m={m} scheme={scheme}")
+    bnd = 1 + scheme
+    inst = synth.make_instance(N, n, m, seed=17, scheme=scheme, bnd=bnd)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    v = np.random.default_rng(n + m).normal(size=len(inst.z))
+    z, y, vt = (torch.from_numpy(a).to(dev) for a in (inst.z, inst.y, v))
+    gA, gB, gg = (t.cpu().numpy() for t in prob.coef_mixed(z, y, vt))
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_mixed_ex(inst, v, scheme, bnd)
+    tag = f"{N},{n},{m},{scheme}"
+    check_close(gA.ravel(), oA.ravel(), mA.ravel(), what=f"mixed A {tag}")
+    check_close(gB.ravel(), oB.ravel(), mB.ravel(), what=f"mixed B {tag}")
+    check_close(gg, og, mg, what=f"mixed gamma {tag}")
+    prob.close()
+
+
+@pytest.mark.parametrize("N,n,m,scheme", [(600_001, 3, 0, 1), (270_000, 17, 9, 0)])
+def test_coef_mixed_many_chunks_per_workgroup(ocp, N, n, m, scheme):
+    """Several chunks per workgroup and a ragged last chunk; a second call
+    gives the same bits."""
+    _say(f"[coef mixed] N={N} n={n} m={m} scheme={scheme}")
+    inst = synth.make_instance(N, n, m, seed=19, scheme=scheme)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    v = np.random.default_rng(4).normal(size=len(inst.z))
+    z, y, vt = (torch.from_numpy(a).to(dev) for a in (inst.z, inst.y, v))
+    got = [t.cpu().numpy() for t in prob.coef_mixed(z, y, vt)]
+    again = [t.cpu().numpy() for t in prob.coef_mixed(z, y, vt)]
+    for first, second in zip(got, again):
+        assert np.array_equal(first.view(np.int64), second.view(np.int64))
+    (oA, oB, og), (mA, mB, mg) = oracle.coef_mixed_ex(inst, v, scheme, 0)
+    tag = f"{N},{n},{m},{scheme}"
+    check_close(got[0].ravel(), oA.ravel(), mA.ravel(), what=f"mixed A {tag}")
+    check_close(got[1].ravel(), oB.ravel(), mB.ravel(), what=f"mixed B {tag}")
+    check_close(got[2], og, mg, what=f"mixed gamma {tag}")
+    prob.close()
+
+
+def test_coef_mixed_rejects_quadrotor_and_null(ocp):
+    q = synth.make_quadrotor(8, seed=0, bnd=1)
+    dev = torch.device("cuda", 0)
+    qp = ocp.QuadrotorProblem.from_instance(q, dev)
+    z, y = torch.from_numpy(q.z).to(dev), torch.from_numpy(q.y).to(dev)
+    with pytest.raises(ocp.OcpError):
+        qp.coef_mixed(z, y, z.clone())
+    qp.close()
+    inst = synth.make_instance(10, 2, 1, seed=1)
+    prob = ocp.Problem.from_instance(inst, dev)
+    out = torch.empty(8, dtype=torch.float64, device=dev)
+    rc = ocp.lib().ocp_eval_coef_mixed(prob._h, None, None, None, out.data_ptr(), out.data_ptr(),
+                                       out.data_ptr(), None)
+    assert rc == ocp.OCP_ERR_ARG
     prob.close()
 
 
