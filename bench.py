@@ -386,11 +386,8 @@ def differentiation(torch, ocp, synth, reps=20):
         "coef_mixed": (lambda: prob.coef_mixed(z, y, v, out=cg), 8 * (nx + nv + nc)),
     }
     out = {"workload": f"N={N} n={n} m={m}, seed 0"}
-    for name, (fn, nbytes) in calls.items():
-        ms, gms = _call_times(torch, fn, reps)
-        out[name] = {"ms": round(ms, 4), "graph_ms": round(gms, 4), "bytes": nbytes,
-                     "hbm_frac": round(nbytes / (gms * 1e-3) / HBM_PEAK, 4),
-                     "eager_hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+    # the autograd pass first: it is timed on the host clock, and HIP graph
+    # captures made before it slowed its Python-side dispatch
     leaf = lambda a: torch.from_numpy(np.array(a)).to(dev).requires_grad_(True)
     zt, yt, At, Bt, gt = (leaf(a) for a in (inst.z, inst.y, inst.A, inst.B, inst.gamma))
 
@@ -406,6 +403,11 @@ def differentiation(torch, ocp, synth, reps=20):
         fwd_bwd()
     torch.cuda.synchronize()
     out["autograd_forward_backward_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+    for name, (fn, nbytes) in calls.items():
+        ms, gms = _call_times(torch, fn, reps)
+        out[name] = {"ms": round(ms, 4), "graph_ms": round(gms, 4), "bytes": nbytes,
+                     "hbm_frac": round(nbytes / (gms * 1e-3) / HBM_PEAK, 4),
+                     "eager_hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
     prob.close()
 
     # the same entry points on the quadrotor model at the paper's largest

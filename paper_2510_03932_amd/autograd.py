@@ -134,11 +134,15 @@ class _Lagrangian(torch.autograd.Function):
             # without the nested Functions' bookkeeping
             zd, yd = z.detach().contiguous(), y.detach().contiguous()
             if ctx.needs_input_grad[0]:
-                gz = prob.lag_grad(zd, yd, sigma).mul_(gL)
+                gz = prob.lag_grad(zd, yd, sigma)
             if ctx.needs_input_grad[1]:
-                gy = prob.cons(zd).mul_(gL)
+                gy = prob.cons(zd)
             if any(ctx.needs_input_grad[2:5]):
-                gA, gB, gg = (t.mul_(gL) for t in prob.coef_grad(zd, yd))
+                gA, gB, gg = prob.coef_grad(zd, yd)
+            # every piece times the incoming gradient in one multi-tensor launch
+            outs = [t for t in (gz, gy, gA, gB, gg) if t is not None]
+            if outs:
+                torch._foreach_mul_(outs, gL)
             return gz, gy, gA, gB, gg, None, None
         prob._coef_uploaded = True
         try:
