@@ -331,6 +331,18 @@ class Problem:
         except Exception:
             pass
 
+    # -- the problem's sparsity structure (host) ----------------------------------
+    def pattern(self, jac: bool = True, hess: bool = True):
+        """This problem's COO patterns (jrow, jcol, hrow, hcol): the module's
+        pattern() for the problem's sizes, scheme and boundary option."""
+        return pattern(self.N, self.n, self.m, jac, hess, self.options.scheme, self.options.boundary)
+
+    def kkt_pattern(self, rowptr=True, colind=True, perm_j=True, perm_h=True):
+        """This problem's KKT structure (rowptr, colind, perm_j, perm_h): the
+        module's kkt_pattern() for the problem's sizes and options."""
+        return kkt_pattern(self.N, self.n, self.m, rowptr, colind, perm_j, perm_h, self.options.scheme,
+                           self.options.boundary)
+
     # -- marshalling helpers ---------------------------------------------------
     def _dev(self, t, numel, dtype, what):
         torch = _torch()
@@ -578,6 +590,14 @@ class QuadrotorProblem(Problem):
     @classmethod
     def from_instance(cls, q, device=None):
         return cls(q.N, q.bnd, q.g, q.r, device)
+
+    def pattern(self, jac: bool = True, hess: bool = True):
+        """The quadrotor NLP's COO patterns (module quad_pattern())."""
+        return quad_pattern(self.N, self.boundary, jac, hess)
+
+    def kkt_pattern(self, rowptr=True, colind=True, perm_j=True, perm_h=True):
+        """The quadrotor NLP's KKT structure (module quad_kkt_pattern())."""
+        return quad_kkt_pattern(self.N, self.boundary, rowptr, colind, perm_j, perm_h)
 
 
 def _autotune_cache_path() -> str:

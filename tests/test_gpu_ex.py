@@ -103,3 +103,29 @@ def test_euler_large_full_arrays(ocp):
     del got, want, mu
     prob.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("scheme,bnd", [(0, 0), (1, 2), (0, 1)])
+def test_problem_pattern_methods(ocp, scheme, bnd):
+    """Problem.pattern() and Problem.kkt_pattern() give the handle's own
+    structure: bit-exact against the oracle's pattern and KKT build for the
+    problem's sizes, scheme and boundary option; the same for the quadrotor."""
+    N, n, m = 37, 5, 2
+    inst = synth.make_instance(N, n, m, seed=3, scheme=scheme, bnd=bnd)
+    prob = ocp.Problem.from_instance(inst, torch.device("cuda", 0))
+    got = prob.pattern()
+    want = oracle.pattern_ex(N, n, m, scheme, bnd)
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+    got = prob.kkt_pattern()
+    rowptr, colind, perm_j, perm_h = oracle.kkt_ex(N, n, m, scheme, bnd)[:4]
+    for g, w in zip(got, (rowptr, colind, perm_j, perm_h)):
+        assert np.array_equal(g, w)
+    prob.close()
+    q = synth.make_quadrotor(21, seed=0, bnd=bnd)
+    qp = ocp.QuadrotorProblem.from_instance(q, torch.device("cuda", 0))
+    for g, w in zip(qp.pattern(), oracle.quad_pattern(21, bnd)):
+        assert np.array_equal(g, w)
+    for g, w in zip(qp.kkt_pattern(), oracle.quad_kkt(21, bnd)[:4]):
+        assert np.array_equal(g, w)
+    qp.close()
