@@ -175,8 +175,8 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
             const int k = td.k0 + tid;
             if (k <= P.N) {
                 if constexpr (SCHEME != 0)
-                    hess_node_euler<NB>(P, zb, y_ + id.c_off, sigma, hess_ + id.hess_off, k);
-                else hess_node<NB>(P, zb, y_ + id.c_off, sigma, hess_ + id.hess_off, k);
+                    hess_node_euler<NB, true>(P, zb, y_ + id.c_off, sigma, hess_ + id.hess_off, k);
+                else hess_node<NB, true>(P, zb, y_ + id.c_off, sigma, hess_ + id.hess_off, k);
             }
             break;
         }

@@ -74,6 +74,14 @@ __device__ __forceinline__ double node_weight(const KP &P, int k)
 }
 
 __device__ __forceinline__ void st_nt(double *p, double v) { __builtin_nontemporal_store(v, p); }
+// A store that is non-temporal when NT (the default for outputs), else an
+// ordinary one.
+template <bool NT>
+__device__ __forceinline__ void st_out(double *p, double v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 __device__ __forceinline__ void st_nt2(double *p, dbl2 v)
 {
     __builtin_nontemporal_store(v, reinterpret_cast<dbl2 *>(p));
@@ -191,8 +199,16 @@ __device__ __forceinline__ void jac_column(const KP &P, const double *__restrict
 // issued before the arithmetic, and the control slots (constants) and the
 // bilinear slots (multipliers only) are stored before the state diagonals,
 // so their stores leave while the sines are computed.
+// NT selects non-temporal stores.  The single-instance trapezoidal kernel
+// stores ordinarily: a node's values go to S slot rows, one 8-byte store per
+// lane and row, and with non-temporal stores that pattern reaches 60 % of HBM
+// with no arithmetic at all against 73 % with ordinary ones.  The lines are
+// then written back during the next kernel (in an interior-point step the
+// assembly, which reads these values).  The batched kernel and the forward
+// Euler kernel keep non-temporal stores (measured no better, or worse, with
+// ordinary ones).
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, bool NT>
 __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict__ z,
                                           const double *__restrict__ y, double sigma,
                                           double *__restrict__ hv, int k)
@@ -212,16 +228,16 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
         }
     }
     const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
-    for (int l = 0; l < m; l++) st_nt(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
+    for (int l = 0; l < m; l++) st_out<NT>(hv + ub + l * N1, 2.0 * sigma * w * P.r[l]);
     double yt[NB];
 #pragma unroll
     for (int i = 0; i < NB; i++) yt[i] = yl[i] + yr[i];
     if (n >= 3) {
 #pragma unroll
         for (int i = 0; i < NB; i++)
-            if (i < n) st_nt(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
+            if (i < n) st_out<NT>(hv + (n + i) * N1 + k, -P.hh * yt[i] * P.gam[i]);
     } else if (n == 2) {
-        st_nt(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+        st_out<NT>(hv + 2 * N1 + k, -P.hh * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
     }
 #pragma unroll
     for (int j = 0; j < NB; j++) {
@@ -233,7 +249,7 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
             for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             double v = 2.0 * sigma * w * P.q[j] + P.hh * sx * s;
             if (n == 1) v -= P.h * yt[0] * P.gam[0];
-            st_nt(hv + j * N1 + k, v);
+            st_out<NT>(hv + j * N1 + k, v);
         }
     }
 }
@@ -370,8 +386,8 @@ __device__ __forceinline__ void jac_column_euler(const KP &P, const double *__re
 // Forward Euler Hessian-of-Lagrangian values at node k <= N: node k enters
 // only the defect of interval k (multiplier y_k, factor h); node N enters no
 // defect and carries no cost, so its entries are zero.  Control slots exist
-// for k < N only, at (n+npair)(N+1) + l N + k.
-template <int NB>
+// for k < N only, at (n+npair)(N+1) + l N + k.  NT as for hess_node.
+template <int NB, bool NT>
 __device__ __forceinline__ void hess_node_euler(const KP &P, const double *__restrict__ z,
                                                 const double *__restrict__ y, double sigma,
                                                 double *__restrict__ hv, int k)
@@ -399,19 +415,19 @@ __device__ __forceinline__ void hess_node_euler(const KP &P, const double *__res
             for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], a[i], s);
             double v = 2.0 * sigma * w * P.q[j] + h * sx * s;
             if (n == 1) v -= 2.0 * h * yt[0] * P.gam[0];
-            st_nt(hv + j * N1 + k, v);
+            st_out<NT>(hv + j * N1 + k, v);
         }
     }
     if (n >= 3) {
 #pragma unroll
         for (int i = 0; i < NB; i++)
-            if (i < n) st_nt(hv + (n + i) * N1 + k, -h * yt[i] * P.gam[i]);
+            if (i < n) st_out<NT>(hv + (n + i) * N1 + k, -h * yt[i] * P.gam[i]);
     } else if (n == 2) {
-        st_nt(hv + 2 * N1 + k, -h * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+        st_out<NT>(hv + 2 * N1 + k, -h * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
     }
     if (k < P.NU) {
         const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
-        for (int l = 0; l < m; l++) st_nt(hv + ub + (int64_t)l * P.NU, 2.0 * sigma * w * P.r[l]);
+        for (int l = 0; l < m; l++) st_out<NT>(hv + ub + (int64_t)l * P.NU, 2.0 * sigma * w * P.r[l]);
     }
 }
 

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void hess_kernel(KP P, const double *__rest
 {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k > P.N) return;
-    hess_node<NB>(P, z, y, sigma, hv, k);
+    hess_node<NB, false>(P, z, y, sigma, hv, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void hess_euler_kernel(KP P, const double *
 {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k > P.N) return;
-    hess_node_euler<NB>(P, z, y, sigma, hv, k);
+    hess_node_euler<NB, true>(P, z, y, sigma, hv, k);
 }
 
 // ---------------------------------------------------------------------------
