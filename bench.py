@@ -330,7 +330,7 @@ def batched(torch, ocp, synth, reps=10):
 def _call_times(torch, fn, reps):
     """(eager ms, graph ms) per call: `reps` calls issued from Python between
     two HIP events, then the same `reps` calls captured in one HIP graph and
-    replayed.  At small sizes the eager figure is bounded by Python's
+    replayed (median of 5 timed replays).  At small sizes the eager figure is bounded by Python's
     per-call dispatch (ctypes, argument checks); the graph figure is the
     device's time per call."""
     fn()
@@ -348,13 +348,15 @@ def _call_times(torch, fn, reps):
             fn()
     g.replay()
     torch.cuda.synchronize()
-    e0.record()
-    g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    graph = e0.elapsed_time(e1) / reps
+    times = []
+    for _ in range(5):
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / reps)
     del g
-    return eager, graph
+    return eager, float(np.median(times))
 
 
 def differentiation(torch, ocp, synth, reps=20):

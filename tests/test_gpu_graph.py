@@ -117,3 +117,83 @@ def test_graph_replays_equal_eager_quadrotor(ocp, N, bnd):
     pattern = ocp.quad_kkt_pattern(N, bnd, colind=False)
     _run(ocp, prob, pattern, _points(point, 3), fused=True)
     prob.close()
+
+
+def _diff_outputs(prob, coef):
+    s = prob.sizes
+    f64 = dict(dtype=torch.float64, device=torch.device("cuda", 0))
+    o = {"L": torch.full((1,), float("nan"), **f64)}
+    for k in ("g", "hv"):
+        o[k] = torch.full((s["nvar"],), float("nan"), **f64)
+    o["jv"] = torch.full((s["ncon"],), float("nan"), **f64)
+    if coef:
+        n, m = prob.n, prob.m
+        for tag in ("cg", "cm", "cn"):
+            o[tag] = (torch.full((n, n), float("nan"), **f64), torch.full((n, m), float("nan"), **f64),
+                      torch.full((n,), float("nan"), **f64))
+    return o
+
+
+def _diff_calls(prob, z, y, v, o, coef):
+    prob.lagrangian(z, y, 0.7, out=o["L"])
+    prob.lag_grad(z, y, 0.7, out=o["g"])
+    prob.hvp(z, y, v, 0.7, out=o["hv"])
+    prob.jvp(z, v, out=o["jv"])
+    if coef:
+        prob.coef_grad(z, y, out=o["cg"])
+        prob.coef_mixed(z, y, v, out=o["cm"])
+        prob.coef_grad(z, y, noalloc=True, out=o["cn"])
+
+
+def _flat(o):
+    out = {}
+    for k, t in o.items():
+        if isinstance(t, tuple):
+            for i, u in enumerate(t):
+                out[f"{k}{i}"] = u
+        else:
+            out[k] = t
+    return out
+
+
+@pytest.mark.parametrize("model,scheme,bnd", [("synthetic", 0, 0), ("synthetic", 1, 2), ("quadrotor", 0, 1)])
+def test_graph_replays_equal_eager_differentiation(ocp, model, scheme, bnd):
+    """The Lagrangian entry points (L, grad_z L, H v, J v and, for the
+    synthetic family, the coefficient gradient, its mixed derivative and the
+    allocation-free coefficient gradient) captured in one graph: each replay
+    at a new point equals the eager calls bit for bit."""
+    _say(f"[graph] differentiation {model} scheme={scheme} bnd={bnd}")
+    dev = torch.device("cuda", 0)
+    coef = model == "synthetic"
+    if coef:
+        make = lambda seed: synth.make_instance(900, 6, 3, seed=seed, scheme=scheme, bnd=bnd)
+        prob = ocp.Problem.from_instance(make(70), dev)
+    else:
+        make = lambda seed: synth.make_quadrotor(700, seed=seed, bnd=bnd)
+        prob = ocp.QuadrotorProblem.from_instance(make(70), dev)
+    rng = np.random.default_rng(5)
+    first = make(100)
+    zs, ys = _t(first.z).clone(), _t(first.y).clone()
+    vs = _t(rng.normal(size=prob.sizes["nvar"])).clone()
+    outs = _diff_outputs(prob, coef)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        _diff_calls(prob, zs, ys, vs, outs, coef)
+    torch.cuda.synchronize()
+    for r, seed in enumerate((100, 101, 102)):
+        p = make(seed)
+        v = _t(rng.normal(size=prob.sizes["nvar"]))
+        ref = _diff_outputs(prob, coef)
+        _diff_calls(prob, _t(p.z), _t(p.y), v, ref, coef)  # eager, same point
+        torch.cuda.synchronize()
+        zs.copy_(_t(p.z))
+        ys.copy_(_t(p.y))
+        vs.copy_(v)
+        g.replay()
+        torch.cuda.synchronize()
+        fo, fr = _flat(outs), _flat(ref)
+        for k in fo:
+            assert torch.equal(fo[k].view(torch.int64), fr[k].view(torch.int64)), (r, k)
+    del g
+    prob.close()
