@@ -15,11 +15,12 @@ coefficients theta = (A, B, gamma) (library call ocp_eval_coef_mixed)::
     gz = lagrangian_grad(prob, z, y, A, B, gamma)
     hv, hA, hB, hg = torch.autograd.grad(gz, (z, A, B, gamma), v)
 
-The coefficient gradient dL/dtheta is differentiable only to first order:
-differentiating it again (``torch.autograd.grad(L, A, create_graph=True)``
-followed by a backward) raises NotImplementedError.  L is affine in theta,
-so the second derivatives in theta alone are zero; the ones that mix theta
-with z are reached through grad_z L as above.
+The coefficient gradient dL/dtheta is differentiable too: L is affine in
+theta, so its derivative in theta is zero and its derivatives in z and y are
+the coefficient parts of grad_z L and of c under the cotangent coefficients
+(the library's grad_z L and c with the handle's coefficients swapped and
+restored).  So ``torch.autograd.gradgradcheck`` of L passes over all of
+(z, y, A, B, gamma).  Third derivatives raise NotImplementedError.
 """
 from __future__ import annotations
 
@@ -98,19 +99,44 @@ class _Cons(torch.autograd.Function):
 
 
 class _CoefGrad(torch.autograd.Function):
-    """dL/d(A, B, gamma) as a function of (z, y); differentiating it again
-    raises (the mixed terms are available through grad_z L instead)."""
+    """dL/d(A, B, gamma) as a function of (z, y, A, B, gamma).  Its backward
+    uses that L is affine in theta = (A, B, gamma): for cotangents tb,
+    tb . dL/dtheta = y^T (c(z; tb) - c(z; 0)), so the gradient in z is
+    grad_z L at sigma = 0 under the coefficients tb less the same under zero
+    coefficients (which leaves the coefficient part of J^T y), the gradient in
+    y is c(z; tb) - c(z; 0) (the coefficient part of the defects; boundary
+    rows cancel), and the gradient in theta is zero.  The handle's
+    coefficients are swapped for the four library calls and restored."""
 
     @staticmethod
     def forward(ctx, z, y, A, B, gamma, prob):
         _coefficients(prob, A, B, gamma)
+        ctx.save_for_backward(z, y, A, B, gamma)
+        ctx.prob = prob
         return prob.coef_grad(z.detach().contiguous(), y.detach().contiguous())
 
     @staticmethod
-    def backward(ctx, *grads):
-        raise NotImplementedError("the coefficient gradient dL/d(A, B, gamma) is differentiable only "
-                                  "to first order; reach the mixed second derivatives through "
-                                  "lagrangian_grad (grad_z L) instead")
+    def backward(ctx, tA, tB, tg):
+        z, y, A, B, gamma = ctx.saved_tensors
+        prob = ctx.prob
+        if torch.is_grad_enabled() and any(t.requires_grad for t in (z, y, tA, tB, tg)):
+            raise NotImplementedError("third derivatives of the Lagrangian are not provided")
+        gz = gy = None
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            zd, yd = z.detach().contiguous(), y.detach().contiguous()
+            zero = [torch.zeros_like(t) for t in (A, B, gamma)]
+            parts = []
+            for coef in ((tA.detach(), tB.detach(), tg.detach()), zero):
+                prob.set_coefficients(*coef)
+                parts.append((prob.lag_grad(zd, yd, 0.0) if ctx.needs_input_grad[0] else None,
+                              prob.cons(zd) if ctx.needs_input_grad[1] else None))
+            prob.set_coefficients(A.detach(), B.detach(), gamma.detach())
+            (z1, y1), (z0, y0) = parts
+            if ctx.needs_input_grad[0]:
+                gz = z1.sub_(z0)
+            if ctx.needs_input_grad[1]:
+                gy = y1.sub_(y0)
+        return gz, gy, None, None, None, None
 
 
 class _Lagrangian(torch.autograd.Function):

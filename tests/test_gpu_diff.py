@@ -273,6 +273,15 @@ def test_autograd_gradcheck(ocp, N, n, m, scheme, bnd):
     z, y, A, B, g = _leaf_inputs(inst, dev, coef_grad=False)
     f2 = lambda z, y: lagrangian(prob, z, y, A, B, g, 1.2)
     assert torch.autograd.gradgradcheck(f2, (z, y), eps=1e-6, atol=1e-6, rtol=1e-5)
+    # second order in every input: the mixed terms through grad_z L and the
+    # derivatives of dL/dtheta in z and y
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    if m == 0:
+        f3 = lambda z, y, A, g: lagrangian(prob, z, y, A, B.detach(), g, 1.2)
+        assert torch.autograd.gradgradcheck(f3, (z, y, A, g), eps=1e-6, atol=1e-6, rtol=1e-5)
+    else:
+        f3 = lambda z, y, A, B, g: lagrangian(prob, z, y, A, B, g, 1.2)
+        assert torch.autograd.gradgradcheck(f3, (z, y, A, B, g), eps=1e-6, atol=1e-6, rtol=1e-5)
     fg = lambda z, y: lagrangian_grad(prob, z, y, A, B, g, 1.2)
     assert torch.autograd.gradcheck(fg, (z, y), eps=1e-6, atol=1e-6, rtol=1e-5)
     z, y, A, B, g = _leaf_inputs(inst, dev)
@@ -313,7 +322,7 @@ def test_hvp_with_detached_coefficients(ocp):
 def test_second_order_through_grad_z_with_coefficients(ocp):
     """grad_z L built from L with the coefficients requiring grad: a backward
     with v gives H v, J v and the mixed terms d/dtheta (v^T grad_z L), each
-    against the oracle; differentiating dL/dA itself again raises."""
+    against the oracle."""
     from paper_2510_03932_amd.autograd import lagrangian
     inst = synth.make_instance(700, 5, 3, seed=8, scheme=1, bnd=2)
     dev = torch.device("cuda", 0)
@@ -331,10 +340,40 @@ def test_second_order_through_grad_z_with_coefficients(ocp):
     check_close(hA.cpu().numpy().ravel(), oA.ravel(), mA.ravel(), what="mixed A")
     check_close(hB.cpu().numpy().ravel(), oB.ravel(), mB.ravel(), what="mixed B")
     check_close(hg.cpu().numpy(), og, mg, what="mixed gamma")
+    prob.close()
+
+
+def test_coefficient_gradient_differentiated_again(ocp):
+    """dL/dtheta as a function of (z, y): for cotangents tb, the gradient of
+    tb . dL/dtheta is the coefficient part of grad_z L and of c under the
+    coefficients tb, against the oracle's grad_z L and c evaluated with
+    coefficients tb and with zero coefficients (sigma = 0); the handle's
+    coefficients are the original ones afterwards; a third derivative
+    raises."""
+    import dataclasses
+    from paper_2510_03932_amd.autograd import lagrangian
+    inst = synth.make_instance(600, 4, 2, seed=23, scheme=0, bnd=1)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y, A, B, g = _leaf_inputs(inst, dev)
+    rng = np.random.default_rng(17)
+    tA, tB, tg = rng.normal(size=(4, 4)), rng.normal(size=(4, 2)), rng.normal(size=4)
+    L = lagrangian(prob, z, y, A, B, g, 0.9)
+    dA, dB, dg = torch.autograd.grad(L, (A, B, g), create_graph=True)
+    gz, gy = torch.autograd.grad((dA, dB, dg), (z, y), tuple(torch.from_numpy(t).to(dev) for t in (tA, tB, tg)))
+    with_tb = dataclasses.replace(inst, A=tA, B=tB, gamma=tg)
+    zero = dataclasses.replace(inst, A=0 * tA, B=0 * tB, gamma=0 * tg)
+    (g1, m1), (g0, m0) = (oracle.lag_grad_ex(i, 0, 1, sigma=0.0) for i in (with_tb, zero))
+    check_close(gz.cpu().numpy(), g1 - g0, m1 + m0, what="d/dz of tb . dL/dtheta")
+    (c1, n1), (c0, n0) = (oracle.cons_ex(i, 0, 1) for i in (with_tb, zero))
+    check_close(gy.cpu().numpy(), c1 - c0, n1 + n0, what="d/dy of tb . dL/dtheta")
+    # the handle holds the original coefficients again
+    Lo, Lm = oracle.lagrangian_ex(inst, 0, 1, sigma=0.9)
+    assert abs(prob.lagrangian(z.detach(), y.detach(), 0.9).item() - Lo) <= 1e-12 * Lm
     L = lagrangian(prob, z, y, A, B, g)
-    (gA,) = torch.autograd.grad(L, A, create_graph=True)
-    with pytest.raises(NotImplementedError):
-        gA.sum().backward()
+    (dA,) = torch.autograd.grad(L, A, create_graph=True)
+    with pytest.raises(NotImplementedError):  # a graph for third derivatives
+        torch.autograd.grad(dA.sum(), z, create_graph=True)
     prob.close()
 
 
