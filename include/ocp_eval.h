@@ -618,7 +618,10 @@ int ocp_batch_autotune(ocp_batch *b, int32_t what, const double *z, const double
 int ocp_batch_autotune_io(ocp_batch *b, int32_t what, const ocp_batch_io *io, int32_t reps,
                           hipStream_t stream, ocp_batch_config *best, float *best_ms, float *all_ms);
 
-/* Message describing the last error on the calling thread ("" if none). */
+/* Message describing the last error on the calling thread ("" if none).
+ * With the environment variable OCP_VERBOSE set (to anything but "" or "0")
+ * when the library first records an error, every error is also printed to
+ * stderr as "[ocp] error <code>: <message>". */
 const char *ocp_last_error(void);
 
 #ifdef __cplusplus

@@ -5,6 +5,7 @@
 // iteration (paper Sec. 6).  No HIP call is made here.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -15,9 +16,21 @@ namespace ocp {
 
 static thread_local std::string g_err;
 
+// OCP_VERBOSE (environment, read once): set to anything but "" or "0", every
+// error the library records is also printed to stderr with its code.
+static bool verbose()
+{
+    static const bool v = [] {
+        const char *e = std::getenv("OCP_VERBOSE");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return v;
+}
+
 int fail(int code, const std::string &msg)
 {
     g_err = msg;
+    if (verbose()) std::fprintf(stderr, "[ocp] error %d: %s\n", code, msg.c_str());
     return code;
 }
 

@@ -5,12 +5,16 @@ bit for bit."""
 from __future__ import annotations
 
 import ctypes
+import os
 import re
+import sys
 
 import numpy as np
 import pytest
 
 import paper_2510_03932_amd as ocp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 GRID = [(1, 1, 0), (1, 1, 1), (2, 1, 0), (3, 2, 0), (2, 2, 1), (5, 3, 0), (4, 3, 1), (3, 4, 2),
         (7, 5, 3), (10, 6, 3), (1, 16, 8), (33, 16, 8), (17, 32, 32), (1000, 4, 2), (999, 8, 4)]
@@ -349,3 +353,24 @@ def test_quad_pattern_and_kkt_partial_outputs_match_full():
     full = ocp.quad_kkt_pattern(40, 1)
     assert ci is None and ph is None
     assert np.array_equal(rp, full[0]) and np.array_equal(pj, full[2])
+
+
+def test_verbose_errors_go_to_stderr(tmp_path):
+    """OCP_VERBOSE=1 echoes every recorded error to stderr; unset, nothing is
+    printed (a child process, since the variable is read once)."""
+    import subprocess
+    import textwrap
+    script = textwrap.dedent("""
+        import ctypes, sys
+        sys.path.insert(0, %r)
+        import paper_2510_03932_amd as ocp
+        s = ocp.Sizes()
+        rc = ocp.lib().ocp_sizes(0, 4, 2, ctypes.byref(s))
+        print("rc", rc)
+    """ % ROOT)
+    env = dict(os.environ, OCP_VERBOSE="1")
+    on = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=120)
+    assert "rc 1" in on.stdout and "[ocp] error 1: N must be >= 1" in on.stderr, on.stderr
+    env.pop("OCP_VERBOSE")
+    off = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=120)
+    assert "rc 1" in off.stdout and "[ocp]" not in off.stderr
