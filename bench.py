@@ -688,8 +688,8 @@ def main():
     ap.add_argument("--N", type=int, default=None, help="override the interval count")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the path shards by node range across GPUs but no multi-GPU run is provided",
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the evaluation "
+              "path would shard by node range across GPUs, but no multi-GPU run is provided",
               file=sys.stderr)
         sys.exit(2)
 
