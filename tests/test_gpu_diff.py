@@ -421,6 +421,23 @@ def test_coef_mixed_many_chunks_per_workgroup(ocp, N, n, m, scheme):
     prob.close()
 
 
+@pytest.mark.parametrize("N,n,m,scheme,bnd", [(1, 1, 0, 0, 0), (5, 1, 0, 1, 2), (3, 2, 1, 0, 1), (2, 1, 3, 1, 0)])
+def test_coef_mixed_degenerate_shapes(ocp, N, n, m, scheme, bnd):
+    """One or two intervals, one state (gamma's partner is the state itself:
+    the product X_i X_p(i) is X_i^2), no controls."""
+    _say(f"[coef mixed] N={N} n={n} m={m} scheme={scheme} bnd={bnd}")
+    inst = synth.make_instance(N, n, m, seed=29, scheme=scheme, bnd=bnd)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    v = np.random.default_rng(N + 10 * n).normal(size=len(inst.z))
+    z, y, vt = (torch.from_numpy(a).to(dev) for a in (inst.z, inst.y, v))
+    for got, (want, mu) in ((prob.coef_mixed(z, y, vt), oracle.coef_mixed_ex(inst, v, scheme, bnd)),
+                            (prob.coef_grad(z, y), oracle.coef_grad_ex(inst, scheme, bnd))):
+        for g, w, u, what in zip(got, want, mu, ("A", "B", "gamma")):
+            check_close(g.cpu().numpy().ravel(), w.ravel(), u.ravel(), what=f"{what} {N},{n},{m}")
+    prob.close()
+
+
 def test_coef_mixed_rejects_quadrotor_and_null(ocp):
     q = synth.make_quadrotor(8, seed=0, bnd=1)
     dev = torch.device("cuda", 0)
