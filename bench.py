@@ -442,7 +442,8 @@ def differentiation(torch, ocp, synth, reps=20):
 def euler(torch, ocp, synth, reps=10):
     """Forward-Euler transcription with initial- and final-state rows, at the
     large shape (N = 1e6, n = 16, m = 8): cons, jac, hess and assemble_kkt
-    timed with HIP events, against their algorithmic bytes."""
+    timed with HIP events, against their algorithmic bytes, each repeated
+    back to back and all four in sequence as a step (`in_step`)."""
     N, n, m = synth.LARGE
     dev = torch.device("cuda", 0)
     inst = synth.make_instance(N, n, m, seed=0, scheme=1, bnd=2)
@@ -481,6 +482,29 @@ def euler(torch, ocp, synth, reps=10):
                      "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
     t = (out["eval_jac"]["ms"] + out["eval_hess"]["ms"]) * 1e-3
     out["jac_hess_nnz_per_s"] = (s["nnzj"] + s["nnzh"]) / t
+    # the four calls in sequence as one step (HIP events between them), as
+    # the headline times its step; the figures above are each call repeated
+    # back to back
+    names = list(calls)
+    for _ in range(2):
+        for nm in names:
+            calls[nm][0]()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(reps)]
+    for ev in evs:
+        ev[0].record()
+        for i, nm in enumerate(names):
+            calls[nm][0]()
+            ev[i + 1].record()
+    torch.cuda.synchronize()
+    in_step = {}
+    for i, nm in enumerate(names):
+        ms = float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in evs]))
+        in_step[nm] = {"ms": round(ms, 4), "hbm_frac": round(calls[nm][1] / (ms * 1e-3) / HBM_PEAK, 4)}
+    in_step["step_ms"] = round(float(np.mean([ev[0].elapsed_time(ev[-1]) for ev in evs])), 4)
+    t = (in_step["eval_jac"]["ms"] + in_step["eval_hess"]["ms"]) * 1e-3
+    in_step["jac_hess_nnz_per_s"] = (s["nnzj"] + s["nnzh"]) / t
+    out["in_step"] = in_step
     # the fused evaluation into the KKT values (no reg), against the separate
     # eval_jac + eval_hess + assemble_kkt above
     fn = lambda: prob.eval_kkt(z, y, 1.0, None, out=kkt)

@@ -205,8 +205,8 @@ __device__ __forceinline__ void jac_column(const KP &P, const double *__restrict
 // with no arithmetic at all against 73 % with ordinary ones.  The lines are
 // then written back during the next kernel (in an interior-point step the
 // assembly, which reads these values).  The batched kernel and the forward
-// Euler kernel keep non-temporal stores (measured no better, or worse, with
-// ordinary ones).
+// Euler kernel keep non-temporal stores (with ordinary ones their steps
+// measured the same or slower).
 // ---------------------------------------------------------------------------
 template <int NB, bool NT>
 __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict__ z,
