@@ -49,7 +49,10 @@ using namespace ocp::dev;
 namespace {
 
 constexpr int kObjTile = 256;  // nodes per objective tile (the single-instance workgroup)
-constexpr int kMasks = 64;     // evaluation masks 1 .. OCP_EVAL_ALL
+constexpr int kMasks = 256;    // tile-list keys: evaluation masks 1 .. OCP_EVAL_ALL and the two KKT keys below
+// Tile-list keys of the two KKT groups (outside the OCP_EVAL_* bits): the
+// defect-row tiles (with the boundary rows), and the variable-row tiles.
+constexpr int kListKktDef = 64, kListKktVar = 128;
 
 // One instance's place in the packed arrays (device copy of the offset table).
 struct InstDesc {
@@ -215,22 +218,22 @@ __global__ __launch_bounds__(BS) void batch_kernel(BP bp, KKTLayout Lo, const In
             break;
         }
         case kKktDef:
-            if (!(KINDS & OCP_EVAL_KKT)) break;
+            if (!(KINDS & (OCP_EVAL_KKT | kListKktDef))) break;
             kkt_defect_tile<BS>(P, Lo, zb, reg_ ? reg_ + id.dim_off : nullptr, kkt_ + id.kkt_off, td.k0,
                                 bp.defect_lg, lds);
             break;
         case kKktVar:
-            if (!(KINDS & OCP_EVAL_KKT)) break;
+            if (!(KINDS & (OCP_EVAL_KKT | kListKktVar))) break;
             kkt_var_tile<NB, BS>(P, Lo, zb, y_ + id.c_off, sigma, reg_ ? reg_ + id.dim_off : nullptr,
                                  kkt_ + id.kkt_off, td.k0, vbuf);
             break;
         case kBnd: {
             const int b = tid;
-            if ((KINDS & (OCP_EVAL_CONS | OCP_EVAL_JAC | OCP_EVAL_KKT)) && b < P.nb) {
+            if ((KINDS & (OCP_EVAL_CONS | OCP_EVAL_JAC | OCP_EVAL_KKT | kListKktDef)) && b < P.nb) {
                 if ((KINDS & OCP_EVAL_CONS) && (what & OCP_EVAL_CONS))
                     cons_[id.c_off + (int64_t)P.n * P.N + b] = bnd_value(P, zb, b);
                 if ((KINDS & OCP_EVAL_JAC) && (what & OCP_EVAL_JAC)) jac_[id.jac_off + (int64_t)P.n * P.N * P.T + b] = 1.0;
-                if ((KINDS & OCP_EVAL_KKT) && (what & OCP_EVAL_KKT))
+                if ((KINDS & (OCP_EVAL_KKT | kListKktDef)) && (what & OCP_EVAL_KKT))
                     kkt_bnd_row(P, Lo, reg_ ? reg_ + id.dim_off : nullptr, kkt_ + id.kkt_off, b);
             }
             break;
@@ -332,11 +335,12 @@ static std::vector<TileDesc> build_tiles(const ocp_batch &b, const ocp_batch_con
             for (int64_t k0 = 0; k0 <= N; k0 += c.block) put(k0, kGrad, 1, 0);
         if (what & OCP_EVAL_OBJ)
             for (int64_t k0 = 0; k0 <= N; k0 += kObjTile) put(k0, kObj, 1, 0);
-        if (what & OCP_EVAL_KKT) {
+        if (what & (OCP_EVAL_KKT | kListKktDef))
             for (int64_t k0 = 0; k0 < N; k0 += (int64_t)1 << b.bp.defect_lg) put(k0, kKktDef, 1, 0);
+        if (what & (OCP_EVAL_KKT | kListKktVar))
             for (int64_t k0 = 0; k0 <= N; k0 += c.block) put(k0, kKktVar, 1, 0);
-        }
-        if (b.shape.nb > 0 && (what & (OCP_EVAL_CONS | OCP_EVAL_JAC | OCP_EVAL_KKT))) put(0, kBnd, 1, 0);
+        if (b.shape.nb > 0 && (what & (OCP_EVAL_CONS | OCP_EVAL_JAC | OCP_EVAL_KKT | kListKktDef)))
+            put(0, kBnd, 1, 0);
     }
     return t;
 }
@@ -376,7 +380,8 @@ static int tile_list(const ocp_batch *b, int what, TileList *out)
 }
 
 // Switch to a new config: every cached tile list is dropped (after the device
-// has finished any work that may read them) and the JAC|HESS list rebuilt.
+// has finished any work that may read them) and the Jacobian and Hessian
+// lists rebuilt.
 static int set_cfg(ocp_batch *b, const ocp_batch_config &c)
 {
     hipError_t e = hipDeviceSynchronize();
@@ -387,7 +392,8 @@ static int set_cfg(ocp_batch *b, const ocp_batch_config &c)
         b->cfg = c;
     }
     TileList l;
-    return tile_list(b, OCP_EVAL_JAC | OCP_EVAL_HESS, &l);
+    if (int rc = tile_list(b, OCP_EVAL_JAC, &l)) return rc;
+    return tile_list(b, OCP_EVAL_HESS, &l);
 }
 
 static BIO to_bio(const ocp_batch *b, const ocp_batch_io &io)
@@ -407,12 +413,26 @@ static BIO to_bio(const ocp_batch *b, const ocp_batch_io &io)
     return d;
 }
 
-// The kernel groups: Jacobian and Hessian values; objective, gradient and
-// defects; the fused KKT values.
-constexpr int kKindsJH = OCP_EVAL_JAC | OCP_EVAL_HESS;
-constexpr int kKindsLight = OCP_EVAL_OBJ | OCP_EVAL_GRAD | OCP_EVAL_CONS;
-constexpr int kKindsKKT = OCP_EVAL_KKT;
-constexpr int kGroups[3] = {kKindsJH, kKindsLight, kKindsKKT};
+// The kernel groups, one launch each: Jacobian values; Hessian values;
+// objective and gradient; defects; the defect rows of the fused KKT values;
+// their variable rows.  Each group is its own kernel, so it gets the
+// registers of its own tile bodies: in one kernel, tile kinds take the
+// registers of the heaviest (at n <= 8 the two KKT kinds together 127 VGPRs
+// against 73 and 110 apart, the defects 111 against 39 for the objective
+// and gradient), and the light tiles run at that residency.  kGroupKinds
+// holds each group's tile kinds, kGroupBits the evaluation bits it serves.
+constexpr int kNumGroups = 6;
+constexpr int kGroupKinds[kNumGroups] = {OCP_EVAL_JAC, OCP_EVAL_HESS, OCP_EVAL_OBJ | OCP_EVAL_GRAD,
+                                         OCP_EVAL_CONS, kListKktDef, kListKktVar};
+constexpr int kGroupBits[kNumGroups] = {OCP_EVAL_JAC, OCP_EVAL_HESS, OCP_EVAL_OBJ | OCP_EVAL_GRAD,
+                                        OCP_EVAL_CONS, OCP_EVAL_KKT, OCP_EVAL_KKT};
+
+// The tile-list key of group g for the evaluation mask `what`: the bits it
+// serves, or its own key for the two KKT groups.
+static int group_key(int g, int what)
+{
+    return kGroupKinds[g] & (kListKktDef | kListKktVar) ? kGroupKinds[g] : (what & kGroupBits[g]);
+}
 
 template <int BS, int KINDS, int SCHEME>
 static void launch_batch_scheme(const ocp_batch *b, const TileDesc *tiles, int ntiles, int what, const BIO &io,
@@ -421,7 +441,9 @@ static void launch_batch_scheme(const ocp_batch *b, const TileDesc *tiles, int n
     const int cap = b->cfg.wgs_per_cu > 0 ? b->cus * b->cfg.wgs_per_cu : ntiles;
     const unsigned grid = (unsigned)std::max(1, std::min(ntiles, cap));
     const bool pair_ok = ((uintptr_t)io.jac % 16 == 0);
-    const size_t lds = (what & OCP_EVAL_KKT) ? kkt_defect_lds(b->n, b->m, b->shape.T, 1 << b->bp.defect_lg) * sizeof(double) : 0;
+    const size_t lds = ((KINDS & kListKktDef) && (what & OCP_EVAL_KKT))
+                           ? kkt_defect_lds(b->n, b->m, b->shape.T, 1 << b->bp.defect_lg) * sizeof(double)
+                           : 0;
     const int n = b->n;
     if (n <= 4)
         hipLaunchKernelGGL((batch_kernel<4, BS, KINDS, SCHEME>), dim3(grid), dim3(BS), lds, s, b->bp, b->Lo, b->inst, tiles, ntiles, what, pair_ok, io.z, io.y, io.reg, io.sigma, io.grad, io.cons, io.jac, io.hess, io.kkt, io.parts);
@@ -446,9 +468,14 @@ template <int BS>
 static void launch_batch_bs(const ocp_batch *b, int g, const TileDesc *tiles, int ntiles, int what,
                             const BIO &io, hipStream_t s)
 {
-    if (g == 0) launch_batch_kinds<BS, kKindsJH>(b, tiles, ntiles, what, io, s);
-    else if (g == 1) launch_batch_kinds<BS, kKindsLight>(b, tiles, ntiles, what, io, s);
-    else launch_batch_kinds<BS, kKindsKKT>(b, tiles, ntiles, what, io, s);
+    switch (g) {
+    case 0: launch_batch_kinds<BS, kGroupKinds[0]>(b, tiles, ntiles, what, io, s); break;
+    case 1: launch_batch_kinds<BS, kGroupKinds[1]>(b, tiles, ntiles, what, io, s); break;
+    case 2: launch_batch_kinds<BS, kGroupKinds[2]>(b, tiles, ntiles, what, io, s); break;
+    case 3: launch_batch_kinds<BS, kGroupKinds[3]>(b, tiles, ntiles, what, io, s); break;
+    case 4: launch_batch_kinds<BS, kGroupKinds[4]>(b, tiles, ntiles, what, io, s); break;
+    default: launch_batch_kinds<BS, kGroupKinds[5]>(b, tiles, ntiles, what, io, s); break;
+    }
 }
 
 static int check_eval_args(const ocp_batch *b, int32_t what, int32_t mode, const ocp_batch_io *io,
@@ -503,16 +530,15 @@ static KP host_kp(const ocp_batch *b, int32_t i)
 // The tile lists of one persistent evaluation: one per kernel group that
 // `what` touches (an empty list where it touches none).
 struct Plan {
-    TileList g[3];
+    TileList g[kNumGroups];
 };
 
 static int plan_of(const ocp_batch *b, int32_t what, Plan *out)
 {
-    for (int g = 0; g < 3; g++) {
+    for (int g = 0; g < kNumGroups; g++) {
         out->g[g] = TileList{};
-        const int sub = what & kGroups[g];
-        if (sub)
-            if (int rc = tile_list(b, sub, &out->g[g])) return rc;
+        if (what & kGroupBits[g])
+            if (int rc = tile_list(b, group_key(g, what), &out->g[g])) return rc;
     }
     return OCP_OK;
 }
@@ -524,8 +550,8 @@ static int batch_launch(const ocp_batch *b, const Plan &plan, int32_t what, int3
 {
     if (mode == OCP_BATCH_PERSISTENT) {
         const BIO d = to_bio(b, io);
-        for (int g = 0; g < 3; g++) {
-            const int sub = what & kGroups[g];
+        for (int g = 0; g < kNumGroups; g++) {
+            const int sub = what & kGroupBits[g];
             if (!sub) continue;
             const TileList &l = plan.g[g];
             if (b->cfg.block == 128) launch_batch_bs<128>(b, g, l.d, l.n, sub, d, s);
@@ -808,7 +834,7 @@ int ocp_batch_graph_create_io(const ocp_batch *b, int32_t what, int32_t mode, co
         for (const TileList &l : plan.g) total += (size_t)l.n;
         hipError_t e = hipMalloc(&g->tiles, std::max<size_t>(total, 1) * sizeof(TileDesc));
         size_t at = 0;
-        for (int k = 0; k < 3 && e == hipSuccess; k++) {
+        for (int k = 0; k < kNumGroups && e == hipSuccess; k++) {
             const TileList &l = plan.g[k];
             if (!l.n) continue;
             e = hipMemcpy(g->tiles + at, l.d, (size_t)l.n * sizeof(TileDesc), hipMemcpyDeviceToDevice);
