@@ -719,7 +719,7 @@ int ocp_batch_create_ex(int32_t count, const int64_t *Ns, int32_t n, int32_t m, 
     b->bp.BT = b->bp.AT + nAT;
     b->Lo = kkt_layout(n);
     TileList l;
-    rc = tile_list(b, OCP_EVAL_JAC | OCP_EVAL_HESS, &l);
+    rc = tile_list(b, OCP_EVAL_JAC, &l);
     if (rc) {
         std::string msg = ocp_last_error();
         ocp_batch_destroy(b);
