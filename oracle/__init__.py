@@ -355,6 +355,60 @@ class Oracle:
         gg, mg = -w * np.sum(Y * QG, axis=1), w * np.sum(Ya * QGm, axis=1)
         return (gA, gB, gg), (mA, mB, mg)
 
+    def coef_adjoint_ex(self, inst, tA, tB, tg, scheme=0, bnd=0, y=None):
+        """The adjoint of the coefficient gradient: for cotangents tA (n, n),
+        tB (n, m), tg (n,) of (dL/dA, dL/dB, dL/dgamma), the gradients in z
+        and in y of  t . dL/dtheta = sum tA * dL/dA + sum tB * dL/dB + tg . dL/dgamma,
+        as ((gz, gy), (mu_z, mu_y)).  The defects are linear in theta, so
+        t . dL/dtheta = sum_ik y_ik D_ik, D being the defects' theta part with
+        theta := t: with Fb = tA sin X + tB U + tg * (X_i X_p) at each node
+        (p = (i+1) mod n),
+          trapezoidal  D_ik = -h/2 (Fb_ik + Fb_i,k+1),   Euler  D_ik = -h Fb_ik.
+        Hence gy = D on the defect rows and 0 on the boundary rows (which do
+        not depend on theta); and with the node multipliers Yt (trapezoidal
+        -h/2 (y_i,k-1 + y_ik), Euler -h y_ik, the missing neighbours zero)
+          gz on X_jk = cos X_jk (tA^T Yt)_jk + Yt_jk tg_j X_p(j)k + Yt_qk tg_q X_qk,
+          gz on U_lk = (tB^T Yt)_lk,
+        q = (j-1) mod n being the row whose bilinear partner is j.  Paper
+        Sec. 8 names differentiable programming as future work; the defects
+        follow Sec. 3."""
+        N, n, m = inst.N, inst.n, inst.m
+        y = _d(inst.y if y is None else y)
+        tA, tB, tg = _d(tA).reshape(n, n), _d(tB).reshape(n, m), _d(tg).reshape(n)
+        NU = N + 1 if scheme == 0 else N
+        X = _d(inst.z[:n * (N + 1)]).reshape(n, N + 1)
+        U = _d(inst.z[n * (N + 1):]).reshape(m, NU)
+        Y = y[:n * N].reshape(n, N)
+        p = (np.arange(n) + 1) % n
+        q = (np.arange(n) - 1) % n
+        S, C, P = np.sin(X), np.cos(X), X * X[p]
+        aA, aB, ag = np.abs(tA), np.abs(tB), np.abs(tg)
+        Fs, Fsm = tA @ S + tg[:, None] * P, aA @ np.abs(S) + ag[:, None] * np.abs(P)
+        Fu, Fum = tB @ U, aB @ np.abs(U)
+        Yt, Ya = np.zeros((n, N + 1)), np.zeros((n, N + 1))
+        if scheme == 0:
+            w = 0.5 * (1.0 / N)
+            Fb, Fbm = Fs + Fu, Fsm + Fum
+            D, Dm = -w * (Fb[:, :N] + Fb[:, 1:]), w * (Fbm[:, :N] + Fbm[:, 1:])
+            Yt[:, :N] += Y
+            Yt[:, 1:] += Y
+            Ya[:, :N] += np.abs(Y)
+            Ya[:, 1:] += np.abs(Y)
+        else:
+            w = 1.0 / N
+            D, Dm = -w * (Fs[:, :N] + Fu), w * (Fsm[:, :N] + Fum)
+            Yt[:, :N] = Y
+            Ya[:, :N] = np.abs(Y)
+        Yt, Ya = -w * Yt, w * Ya
+        B1, B1m = Yt * tg[:, None] * X, Ya * ag[:, None] * np.abs(X)
+        gX = C * (tA.T @ Yt) + Yt * tg[:, None] * X[p] + B1[q]
+        mX = np.abs(C) * (aA.T @ Ya) + Ya * ag[:, None] * np.abs(X[p]) + B1m[q]
+        gU, mU = tB.T @ Yt[:, :NU], aB.T @ Ya[:, :NU]
+        nb = len(y) - n * N
+        gz, mz = np.concatenate([gX.ravel(), gU.ravel()]), np.concatenate([mX.ravel(), mU.ravel()])
+        gy, my = np.concatenate([D.ravel(), np.zeros(nb)]), np.concatenate([Dm.ravel(), np.zeros(nb)])
+        return (gz, gy), (mz, my)
+
     # ---- schemes (0 trapezoidal, 1 forward Euler) and boundary rows --------
     def sizes_ex(self, N, n, m, scheme=0, bnd=0) -> dict:
         out = np.zeros(10, np.int64)
@@ -602,6 +656,7 @@ hvp_ex = DEFAULT.hvp_ex
 jvp_ex = DEFAULT.jvp_ex
 coef_grad_ex = DEFAULT.coef_grad_ex
 coef_mixed_ex = DEFAULT.coef_mixed_ex
+coef_adjoint_ex = DEFAULT.coef_adjoint_ex
 sizes_ex = DEFAULT.sizes_ex
 obj_ex = DEFAULT.obj_ex
 grad_ex = DEFAULT.grad_ex

@@ -1,6 +1,7 @@
 """Plant plausible mistakes in the oracle's Python-level derivative
 compositions (grad_z L = sigma grad f + J^T y, H v from the lower triangle,
-J v, and the coefficient gradient as matrix products) and check that the pins
+J v, the coefficient gradient, its mixed derivative and its adjoint as
+matrix products) and check that the pins
 of tests/test_oracle_diff_ex_pins.py catch every one, as the C-level mutation
 test does for the C oracle."""
 from __future__ import annotations
@@ -117,6 +118,45 @@ def _mixed_mutant(kind):
     return coef_mixed_ex
 
 
+def _adjoint_mutant(kind):
+    """A copy of coef_adjoint_ex with one planted mistake."""
+    def coef_adjoint_ex(self, inst, tA, tB, tg, scheme=0, bnd=0, y=None):
+        N, n, m = inst.N, inst.n, inst.m
+        y = np.asarray(inst.y if y is None else y, dtype=float)
+        tA, tB, tg = (np.asarray(t, dtype=float) for t in (tA, tB, tg))
+        tA, tB = tA.reshape(n, n), tB.reshape(n, m)
+        NU = N + 1 if scheme == 0 else N
+        Xv = np.asarray(inst.z[:n * (N + 1)], dtype=float).reshape(n, N + 1)
+        U = np.asarray(inst.z[n * (N + 1):], dtype=float).reshape(m, NU)
+        Y = y[:n * N].reshape(n, N)
+        p = (np.arange(n) + 1) % n
+        q = p if kind == "partner row" else (np.arange(n) - 1) % n
+        Fs, Fu = tA @ np.sin(Xv) + tg[:, None] * Xv * Xv[p], tB @ U
+        Yt = np.zeros((n, N + 1))
+        if scheme == 0:
+            w = 0.5 * (1.0 / N)
+            Fb = Fs + Fu
+            D = -w * Fb[:, :N] if kind == "right node dropped" else -w * (Fb[:, :N] + Fb[:, 1:])
+            Yt[:, :N] += Y
+            Yt[:, 1:] += Y
+        else:
+            w = 1.0 / N
+            D = -w * (Fs[:, :N] + Fu)
+            if kind == "euler next node":
+                Yt[:, 1:] = Y
+            else:
+                Yt[:, :N] = Y
+        Yt = -w * Yt
+        C = np.sin(Xv) if kind == "sine" else np.cos(Xv)
+        gX = C * (tA.T @ Yt) + Yt * tg[:, None] * Xv[p] + (Yt * tg[:, None] * Xv)[q]
+        gU = tB.T @ Yt[:, :NU]
+        nb = len(y) - n * N
+        gz, gy = np.concatenate([gX.ravel(), gU.ravel()]), np.concatenate([D.ravel(), np.zeros(nb)])
+        big = lambda a: np.abs(a) + 1e-300
+        return (gz, gy), (big(gz), big(gy))
+    return coef_adjoint_ex
+
+
 # (name, attribute of the oracle module or of its Oracle class, replacement)
 MUTATIONS = [
     ("grad_z L without sigma", "_grad_plus_jt_y", _jt_y_no_sigma),
@@ -132,6 +172,10 @@ MUTATIONS = [
     ("mixed derivative with one product-rule term", "Oracle.coef_mixed_ex", _mixed_mutant("one product term")),
     ("mixed derivative without the left node", "Oracle.coef_mixed_ex", _mixed_mutant("right node only")),
     ("mixed derivative at the next node under Euler", "Oracle.coef_mixed_ex", _mixed_mutant("euler next node")),
+    ("adjoint with the partner's row for the bilinear term", "Oracle.coef_adjoint_ex", _adjoint_mutant("partner row")),
+    ("adjoint with sin for cos", "Oracle.coef_adjoint_ex", _adjoint_mutant("sine")),
+    ("adjoint defects without the right node", "Oracle.coef_adjoint_ex", _adjoint_mutant("right node dropped")),
+    ("adjoint multipliers at the next node under Euler", "Oracle.coef_adjoint_ex", _adjoint_mutant("euler next node")),
 ]
 
 # pins, each a call that raises when the oracle is wrong
@@ -145,6 +189,8 @@ PINS = [
     lambda orc: X.test_coef_grad_ex_complex_step(orc, 5, 3, 2, 1, 2),
     lambda orc: X.test_coef_mixed_ex_high_precision_differences(orc, 4, 3, 2, 0, 1),
     lambda orc: X.test_coef_mixed_ex_high_precision_differences(orc, 4, 3, 2, 1, 0),
+    lambda orc: X.test_coef_adjoint_ex_high_precision(orc, 3, 3, 2, 0, 1),
+    lambda orc: X.test_coef_adjoint_ex_high_precision(orc, 3, 3, 1, 1, 2),
     lambda orc: X.test_quad_lag_grad_complex_step(orc, 2, 1),
     lambda orc: X.test_quad_hvp_mixed_difference(orc, 2, 1),
     lambda orc: X.test_quad_jvp_complex_step(orc, 2, 1),

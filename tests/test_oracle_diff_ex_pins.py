@@ -197,6 +197,94 @@ def test_coef_mixed_ex_linear_in_v_and_zero_without_state_direction(orc):
     check_close(b.ravel(), bw.ravel(), mbw.ravel(), rel=1e-13, what="B part = dL/dB with U := V_U")
 
 
+def _cotangents(n, m, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(n, n)), rng.normal(size=(n, m)), rng.normal(size=n)
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+@pytest.mark.parametrize("N,n,m", [(3, 3, 2), (3, 1, 1), (2, 2, 0), (2, 4, 1)])
+def test_coef_adjoint_ex_high_precision(orc, N, n, m, scheme, bnd):
+    """L is affine in theta, so t . dL/dtheta = L(theta + t) - L(theta)
+    exactly.  From 50-digit evaluations of the definition module, its
+    derivative in y_r is c_r(theta + t) - c_r(theta) and its derivative in
+    z_a is a central difference at step 1e-20 (exact far below double
+    rounding)."""
+    import mpmath
+    mpmath.mp.dps = 50
+    inst = _inst(N, n, m, 280 + 5 * N + n, scheme, bnd)
+    tA, tB, tg = _cotangents(n, m, 41 + N + n)
+    (gz, gy), (mz, my) = orc.coef_adjoint_ex(inst, tA, tB, tg, scheme, bnd)
+    mp = mpmath.mpf
+    A, B, g, q, r = defn.as_lists(inst)
+    cv = lambda x: [mp(float(t)) for t in x]
+    A0, B0, g0 = [cv(a) for a in A], [cv(b) for b in B], cv(g)
+    A1 = [[a + mp(float(t)) for a, t in zip(ra, rt)] for ra, rt in zip(A0, tA)]
+    B1 = [[b + mp(float(t)) for b, t in zip(rb, rt)] for rb, rt in zip(B0, tB)]
+    g1 = [a + mp(float(t)) for a, t in zip(g0, tg)]
+    z0, yy, qq, rr = cv(inst.z), cv(inst.y), cv(q), cv(r)
+    dt = mp(1) / N
+
+    def tdot(z):
+        L = lambda A_, B_, g_: defn.lagrangian_ex(z, yy, mp(float(inst.sigma)), N, n, m, A_, B_, g_, qq, rr,
+                                                  scheme, bnd, sin=mpmath.sin, dt=dt)
+        return L(A1, B1, g1) - L(A0, B0, g0)
+
+    eps = mp("1e-20")
+    want_z = []
+    for a in range(len(z0)):
+        zp, zm = z0[:], z0[:]
+        zp[a] += eps
+        zm[a] -= eps
+        want_z.append(float((tdot(zp) - tdot(zm)) / (2 * eps)))
+    c = lambda A_, B_, g_: defn.constraints_ex(z0, N, n, m, A_, B_, g_, scheme, bnd, sin=mpmath.sin, dt=dt)
+    want_y = [float(a - b) for a, b in zip(c(A1, B1, g1), c(A0, B0, g0))]
+    # the differences resolve 1e-50 / 1e-20: entries that are exactly zero
+    # (Euler's last node carries no multiplier) come out near 1e-30, so the
+    # bound gets an absolute floor of 1e-29 (1e-16 in units of mu)
+    check_close(gz, np.array(want_z), mz + 1e-16, rel=1e-13, what=f"adjoint in z scheme={scheme} bnd={bnd}")
+    check_close(gy, np.array(want_y), my, rel=1e-13, what=f"adjoint in y scheme={scheme} bnd={bnd}")
+
+
+@pytest.mark.parametrize("scheme,bnd", CASES)
+def test_coef_adjoint_ex_is_the_transpose_of_coef_grad_and_mixed(orc, scheme, bnd):
+    """<gy, w> = t . dL/dtheta at multipliers w (dL/dtheta is linear in y),
+    and <gz, v> = t . (the coefficient gradient's derivative along v): the
+    adjoint is the transpose of the two node contractions, evaluated by the
+    oracle's own coefficient gradient and mixed derivative."""
+    inst = _inst(50, 5, 3, 290 + 3 * scheme + bnd, scheme, bnd)
+    tA, tB, tg = _cotangents(5, 3, 43)
+    (gz, gy), (mz, my) = orc.coef_adjoint_ex(inst, tA, tB, tg, scheme, bnd)
+    rng = np.random.default_rng(44)
+    w, v = rng.normal(size=len(inst.y)), rng.normal(size=len(inst.z))
+    tdot = lambda parts: float(np.sum(tA * parts[0]) + np.sum(tB * parts[1]) + np.dot(tg, parts[2]))
+    mdot = lambda parts: float(np.sum(np.abs(tA) * parts[0]) + np.sum(np.abs(tB) * parts[1])
+                               + np.dot(np.abs(tg), parts[2]))
+    cg, cgm = orc.coef_grad_ex(inst, scheme, bnd, y=w)
+    assert abs(np.dot(gy, w) - tdot(cg)) <= 1e-12 * (np.dot(my, np.abs(w)) + mdot(cgm))
+    cm, cmm = orc.coef_mixed_ex(inst, v, scheme, bnd)
+    assert abs(np.dot(gz, v) - tdot(cm)) <= 1e-12 * (np.dot(mz, np.abs(v)) + mdot(cmm))
+
+
+@pytest.mark.parametrize("N,n,m", [(40, 3, 2), (1, 1, 0), (17, 5, 1)])
+def test_coef_adjoint_ex_affine_identity_through_c_oracle(orc, N, n, m):
+    """With sigma = 0, grad_z L = J^T y, and J depends affinely on theta: the
+    adjoint in z is J(t)^T y - J(0)^T y and the adjoint in y is
+    c(t) - c(0), both from the C oracle's trapezoidal functions with the
+    coefficients replaced by the cotangents and by zeros."""
+    inst = _inst(N, n, m, 300 + N, 0, 0)
+    tA, tB, tg = _cotangents(n, m, 45 + N)
+    (gz, gy), (mz, my) = orc.coef_adjoint_ex(inst, tA, tB, tg, 0, 0)
+    with_t = types.SimpleNamespace(**{k: getattr(inst, k) for k in ("N", "n", "m", "z", "y", "q", "r")})
+    with_0 = types.SimpleNamespace(**vars(with_t))
+    with_t.A, with_t.B, with_t.gamma = tA, tB, tg
+    with_0.A, with_0.B, with_0.gamma = np.zeros_like(tA), np.zeros_like(tB), np.zeros_like(tg)
+    (g1, m1), (g0, m0) = orc.lag_grad(with_t, sigma=0.0), orc.lag_grad(with_0, sigma=0.0)
+    check_close(gz, g1 - g0, mz + 4 * np.finfo(float).eps * (m1 + m0), rel=1e-12, what="J(t)^T y - J(0)^T y")
+    (c1, n1), (c0, n0) = orc.cons(with_t), orc.cons(with_0)
+    check_close(gy, c1 - c0, my + 4 * np.finfo(float).eps * (n1 + n0), rel=1e-12, what="c(t) - c(0)")
+
+
 @pytest.mark.parametrize("N,n,m", [(300, 4, 2), (1, 1, 0), (64, 6, 3)])
 def test_trapezoidal_composites_equal_c_oracle(orc, N, n, m):
     """Without boundary rows the trapezoidal composites and the C oracle's
