@@ -386,6 +386,8 @@ def differentiation(torch, ocp, synth, reps=20):
         "jvp": (lambda: prob.jvp(z, v, out=jv), 8 * (nx + nv + nc)),
         "coef_grad": (lambda: prob.coef_grad(z, y, out=cg), 8 * (nv + nc)),
         "coef_mixed": (lambda: prob.coef_mixed(z, y, v, out=cg), 8 * (nx + nv + nc)),
+        # cotangents: the coefficient-shaped outputs the calls above leave in cg
+        "coef_adjoint": (lambda: prob.coef_adjoint(z, y, *cg, out_z=hv, out_y=jv), 8 * (2 * nv + 2 * nc)),
     }
     out = {"workload": f"N={N} n={n} m={m}, seed 0"}
     # the autograd pass first: it is timed on the host clock, and HIP graph

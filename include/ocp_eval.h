@@ -362,6 +362,25 @@ int ocp_eval_coef_grad(const ocp_problem *p, const double *z, const double *y, d
 int ocp_eval_coef_mixed(const ocp_problem *p, const double *z, const double *y, const double *v, double *gA,
                         double *gB, double *ggamma, hipStream_t stream);
 
+/* The adjoint of the coefficient gradient: for cotangents tA (n x n
+ * row-major), tB (n x m; may be NULL when m = 0) and tgamma (n) of
+ * (dL/dA, dL/dB, dL/dgamma), the gradients of
+ *   t . dL/dtheta = sum tA_ij dL/dA_ij + sum tB_il dL/dB_il + sum tgamma_i dL/dgamma_i
+ * in z, into gz (nvar doubles, the layout of z), and in y, into gy (ncon
+ * doubles, the layout of c) -- what the backward of ocp_eval_coef_grad needs.
+ * The defects are linear in theta = (A, B, gamma), so this is the
+ * coefficient part of J^T y and of c with theta replaced by t: gy holds the
+ * defects' theta part under t (zero on the boundary rows), and gz the part of
+ * grad_z L (sigma = 0) that the coefficients contribute (differentiable
+ * programming, named as future work in Sec. 8; the defects of Sec. 3, either
+ * scheme, any boundary option).  gz or gy may be NULL to skip that output,
+ * not both.  The call reads t from the caller's arrays and leaves the
+ * handle's coefficients and workspaces untouched; it may run concurrently
+ * with any other call on the handle.  Errors: OCP_ERR_ARG (null array, no
+ * output, quadrotor handle), OCP_ERR_HIP. */
+int ocp_eval_coef_adjoint(const ocp_problem *p, const double *z, const double *y, const double *tA,
+                          const double *tB, const double *tgamma, double *gz, double *gy, hipStream_t stream);
+
 /* Allocation-free ocp_eval_coef_grad, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same kernels, same arguments and bitwise the same

@@ -132,6 +132,7 @@ def lib():
         L.ocp_eval_coef_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ocp_eval_coef_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ocp_eval_coef_mixed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_eval_coef_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_batch_create.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.ocp_batch_destroy.argtypes = [vp]
         L.ocp_batch_destroy.restype = None
@@ -564,6 +565,31 @@ class Problem:
                                           ctypes.c_void_p(gg.data_ptr()), self._stream()),
                "ocp_eval_coef_mixed")
         return gA, gB, gg
+
+    def coef_adjoint(self, z, y, tA, tB, tgamma, want_z=True, want_y=True, out_z=None, out_y=None):
+        """The adjoint of coef_grad(z, y): for cotangents tA (n, n), tB (n, m)
+        and tgamma (n,) of its three outputs, the gradients of
+        tA . dL/dA + tB . dL/dB + tgamma . dL/dgamma in z (nvar doubles) and
+        in y (ncon doubles), as (gz, gy); an output not wanted is None.  The
+        handle's coefficients are neither read nor changed."""
+        torch = _torch()
+        n, m = self.n, self.m
+        if not (want_z or want_y):
+            raise ValueError("coef_adjoint: neither output is wanted")
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        ap = self._dev(tA, n * n, torch.float64, "tA")
+        bp = self._dev(tB, n * m, torch.float64, "tB") if m else None
+        gp = self._dev(tgamma, n, torch.float64, "tgamma")
+        gz = gy = None
+        zo = yo = None
+        if want_z:
+            gz, zo = self._out(out_z, self.sizes["nvar"], "gz")
+        if want_y:
+            gy, yo = self._out(out_y, self.sizes["ncon"], "gy")
+        _check(lib().ocp_eval_coef_adjoint(self._h, zp, yp, ap, bp, gp, zo, yo, self._stream()),
+               "ocp_eval_coef_adjoint")
+        return gz, gy
 
 
 class QuadrotorProblem(Problem):

@@ -18,8 +18,7 @@ coefficients theta = (A, B, gamma) (library call ocp_eval_coef_mixed)::
 The coefficient gradient dL/dtheta is differentiable too: L is affine in
 theta, so its derivative in theta is zero and its derivatives in z and y are
 the coefficient parts of grad_z L and of c under the cotangent coefficients
-(the library's grad_z L and c with the handle's coefficients swapped and
-restored).  So ``torch.autograd.gradgradcheck`` of L passes over all of
+(library call ocp_eval_coef_adjoint).  So ``torch.autograd.gradgradcheck`` of L passes over all of
 (z, y, A, B, gamma).  Third derivatives raise NotImplementedError.
 """
 from __future__ import annotations
@@ -101,12 +100,10 @@ class _Cons(torch.autograd.Function):
 class _CoefGrad(torch.autograd.Function):
     """dL/d(A, B, gamma) as a function of (z, y, A, B, gamma).  Its backward
     uses that L is affine in theta = (A, B, gamma): for cotangents tb,
-    tb . dL/dtheta = y^T (c(z; tb) - c(z; 0)), so the gradient in z is
-    grad_z L at sigma = 0 under the coefficients tb less the same under zero
-    coefficients (which leaves the coefficient part of J^T y), the gradient in
-    y is c(z; tb) - c(z; 0) (the coefficient part of the defects; boundary
-    rows cancel), and the gradient in theta is zero.  The handle's
-    coefficients are swapped for the four library calls and restored."""
+    tb . dL/dtheta = y^T (c(z; tb) - c(z; 0)), whose gradients in z and y
+    (the coefficient parts of J^T y and of c under tb) one library call
+    returns (ocp_eval_coef_adjoint, which reads tb from its arguments and
+    leaves the handle alone); the gradient in theta is zero."""
 
     @staticmethod
     def forward(ctx, z, y, A, B, gamma, prob):
@@ -123,19 +120,9 @@ class _CoefGrad(torch.autograd.Function):
             raise NotImplementedError("third derivatives of the Lagrangian are not provided")
         gz = gy = None
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
-            zd, yd = z.detach().contiguous(), y.detach().contiguous()
-            zero = [torch.zeros_like(t) for t in (A, B, gamma)]
-            parts = []
-            for coef in ((tA.detach(), tB.detach(), tg.detach()), zero):
-                prob.set_coefficients(*coef)
-                parts.append((prob.lag_grad(zd, yd, 0.0) if ctx.needs_input_grad[0] else None,
-                              prob.cons(zd) if ctx.needs_input_grad[1] else None))
-            prob.set_coefficients(A.detach(), B.detach(), gamma.detach())
-            (z1, y1), (z0, y0) = parts
-            if ctx.needs_input_grad[0]:
-                gz = z1.sub_(z0)
-            if ctx.needs_input_grad[1]:
-                gy = y1.sub_(y0)
+            gz, gy = prob.coef_adjoint(z.detach().contiguous(), y.detach().contiguous(),
+                                       *(t.detach().contiguous() for t in (tA, tB, tg)),
+                                       want_z=ctx.needs_input_grad[0], want_y=ctx.needs_input_grad[1])
         return gz, gy, None, None, None, None
 
 

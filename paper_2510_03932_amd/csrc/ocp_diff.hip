@@ -571,6 +571,141 @@ __global__ __launch_bounds__(kBlock) void coef_final_kernel(KP P, const double *
     else gg[i] = val;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the coefficient gradient: for cotangents t = (tA, tB, tg) of
+// (dL/dA, dL/dB, dL/dgamma), the gradients in z and in y of t . dL/dtheta.
+// The defects are linear in theta, so t . dL/dtheta = sum_ik y_ik D_ik, D
+// being the defects' theta part with theta := t:
+//   Ft_i(k) = sum_j tA_ij sin X_jk + sum_l tB_il U_lk + tg_i X_ik X_p(i)k,
+//   D_ik    = -al Ft_i(k) - be Ft_i(k+1)   ((al, be) = (hh, hh) or (h, 0)).
+// The y-gradient is D on the defect rows and 0 on the boundary rows; the
+// z-gradient is the coefficient part of J^T y with theta := t:
+//   at X_jk  -wF (cos X_jk (tA^T yt)_j + yt_j tg_j X_p(j)k + yt_q tg_q X_qk),
+//   at U_lk  -wF (tB^T yt)_l,
+// q = (j-1) mod n being the row whose bilinear partner is j.  Chunks of B
+// nodes close B-1 intervals, as in the defect kernel: lane k publishes
+// Ft(k) in LDS for lane k-1, and node k's z-entries are written by the chunk
+// in which it is not the overlap node.  Every workgroup copies t from the
+// caller's row-major arrays into zero-padded columns in LDS (the same region
+// later holds the exchange), so the call reads no coefficients of the handle.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(kBlock) void coef_adjoint_kernel(KP P, const double *__restrict__ z,
+                                                              const double *__restrict__ y,
+                                                              const double *__restrict__ tA,
+                                                              const double *__restrict__ tB,
+                                                              const double *__restrict__ tg,
+                                                              double *__restrict__ gz,
+                                                              double *__restrict__ gy)
+{
+    // columns: tA's n (of NB rows), then tB's m (kLd slots), then tg
+    constexpr int kCoef = (NB + kLd + 1) * NB, kExch = NB * kBlock;
+    __shared__ double lds[kCoef > kExch ? kCoef : kExch];
+    const double *cA = lds, *cB = lds + NB * NB, *cg = lds + (NB + kLd) * NB;
+    const int tid = threadIdx.x;
+    const int n = P.n, m = P.m;
+    const int64_t N = P.N, N1 = P.N1, NU = P.NU;
+    for (int e = tid; e < kCoef; e += kBlock) {
+        const int c = e / NB, i = e - c * NB;  // column c, row i
+        double v = 0.0;
+        if (i < n) {
+            if (c < NB) v = c < n ? tA[i * n + c] : 0.0;
+            else if (c < NB + kLd) v = c - NB < m ? tB[i * m + (c - NB)] : 0.0;
+            else v = tg[i];
+        }
+        lds[e] = v;
+    }
+    if (gy && blockIdx.x == 0 && tid < P.nb) gy[(int64_t)n * N + tid] = 0.0;  // boundary rows
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
+    const bool live = k <= N;
+    const bool euler = P.scheme != 0;
+    const double wF = euler ? P.h : P.hh;
+    double x[NB], Ft[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) x[i] = Ft[i] = 0.0;
+    if (live) {
+        double yt[NB];
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            yt[i] = 0.0;
+            if (i < n) {
+                x[i] = z[i * N1 + k];
+                const double *yi = y + i * N + k;
+                const double yr = k < N ? yi[0] : 0.0;
+                yt[i] = euler ? yr : (k >= 1 ? yi[-1] : 0.0) + yr;
+            }
+        }
+        if (gz && (tid < kBlock - 1 || k == N)) {
+            const double x_last = last_of<NB>(x, n), yt_last = last_of<NB>(yt, n);
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                if (j < n) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], cA[j * NB + i], s);
+                    const double xn = (j + 1 < n) ? x[(j + 1) % NB] : x[0];
+                    const int jm = (j == 0) ? n - 1 : j - 1;
+                    const double xm = (j == 0) ? x_last : x[(j + NB - 1) % NB];
+                    const double ym = (j == 0) ? yt_last : yt[(j + NB - 1) % NB];
+                    const double G = cos(x[j]) * s + yt[j] * cg[j] * xn + ym * cg[jm] * xm;
+                    gz[j * N1 + k] = -wF * G;
+                }
+            }
+            if (k < NU) {
+                for (int l = 0; l < m; l++) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NB; i++) s = __builtin_fma(yt[i], cB[l * NB + i], s);
+                    gz[n * N1 + l * NU + k] = -wF * s;
+                }
+            }
+        }
+        if (gy && (!euler || k < N)) {
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                if (j < n) {
+                    const double sx = sin(x[j]);
+#pragma unroll
+                    for (int i = 0; i < NB; i++) Ft[i] = __builtin_fma(cA[j * NB + i], sx, Ft[i]);
+                }
+            }
+            if (k < NU) {
+                const double *U = z + (int64_t)n * N1;
+                for (int l = 0; l < m; l++) {
+                    const double ul = U[l * NU + k];
+#pragma unroll
+                    for (int i = 0; i < NB; i++) Ft[i] = __builtin_fma(cB[l * NB + i], ul, Ft[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NB; i++) {
+                if (i < n) {
+                    const double xp = (i + 1 < n) ? x[(i + 1) % NB] : x[0];
+                    Ft[i] = __builtin_fma(cg[i] * x[i], xp, Ft[i]);
+                }
+            }
+        }
+    }
+    if (!gy) return;  // uniform: no barrier follows for any lane
+    __syncthreads();  // every read of the coefficient columns is done
+    if (!euler) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) lds[i * kBlock + tid] = Ft[i];
+    }
+    __syncthreads();
+    if (tid < kBlock - 1 && k < N) {
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            if (i < n) {
+                const double v = euler ? -P.h * Ft[i] : -P.hh * (Ft[i] + lds[i * kBlock + tid + 1]);
+                gy[i * N + k] = v;
+            }
+        }
+    }
+}
+
 int nb_of(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
 // A coefficient update in one launch: the row-major copies of A, B and gamma
@@ -740,6 +875,20 @@ int ocp_eval_coef_mixed(const ocp_problem *p, const double *z, const double *y, 
     if (!z || !y || !v || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_mixed: null array");
     return launch_coef_grad(p, z, y, v, gA, gB, ggamma, p->cpart, stream, "ocp_eval_coef_mixed");
+}
+
+int ocp_eval_coef_adjoint(const ocp_problem *p, const double *z, const double *y, const double *tA,
+                          const double *tB, const double *tgamma, double *gz, double *gy, hipStream_t stream)
+{
+    const char *fn = "ocp_eval_coef_adjoint";
+    clear_error();
+    if (int rc = check_handle(p, fn)) return rc;
+    if (int rc = check_coefficients(p, fn)) return rc;
+    if (!z || !y || !tA || !tgamma || (p->d.m > 0 && !tB)) return fail(OCP_ERR_ARG, std::string(fn) + ": null array");
+    if (!gz && !gy) return fail(OCP_ERR_ARG, std::string(fn) + ": no output (gz and gy are both NULL)");
+    OCP_DISPATCH_NB(p->d.n, coef_adjoint_kernel, dim3(blocks_for(p->d.N, kBlock - 1)), stream, p->kp, z, y, tA, tB,
+                    tgamma, gz, gy);
+    return check_launch(fn);
 }
 
 int ocp_eval_coef_grad_noalloc(const ocp_problem *p, const double *z, const double *y, double *gA,

@@ -455,6 +455,107 @@ def test_coef_mixed_rejects_quadrotor_and_null(ocp):
     prob.close()
 
 
+def _cotangents(n, m, seed, dev):
+    rng = np.random.default_rng(seed)
+    t = rng.normal(size=(n, n)), rng.normal(size=(n, m)), rng.normal(size=n)
+    return t, tuple(torch.from_numpy(a).to(dev) for a in t)
+
+
+def _check_adjoint(ocp, inst, scheme, bnd, seed, tag):
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    (tA, tB, tg), dt = _cotangents(inst.n, inst.m, seed, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    gz, gy = prob.coef_adjoint(z, y, *dt)
+    (oz, oy), (mz, my) = oracle.coef_adjoint_ex(inst, tA, tB, tg, scheme, bnd)
+    gz, gy = gz.cpu().numpy(), gy.cpu().numpy()
+    check_close(gz, oz, mz, what=f"adjoint in z {tag}")
+    check_close(gy, oy, my, what=f"adjoint in y {tag}")
+    return prob, z, y, dt, gz, gy
+
+
+ADJ_SHAPES = [(1000, 4, 2), (777, 5, 3), (1, 1, 0), (1, 1, 1), (2, 2, 1), (3, 3, 0), (255, 2, 0),
+              (510, 8, 4), (257, 16, 8), (513, 32, 32), (300, 9, 4), (389, 17, 15)]
+
+
+@pytest.mark.parametrize("scheme,bnd", [(0, 0), (0, 2), (1, 1), (1, 2)])
+@pytest.mark.parametrize("N,n,m", ADJ_SHAPES)
+def test_coef_adjoint_matches_oracle(ocp, N, n, m, scheme, bnd):
+    """Every register tiling (n up to 4, 8, 16, 32), one or several chunks
+    of 256 nodes with a ragged last one (N = 255 and 510 end exactly at a
+    chunk's last node), one state (X_i X_p(i) = X_i^2), no controls, either
+    scheme and boundary rows."""
+    tag = f"N={N} n={n} m={m} scheme={scheme} bnd={bnd}"
+    _say(f"[coef adjoint] {tag}")
+    inst = synth.make_instance(N, n, m, seed=31 + n, scheme=scheme, bnd=bnd)
+    prob, *_ = _check_adjoint(ocp, inst, scheme, bnd, 7 + N, tag)
+    prob.close()
+
+
+def test_coef_adjoint_differentiation_workload(ocp):
+    """At the 2e5-interval differentiation workload, every entry; a second
+    call gives the same bits; each output alone equals the joint call's."""
+    N, n, m = synth.DIFF
+    _say(f"[coef adjoint] N={N} n={n} m={m}")
+    inst = synth.make_instance(N, n, m, seed=0)
+    prob, z, y, dt, gz, gy = _check_adjoint(ocp, inst, 0, 0, 3, f"N={N}")
+    gz2, gy2 = (t.cpu().numpy() for t in prob.coef_adjoint(z, y, *dt))
+    assert np.array_equal(gz.view(np.int64), gz2.view(np.int64))
+    assert np.array_equal(gy.view(np.int64), gy2.view(np.int64))
+    only_z, none_y = prob.coef_adjoint(z, y, *dt, want_y=False)
+    none_z, only_y = prob.coef_adjoint(z, y, *dt, want_z=False)
+    assert none_y is None and none_z is None
+    assert np.array_equal(only_z.cpu().numpy().view(np.int64), gz.view(np.int64))
+    assert np.array_equal(only_y.cpu().numpy().view(np.int64), gy.view(np.int64))
+    prob.close()
+
+
+def test_coef_adjoint_leaves_the_handle_alone(ocp):
+    """The adjoint reads the cotangents from the caller's arrays: the
+    handle's own coefficients (hence every other evaluation) are the same
+    bits before and after, and a different cotangent gives a different
+    result (nothing is cached)."""
+    _say("[coef adjoint] handle untouched")
+    inst = synth.make_instance(300, 5, 2, seed=8, scheme=0, bnd=1)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    before = prob.lag_grad(z, y, 0.7).cpu().numpy()
+    _, dt = _cotangents(5, 2, 1, dev)
+    g1 = prob.coef_adjoint(z, y, *dt)[0].cpu().numpy()
+    g2 = prob.coef_adjoint(z, y, *(2.0 * t for t in dt))[0].cpu().numpy()
+    after = prob.lag_grad(z, y, 0.7).cpu().numpy()
+    assert np.array_equal(before.view(np.int64), after.view(np.int64))
+    check_close(g2, 2.0 * g1, 2.0 * np.abs(g1) + 1e-300, rel=1e-15, what="linear in t")
+    prob.close()
+
+
+def test_coef_adjoint_rejects_quadrotor_null_and_no_output(ocp):
+    q = synth.make_quadrotor(8, seed=0, bnd=1)
+    dev = torch.device("cuda", 0)
+    qp = ocp.QuadrotorProblem.from_instance(q, dev)
+    z, y = torch.from_numpy(q.z).to(dev), torch.from_numpy(q.y).to(dev)
+    t = torch.zeros(81, dtype=torch.float64, device=dev)
+    rc = ocp.lib().ocp_eval_coef_adjoint(qp._h, z.data_ptr(), y.data_ptr(), t.data_ptr(), t.data_ptr(),
+                                         t.data_ptr(), t.data_ptr(), None, None)
+    assert rc == ocp.OCP_ERR_ARG
+    qp.close()
+    inst = synth.make_instance(10, 2, 1, seed=1)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    out = torch.empty(len(inst.z), dtype=torch.float64, device=dev)
+    L = ocp.lib()
+    assert L.ocp_eval_coef_adjoint(prob._h, z.data_ptr(), y.data_ptr(), None, t.data_ptr(), t.data_ptr(),
+                                   out.data_ptr(), None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_eval_coef_adjoint(prob._h, z.data_ptr(), y.data_ptr(), t.data_ptr(), None, t.data_ptr(),
+                                   out.data_ptr(), None, None) == ocp.OCP_ERR_ARG
+    assert L.ocp_eval_coef_adjoint(prob._h, z.data_ptr(), y.data_ptr(), t.data_ptr(), t.data_ptr(),
+                                   t.data_ptr(), None, None, None) == ocp.OCP_ERR_ARG
+    with pytest.raises(ValueError):
+        prob.coef_adjoint(z, y, t[:4].view(2, 2), t[:2].view(2, 1), t[:2], want_z=False, want_y=False)
+    prob.close()
+
+
 def test_differentiation_workload_central_differences(ocp):
     """On the 2e5-interval workload, with the GPU's own Lagrangian:
     - central differences at step 1e-6 along sampled entries of z against
