@@ -605,6 +605,26 @@ __global__ __launch_bounds__(kBlock) void coef_adjoint_kernel(KP P, const double
     const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
     const int64_t N = P.N, N1 = P.N1, NU = P.NU;
+    const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
+    const bool live = k <= N;
+    const bool euler = P.scheme != 0;
+    const double wF = euler ? P.h : P.hh;
+    // The node's state and multiplier loads come first, at clamped indices
+    // (every lane issues them unconditionally; a lane past node N computes
+    // values it never stores), so that the staging of t below overlaps their
+    // latency.  (Loading the controls here too doubled the registers.)
+    const int64_t kc = live ? k : N;
+    const int64_t kr = kc < N ? kc : N - 1, kl = kc >= 1 ? kc - 1 : 0;
+    double x[NB], yt[NB], Ft[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        x[i] = yt[i] = Ft[i] = 0.0;
+        if (i < n) {
+            x[i] = z[i * N1 + kc];
+            const double yr = y[i * N + kr], yl = y[i * N + kl];
+            yt[i] = (kc < N ? yr : 0.0) + (euler || kc < 1 ? 0.0 : yl);
+        }
+    }
     for (int e = tid; e < kCoef; e += kBlock) {
         const int c = e / NB, i = e - c * NB;  // column c, row i
         double v = 0.0;
@@ -617,25 +637,7 @@ __global__ __launch_bounds__(kBlock) void coef_adjoint_kernel(KP P, const double
     }
     if (gy && blockIdx.x == 0 && tid < P.nb) gy[(int64_t)n * N + tid] = 0.0;  // boundary rows
     __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * (kBlock - 1) + tid;
-    const bool live = k <= N;
-    const bool euler = P.scheme != 0;
-    const double wF = euler ? P.h : P.hh;
-    double x[NB], Ft[NB];
-#pragma unroll
-    for (int i = 0; i < NB; i++) x[i] = Ft[i] = 0.0;
     if (live) {
-        double yt[NB];
-#pragma unroll
-        for (int i = 0; i < NB; i++) {
-            yt[i] = 0.0;
-            if (i < n) {
-                x[i] = z[i * N1 + k];
-                const double *yi = y + i * N + k;
-                const double yr = k < N ? yi[0] : 0.0;
-                yt[i] = euler ? yr : (k >= 1 ? yi[-1] : 0.0) + yr;
-            }
-        }
         if (gz && (tid < kBlock - 1 || k == N)) {
             const double x_last = last_of<NB>(x, n), yt_last = last_of<NB>(yt, n);
 #pragma unroll
