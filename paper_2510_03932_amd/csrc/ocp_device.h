@@ -257,21 +257,23 @@ __device__ __forceinline__ void hess_node(const KP &P, const double *__restrict_
 // ---------------------------------------------------------------------------
 // Dynamics at node k <= N: the node's states x[i] = X_ik and F_i(k) for every
 // i < n (NB >= n, entries beyond n are zero).  F_i sums j ascending, then l
-// ascending, then the bilinear term.  The states and the first NB controls
-// are loaded before any arithmetic (further controls, when m > NB, after).
+// ascending, then the bilinear term.  The states and the first MB controls
+// are loaded before any arithmetic (further controls, when m > MB, after);
+// a caller that knows m <= MB < NB saves the registers of NB - MB controls.
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, int MB = NB>
 __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__ z, int64_t k,
                                          double (&x)[NB], double (&F)[NB])
 {
+    static_assert(MB <= NB, "the control bound is at most the state bound");
     const int n = P.n, m = P.m;
     const int64_t N1 = P.N1;
     const double *U = z + (int64_t)n * N1;
-    double u[NB];
+    double u[MB];
 #pragma unroll
     for (int i = 0; i < NB; i++) {
         x[i] = (i < n) ? z[i * N1 + k] : 0.0;
-        u[i] = (i < m) ? U[(int64_t)i * P.NU + k] : 0.0;
+        if (i < MB) u[i] = (i < m) ? U[(int64_t)i * P.NU + k] : 0.0;
         F[i] = 0.0;
     }
 #pragma unroll
@@ -284,14 +286,14 @@ __device__ __forceinline__ void dyn_node(const KP &P, const double *__restrict__
         }
     }
 #pragma unroll
-    for (int l = 0; l < NB; l++) {
+    for (int l = 0; l < MB; l++) {
         if (l < m) {
             const double *b = P.BT + l * kLd;
 #pragma unroll
             for (int i = 0; i < NB; i++) F[i] = __builtin_fma(b[i], u[l], F[i]);
         }
     }
-    for (int l = NB; l < m; l++) {
+    for (int l = MB; l < m; l++) {
         const double ul = U[(int64_t)l * P.NU + k];
         const double *b = P.BT + l * kLd;
 #pragma unroll
