@@ -1,5 +1,5 @@
-"""GPU parity of the Lagrangian derivatives (L, grad_z L, H v, J v, dL/dtheta)
-against the CPU oracle, and of the autograd wrapper against finite differences
+"""GPU parity of the Lagrangian derivatives (L, grad_z L, H v, J v, dL/dtheta,
+its mixed derivative along v and its adjoint) against the CPU oracle, and of the autograd wrapper against finite differences
 (torch.autograd.gradcheck / gradgradcheck, and central differences at step
 1e-6 on the 2e5-interval differentiation workload)."""
 from __future__ import annotations
@@ -347,9 +347,9 @@ def test_coefficient_gradient_differentiated_again(ocp):
     """dL/dtheta as a function of (z, y): for cotangents tb, the gradient of
     tb . dL/dtheta is the coefficient part of grad_z L and of c under the
     coefficients tb, against the oracle's grad_z L and c evaluated with
-    coefficients tb and with zero coefficients (sigma = 0); the handle's
-    coefficients are the original ones afterwards; a third derivative
-    raises."""
+    coefficients tb and with zero coefficients (sigma = 0) and against the
+    oracle's adjoint; the handle's coefficients are the original ones
+    afterwards; a third derivative raises."""
     import dataclasses
     from paper_2510_03932_amd.autograd import lagrangian
     inst = synth.make_instance(600, 4, 2, seed=23, scheme=0, bnd=1)
@@ -367,6 +367,9 @@ def test_coefficient_gradient_differentiated_again(ocp):
     check_close(gz.cpu().numpy(), g1 - g0, m1 + m0, what="d/dz of tb . dL/dtheta")
     (c1, n1), (c0, n0) = (oracle.cons_ex(i, 0, 1) for i in (with_tb, zero))
     check_close(gy.cpu().numpy(), c1 - c0, n1 + n0, what="d/dy of tb . dL/dtheta")
+    (oz, oy), (mz, my) = oracle.coef_adjoint_ex(inst, tA, tB, tg, 0, 1)
+    check_close(gz.cpu().numpy(), oz, mz, what="d/dz against the oracle's adjoint")
+    check_close(gy.cpu().numpy(), oy, my, what="d/dy against the oracle's adjoint")
     # the handle holds the original coefficients again
     Lo, Lm = oracle.lagrangian_ex(inst, 0, 1, sigma=0.9)
     assert abs(prob.lagrangian(z.detach(), y.detach(), 0.9).item() - Lo) <= 1e-12 * Lm

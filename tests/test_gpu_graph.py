@@ -131,6 +131,8 @@ def _diff_outputs(prob, coef):
         for tag in ("cg", "cm", "cn"):
             o[tag] = (torch.full((n, n), float("nan"), **f64), torch.full((n, m), float("nan"), **f64),
                       torch.full((n,), float("nan"), **f64))
+        o["az"] = torch.full((s["nvar"],), float("nan"), **f64)
+        o["ay"] = torch.full((s["ncon"],), float("nan"), **f64)
     return o
 
 
@@ -143,6 +145,8 @@ def _diff_calls(prob, z, y, v, o, coef):
         prob.coef_grad(z, y, out=o["cg"])
         prob.coef_mixed(z, y, v, out=o["cm"])
         prob.coef_grad(z, y, noalloc=True, out=o["cn"])
+        # the adjoint, with the coefficient gradient just computed as cotangents
+        prob.coef_adjoint(z, y, *o["cg"], out_z=o["az"], out_y=o["ay"])
 
 
 def _flat(o):
@@ -159,9 +163,10 @@ def _flat(o):
 @pytest.mark.parametrize("model,scheme,bnd", [("synthetic", 0, 0), ("synthetic", 1, 2), ("quadrotor", 0, 1)])
 def test_graph_replays_equal_eager_differentiation(ocp, model, scheme, bnd):
     """The Lagrangian entry points (L, grad_z L, H v, J v and, for the
-    synthetic family, the coefficient gradient, its mixed derivative and the
-    allocation-free coefficient gradient) captured in one graph: each replay
-    at a new point equals the eager calls bit for bit."""
+    synthetic family, the coefficient gradient, its mixed derivative, the
+    allocation-free coefficient gradient and the adjoint fed by the first)
+    captured in one graph: each replay at a new point equals the eager calls
+    bit for bit."""
     _say(f"[graph] differentiation {model} scheme={scheme} bnd={bnd}")
     dev = torch.device("cuda", 0)
     coef = model == "synthetic"
