@@ -481,6 +481,7 @@ class Problem:
         Bp = self._dev(B, n * m, torch.float64, "B") if m else None
         gp = self._dev(gamma, n, torch.float64, "gamma")
         _check(lib().ocp_set_coefficients(self._h, Ap, Bp, gp, self._stream()), "ocp_set_coefficients")
+        self._coef_key = None  # an upload the autograd functions did not make
 
     def lagrangian(self, z, y, sigma=1.0, out=None):
         torch = _torch()

@@ -26,19 +26,27 @@ from __future__ import annotations
 import torch
 
 
-def _coefficients(prob, A, B, gamma):
-    """Push the coefficient tensors into the handle (one stream-ordered kernel
-    launch); a model without coefficient arrays (the quadrotor) takes
-    A = B = gamma = None.  Skipped inside _Lagrangian.backward, which uploads
-    once for the three Functions it applies.  (Keying a cache on the tensors'
-    identity and version is not safe: writes through ``.data``, as
+def _coefficients(prob, A, B, gamma, key=None):
+    """Make the handle hold the coefficient tensors (one stream-ordered kernel
+    launch) and return the key of the upload that put them there; a model
+    without coefficient arrays (the quadrotor) takes A = B = gamma = None.
+    Each upload gets a fresh key.  A backward passes the key its forward got,
+    and nothing is uploaded while that upload is still the handle's last one
+    (the values are then exactly the forward's); inside _Lagrangian.backward,
+    which uploads for the Functions it applies, nothing is uploaded either.
+    Problem.set_coefficients clears the key, so an upload made any other way
+    makes the next backward upload again.  (A cache keyed on the tensors'
+    identity and version would not be safe: writes through ``.data``, as
     torch.autograd.gradcheck makes them, change values without a version
     bump.)"""
     if A is None and B is None and gamma is None:
-        return
-    if getattr(prob, "_coef_uploaded", False):
-        return
+        return None
+    current = getattr(prob, "_coef_key", None)
+    if getattr(prob, "_coef_uploaded", False) or (key is not None and current is key):
+        return current
     prob.set_coefficients(A.detach(), B.detach(), gamma.detach())
+    prob._coef_key = key = object()
+    return key
 
 
 class _LagGrad(torch.autograd.Function):
@@ -48,7 +56,7 @@ class _LagGrad(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, z, y, A, B, gamma, sigma, prob):
-        _coefficients(prob, A, B, gamma)
+        ctx.coef_key = _coefficients(prob, A, B, gamma)
         ctx.save_for_backward(z, y, A, B, gamma)
         ctx.sigma, ctx.prob = sigma, prob
         return prob.lag_grad(z.detach().contiguous(), y.detach().contiguous(), sigma)
@@ -57,7 +65,7 @@ class _LagGrad(torch.autograd.Function):
     def backward(ctx, v):
         z, y, A, B, gamma = ctx.saved_tensors
         prob = ctx.prob
-        _coefficients(prob, A, B, gamma)
+        _coefficients(prob, A, B, gamma, ctx.coef_key)
         v = v.detach().contiguous()
         zd, yd = z.detach().contiguous(), y.detach().contiguous()
         gz = gy = gA = gB = gg = None
@@ -77,7 +85,7 @@ class _Cons(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, z, A, B, gamma, prob):
-        _coefficients(prob, A, B, gamma)
+        ctx.coef_key = _coefficients(prob, A, B, gamma)
         ctx.save_for_backward(z, A, B, gamma)
         ctx.prob = prob
         return prob.cons(z.detach().contiguous())
@@ -88,7 +96,7 @@ class _Cons(torch.autograd.Function):
         prob = ctx.prob
         if torch.is_grad_enabled() and (w.requires_grad or z.requires_grad):
             raise NotImplementedError("third derivatives of the defects are not provided")
-        _coefficients(prob, A, B, gamma)
+        _coefficients(prob, A, B, gamma, ctx.coef_key)
         zd, w = z.detach().contiguous(), w.detach().contiguous()
         gz = prob.lag_grad(zd, w, 0.0) if ctx.needs_input_grad[0] else None
         gA = gB = gg = None
@@ -129,7 +137,7 @@ class _CoefGrad(torch.autograd.Function):
 class _Lagrangian(torch.autograd.Function):
     @staticmethod
     def forward(ctx, z, y, A, B, gamma, sigma, prob):
-        _coefficients(prob, A, B, gamma)
+        ctx.coef_key = _coefficients(prob, A, B, gamma)
         ctx.save_for_backward(z, y, A, B, gamma)
         ctx.sigma, ctx.prob = sigma, prob
         return prob.lagrangian(z.detach().contiguous(), y.detach().contiguous(), sigma)[0]
@@ -139,9 +147,10 @@ class _Lagrangian(torch.autograd.Function):
         z, y, A, B, gamma = ctx.saved_tensors
         prob, sigma = ctx.prob, ctx.sigma
         gz = gy = gA = gB = gg = None
-        # one upload serves the three Functions below (nothing else runs on
+        # the forward's upload, if it is still the handle's last one, or one
+        # upload now, serves the three Functions below (nothing else runs on
         # the handle in between)
-        _coefficients(prob, A, B, gamma)
+        _coefficients(prob, A, B, gamma, ctx.coef_key)
         if not torch.is_grad_enabled():
             # a plain backward (no create_graph): the library calls directly,
             # without the nested Functions' bookkeeping

@@ -233,6 +233,43 @@ def _leaf_inputs(inst, dev, coef_grad=True):
     return (t(inst.z), t(inst.y), t(inst.A, coef_grad), t(inst.B, coef_grad), t(inst.gamma, coef_grad))
 
 
+def test_backward_uses_its_own_forwards_coefficients(ocp):
+    """The backward skips the coefficient upload only while its forward's
+    upload is the handle's last one.  Two graphs on one handle with different
+    coefficients, and an explicit upload between a forward and its backward:
+    every gradient equals, bit for bit, that of a forward + backward run on
+    its own (first and second order)."""
+    from paper_2510_03932_amd.autograd import lagrangian, lagrangian_grad
+    _say("[autograd] interleaved graphs on one handle")
+    inst = synth.make_instance(700, 5, 2, seed=41, scheme=0, bnd=1)
+    dev = torch.device("cuda", 0)
+    prob = ocp.Problem.from_instance(inst, dev)
+    first, second = _leaf_inputs(inst, dev), _leaf_inputs(inst, dev)
+    with torch.no_grad():
+        second[2].mul_(1.5)
+        second[3].add_(0.5)
+        second[4].mul_(-2.0)
+    grads = lambda L, x: torch.autograd.grad(L, x)
+    want = [grads(lagrangian(prob, *x, 0.8), x) for x in (first, second)]
+    L1 = lagrangian(prob, *first, 0.8)
+    L2 = lagrangian(prob, *second, 0.8)  # the handle now holds the second coefficients
+    got = [grads(L1, first), grads(L2, second)]
+    L1 = lagrangian(prob, *first, 0.8)
+    prob.set_coefficients(*(t.detach() for t in second[2:]))
+    got.append(grads(L1, first))
+    for g, w in zip(got, [want[0], want[1], want[0]]):
+        for a, b in zip(g, w):
+            assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+    # second order: H v through grad_z L after another graph's forward
+    v = torch.from_numpy(np.random.default_rng(3).normal(size=len(inst.z))).to(dev)
+    hv_want = torch.autograd.grad(lagrangian_grad(prob, *first, 0.8), first[0], v)[0]
+    gz = lagrangian_grad(prob, *first, 0.8)
+    lagrangian(prob, *second, 0.8)
+    hv_got = torch.autograd.grad(gz, first[0], v)[0]
+    assert torch.equal(hv_got.view(torch.int64), hv_want.view(torch.int64))
+    prob.close()
+
+
 def test_autograd_backward_matches_oracle(ocp):
     from paper_2510_03932_amd.autograd import lagrangian
     inst = synth.make_instance(2000, 6, 3, seed=6)
