@@ -89,6 +89,29 @@ def _run(ocp, prob, pattern, points, fused):
     del g
 
 
+def test_calls_go_to_the_current_stream(ocp):
+    """The binding hands every call torch's current stream: its stream query
+    gives the same handle as torch's public one on the default stream and
+    inside a side stream's context, and a call issued there is ordered on that
+    stream (its result is complete after the stream alone synchronizes)."""
+    dev = torch.device("cuda", 0)
+    inst = synth.make_instance(5000, 6, 3, seed=3)
+    prob = ocp.Problem.from_instance(inst, dev)
+    handle = lambda: prob._stream().value or 0  # the null stream's handle is 0 (None as a c_void_p)
+    assert handle() == torch.cuda.current_stream(dev).cuda_stream
+    z = _t(inst.z)
+    want = prob.cons(z)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        assert handle() == side.cuda_stream != torch.cuda.default_stream(dev).cuda_stream
+        got = prob.cons(z)
+    side.synchronize()
+    assert torch.equal(got.view(torch.int64), want.view(torch.int64))
+    prob.close()
+
+
 @pytest.mark.parametrize("N,n,m,scheme,bnd", [(3000, 6, 3, 0, 0), (1001, 16, 8, 0, 1), (777, 5, 2, 1, 2)])
 def test_graph_replays_equal_eager_synthetic(ocp, N, n, m, scheme, bnd):
     _say(f"[graph] synthetic N={N} n={n} m={m} scheme={scheme} bnd={bnd}")
