@@ -381,6 +381,24 @@ int ocp_eval_coef_mixed(const ocp_problem *p, const double *z, const double *y, 
 int ocp_eval_coef_adjoint(const ocp_problem *p, const double *z, const double *y, const double *tA,
                           const double *tB, const double *tgamma, double *gz, double *gy, hipStream_t stream);
 
+/* One backward pass of L(z, y) = sigma f + y^T c, what a reverse-mode
+ * wrapper needs from one call (differentiable programming, named as future
+ * work in Sec. 8): with gL the incoming gradient (one device double),
+ * gz = gL grad_z L (nvar doubles), gy = gL c(z) (ncon doubles, the gradient
+ * in y) and gA, gB, ggamma = gL dL/d(A, B, gamma) (the layouts of
+ * ocp_eval_coef_grad).  The same kernels as ocp_eval_lag_grad,
+ * ocp_eval_cons and ocp_eval_coef_grad, then one kernel that multiplies
+ * every output by gL, so each value is bit for bit that call's value times
+ * gL.  Any output may be NULL to skip it, not all; gA, gB and ggamma go
+ * together (gB NULL when m = 0), use the coefficient-gradient workspace as
+ * ocp_eval_coef_grad does, and are rejected on a quadrotor handle.
+ * Errors: OCP_ERR_ARG (null input, no output, incomplete coefficient
+ * outputs, quadrotor handle with coefficient outputs, non-finite sigma),
+ * OCP_ERR_HIP. */
+int ocp_eval_lagrangian_backward(const ocp_problem *p, const double *z, const double *y, double sigma,
+                                 const double *gL, double *gz, double *gy, double *gA, double *gB,
+                                 double *ggamma, hipStream_t stream);
+
 /* Allocation-free ocp_eval_coef_grad, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same kernels, same arguments and bitwise the same

@@ -133,6 +133,7 @@ def lib():
         L.ocp_eval_coef_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ocp_eval_coef_mixed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_eval_coef_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ocp_eval_lagrangian_backward.argtypes = [vp, vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]
         L.ocp_batch_create.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.ocp_batch_destroy.argtypes = [vp]
         L.ocp_batch_destroy.restype = None
@@ -578,6 +579,33 @@ class Problem:
                                           ctypes.c_void_p(gg.data_ptr()), self._stream()),
                "ocp_eval_coef_mixed")
         return gA, gB, gg
+
+    def lagrangian_backward(self, z, y, sigma, gL, want_z=True, want_y=True, want_coef=False):
+        """One backward pass of L in one library call: (gz, gy, coef) =
+        gL times (grad_z L, c(z), (dL/dA, dL/dB, dL/dgamma)), gL being a
+        one-element float64 device tensor (the incoming gradient); an output
+        not wanted is None."""
+        torch = _torch()
+        n, m = self.n, self.m
+        if not (want_z or want_y or want_coef):
+            raise ValueError("lagrangian_backward: no output is wanted")
+        zp = self._dev(z, self.sizes["nvar"], torch.float64, "z")
+        yp = self._dev(y, self.sizes["ncon"], torch.float64, "y")
+        gp = self._dev(gL, 1, torch.float64, "gL")
+        gz = gy = coef = None
+        zo = yo = ap = bp = cp = None
+        if want_z:
+            gz, zo = self._out(None, self.sizes["nvar"], "gz")
+        if want_y:
+            gy, yo = self._out(None, self.sizes["ncon"], "gy")
+        if want_coef:
+            f64 = dict(dtype=torch.float64, device=self.device)
+            coef = (torch.empty(n, n, **f64), torch.empty(n, m, **f64), torch.empty(n, **f64))
+            ap, cp = ctypes.c_void_p(coef[0].data_ptr()), ctypes.c_void_p(coef[2].data_ptr())
+            bp = ctypes.c_void_p(coef[1].data_ptr()) if m else None
+        _check(lib().ocp_eval_lagrangian_backward(self._h, zp, yp, float(sigma), gp, zo, yo, ap, bp, cp,
+                                                  self._stream()), "ocp_eval_lagrangian_backward")
+        return gz, gy, coef
 
     def coef_adjoint(self, z, y, tA, tB, tgamma, want_z=True, want_y=True, out_z=None, out_y=None):
         """The adjoint of coef_grad(z, y): for cotangents tA (n, n), tB (n, m)

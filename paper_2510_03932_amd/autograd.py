@@ -152,19 +152,16 @@ class _Lagrangian(torch.autograd.Function):
         # the handle in between)
         _coefficients(prob, A, B, gamma, ctx.coef_key)
         if not torch.is_grad_enabled():
-            # a plain backward (no create_graph): the library calls directly,
-            # without the nested Functions' bookkeeping
-            zd, yd = z.detach().contiguous(), y.detach().contiguous()
-            if ctx.needs_input_grad[0]:
-                gz = prob.lag_grad(zd, yd, sigma)
-            if ctx.needs_input_grad[1]:
-                gy = prob.cons(zd)
-            if any(ctx.needs_input_grad[2:5]):
-                gA, gB, gg = prob.coef_grad(zd, yd)
-            # every piece times the incoming gradient in one multi-tensor launch
-            outs = [t for t in (gz, gy, gA, gB, gg) if t is not None]
-            if outs:
-                torch._foreach_mul_(outs, gL)
+            # a plain backward (no create_graph): one library call computes
+            # every piece and scales it by the incoming gradient on the device
+            want_z, want_y = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            want_coef = any(ctx.needs_input_grad[2:5])
+            if not (want_z or want_y or want_coef):
+                return gz, gy, gA, gB, gg, None, None
+            gz, gy, coef = prob.lagrangian_backward(z.detach().contiguous(), y.detach().contiguous(), sigma,
+                                                    gL.detach().contiguous(), want_z, want_y, want_coef)
+            if coef is not None:
+                gA, gB, gg = coef
             return gz, gy, gA, gB, gg, None, None
         prob._coef_uploaded = True
         try:

@@ -708,6 +708,33 @@ __global__ __launch_bounds__(kBlock) void coef_adjoint_kernel(KP P, const double
     }
 }
 
+// Up to five device arrays scaled in place by one device double (the
+// incoming gradient of a backward pass), in one launch over their
+// concatenation; end[j] is the cumulative length through array j.
+struct ScaleSegs {
+    double *p[5];
+    int64_t end[5];
+    int count;
+};
+
+__global__ __launch_bounds__(kBlock) void scale_kernel(ScaleSegs s, const double *__restrict__ g)
+{
+    const int64_t total = s.end[s.count - 1];
+    const double f = *g;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        double *dst = s.p[0];
+        int64_t off = i;
+#pragma unroll
+        for (int j = 1; j < 5; j++) {
+            if (j < s.count && i >= s.end[j - 1]) {
+                dst = s.p[j];
+                off = i - s.end[j - 1];
+            }
+        }
+        dst[off] *= f;
+    }
+}
+
 int nb_of(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
 // A coefficient update in one launch: the row-major copies of A, B and gamma
@@ -877,6 +904,51 @@ int ocp_eval_coef_mixed(const ocp_problem *p, const double *z, const double *y, 
     if (!z || !y || !v || !gA || !ggamma || (p->d.m > 0 && !gB))
         return fail(OCP_ERR_ARG, "ocp_eval_coef_mixed: null array");
     return launch_coef_grad(p, z, y, v, gA, gB, ggamma, p->cpart, stream, "ocp_eval_coef_mixed");
+}
+
+int ocp_eval_lagrangian_backward(const ocp_problem *p, const double *z, const double *y, double sigma,
+                                 const double *gL, double *gz, double *gy, double *gA, double *gB, double *ggamma,
+                                 hipStream_t stream)
+{
+    const char *fn = "ocp_eval_lagrangian_backward";
+    clear_error();
+    if (int rc = check_handle(p, fn)) return rc;
+    if (!z || !y || !gL) return fail(OCP_ERR_ARG, std::string(fn) + ": null array");
+    if (!std::isfinite(sigma)) return fail(OCP_ERR_ARG, std::string(fn) + ": sigma is not finite");
+    const bool coef = gA || gB || ggamma;
+    if (coef) {
+        if (int rc = check_coefficients(p, fn)) return rc;
+        if (!gA || !ggamma || (p->d.m > 0 && !gB))
+            return fail(OCP_ERR_ARG, std::string(fn) + ": gA and ggamma (and gB when m > 0) go together");
+    }
+    if (!gz && !gy && !coef) return fail(OCP_ERR_ARG, std::string(fn) + ": no output");
+    // the same kernels as the three separate calls, then one scale
+    if (gz)
+        if (int rc = ocp_eval_lag_grad(p, z, y, sigma, gz, stream)) return rc;
+    if (gy)
+        if (int rc = ocp_eval_cons(p, z, gy, stream)) return rc;
+    if (coef)
+        if (int rc = ocp_eval_coef_grad(p, z, y, gA, gB, ggamma, stream)) return rc;
+    ScaleSegs segs{};
+    int64_t total = 0;
+    auto add = [&](double *ptr, int64_t len) {
+        if (!ptr || len <= 0) return;
+        total += len;
+        segs.p[segs.count] = ptr;
+        segs.end[segs.count++] = total;
+    };
+    const int64_t n = p->d.n, m = p->d.m;
+    add(gz, p->d.nvar);
+    add(gy, p->d.ncon);
+    if (coef) {
+        add(gA, n * n);
+        add(gB, n * m);
+        add(ggamma, n);
+    }
+    if (segs.count == 0) return OCP_OK;
+    const unsigned grid = std::min<unsigned>(blocks_for(total, kBlock), 4096u);
+    hipLaunchKernelGGL(scale_kernel, dim3(grid), dim3(kBlock), 0, stream, segs, gL);
+    return check_launch(fn);
 }
 
 int ocp_eval_coef_adjoint(const ocp_problem *p, const double *z, const double *y, const double *tA,

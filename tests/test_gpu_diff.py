@@ -233,6 +233,52 @@ def _leaf_inputs(inst, dev, coef_grad=True):
     return (t(inst.z), t(inst.y), t(inst.A, coef_grad), t(inst.B, coef_grad), t(inst.gamma, coef_grad))
 
 
+@pytest.mark.parametrize("model,scheme,bnd", [("synthetic", 0, 0), ("synthetic", 1, 2), ("synthetic", 0, 1),
+                                              ("quadrotor", 0, 1)])
+def test_lagrangian_backward_equals_separate_calls(ocp, model, scheme, bnd):
+    """ocp_eval_lagrangian_backward: every output is bit for bit the
+    separate call's value times the incoming gradient, for every subset of
+    outputs; and the calls it rejects."""
+    _say(f"[lagrangian backward] {model} scheme={scheme} bnd={bnd}")
+    dev = torch.device("cuda", 0)
+    coef = model == "synthetic"
+    if coef:
+        inst = synth.make_instance(3000, 6, 3, seed=51, scheme=scheme, bnd=bnd)
+        prob = ocp.Problem.from_instance(inst, dev)
+    else:
+        inst = synth.make_quadrotor(2000, seed=51, bnd=bnd)
+        prob = ocp.QuadrotorProblem.from_instance(inst, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    gL = torch.tensor(0.37, dtype=torch.float64, device=dev)
+    parts = {"z": prob.lag_grad(z, y, 0.8) * gL, "y": prob.cons(z) * gL}
+    if coef:
+        parts["coef"] = tuple(t * gL for t in prob.coef_grad(z, y))
+    same = lambda a, b: torch.equal(a.reshape(-1).view(torch.int64), b.reshape(-1).view(torch.int64))
+    for want in ((True, True, coef), (True, False, False), (False, True, False), (False, False, coef)):
+        if not any(want):
+            continue
+        gz, gy, gc = prob.lagrangian_backward(z, y, 0.8, gL, *want)
+        assert (gz is not None, gy is not None, gc is not None) == want
+        if want[0]:
+            assert same(gz, parts["z"])
+        if want[1]:
+            assert same(gy, parts["y"])
+        if want[2]:
+            assert all(same(a, b) for a, b in zip(gc, parts["coef"]))
+    L = ocp.lib()
+    p = lambda t: t.data_ptr()
+    out = torch.empty(len(inst.z), dtype=torch.float64, device=dev)
+    assert L.ocp_eval_lagrangian_backward(prob._h, p(z), p(y), 0.8, p(gL), None, None, None, None, None,
+                                          None) == ocp.OCP_ERR_ARG  # no output
+    assert L.ocp_eval_lagrangian_backward(prob._h, p(z), p(y), 0.8, None, p(out), None, None, None, None,
+                                          None) == ocp.OCP_ERR_ARG  # no incoming gradient
+    assert L.ocp_eval_lagrangian_backward(prob._h, p(z), p(y), 0.8, p(gL), None, None, p(out), None, None,
+                                          None) == ocp.OCP_ERR_ARG  # incomplete (or, quadrotor, any) coefficients
+    with pytest.raises(ValueError):
+        prob.lagrangian_backward(z, y, 0.8, gL, False, False, False)
+    prob.close()
+
+
 def test_backward_uses_its_own_forwards_coefficients(ocp):
     """The backward skips the coefficient upload only while its forward's
     upload is the handle's last one.  Two graphs on one handle with different
