@@ -91,13 +91,13 @@ __global__ __launch_bounds__(kBlock) void cons_kernel(KP P, const double *__rest
 // Forward-Euler defects: one lane per interval k < N,
 //   c_ik = (X_{i,k+1} - X_ik) - h F_i(k)  (paper Sec. 3).
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, int MB>
 __global__ __launch_bounds__(kBlock) void cons_euler_kernel(KP P, const double *__restrict__ z,
                                                             double *__restrict__ c)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= P.N) return;
-    cons_euler_interval<NB>(P, z, c, k);
+    cons_euler_interval<NB, MB>(P, z, c, k);
 }
 
 // Boundary rows after the n N defect rows: row b holds X_{b mod n} at node 0
@@ -396,6 +396,14 @@ void launch_cons_trap(const KP &P, unsigned g, const double *z, double *c, hipSt
     else hipLaunchKernelGGL((cons_kernel<NB, NB>), dim3(g), dim3(kBlock), 0, stream, P, z, c);
 }
 
+// The forward-Euler defect kernel, with the same control bound.
+template <int NB>
+void launch_cons_euler(const KP &P, unsigned g, const double *z, double *c, hipStream_t stream)
+{
+    if (P.m <= NB / 2) hipLaunchKernelGGL((cons_euler_kernel<NB, NB / 2>), dim3(g), dim3(kBlock), 0, stream, P, z, c);
+    else hipLaunchKernelGGL((cons_euler_kernel<NB, NB>), dim3(g), dim3(kBlock), 0, stream, P, z, c);
+}
+
 hipError_t launch_cons(const KP &P, const double *z, double *c, hipStream_t stream)
 {
     const int n = P.n;
@@ -407,10 +415,10 @@ hipError_t launch_cons(const KP &P, const double *z, double *c, hipStream_t stre
         else launch_cons_trap<32>(P, g, z, c, stream);
     } else {
         const unsigned g = blocks_for(P.N, kBlock);
-        if (n <= 4) hipLaunchKernelGGL(cons_euler_kernel<4>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
-        else if (n <= 8) hipLaunchKernelGGL(cons_euler_kernel<8>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
-        else if (n <= 16) hipLaunchKernelGGL(cons_euler_kernel<16>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
-        else hipLaunchKernelGGL(cons_euler_kernel<32>, dim3(g), dim3(kBlock), 0, stream, P, z, c);
+        if (n <= 4) launch_cons_euler<4>(P, g, z, c, stream);
+        else if (n <= 8) launch_cons_euler<8>(P, g, z, c, stream);
+        else if (n <= 16) launch_cons_euler<16>(P, g, z, c, stream);
+        else launch_cons_euler<32>(P, g, z, c, stream);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -49,17 +49,30 @@ __device__ __forceinline__ void cons_wave(const KP &P, const double *__restrict_
 }
 
 // Forward-Euler defects of interval k < N: c_ik = (X_{i,k+1} - X_ik) - h F_i(k).
-template <int NB>
+// Up to NB = 16 the next node's states are loaded with this node's, before
+// any arithmetic; at NB = 32 those registers would leave one wavefront per
+// SIMD, so they are loaded at the stores.  (MB: the controls' register
+// bound, as in dyn_node.)
+template <int NB, int MB = NB>
 __device__ __forceinline__ void cons_euler_interval(const KP &P, const double *__restrict__ z,
                                                     double *__restrict__ c, int64_t k)
 {
+    constexpr bool kEarly = NB <= 16;
     const int n = P.n;
     const int64_t N = P.N, N1 = P.N1;
-    double x[NB], F[NB];
-    dyn_node<NB>(P, z, k, x, F);
+    double xn[kEarly ? NB : 1], x[NB], F[NB];
+    if constexpr (kEarly) {
 #pragma unroll
-    for (int i = 0; i < NB; i++)
-        if (i < n) st_nt(c + i * N + k, __builtin_fma(-P.h, F[i], z[i * N1 + k + 1] - x[i]));
+        for (int i = 0; i < NB; i++) xn[i] = (i < n) ? z[i * N1 + k + 1] : 0.0;
+    }
+    dyn_node<NB, MB>(P, z, k, x, F);
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        if (i < n) {
+            const double next = kEarly ? xn[kEarly ? i : 0] : z[i * N1 + k + 1];
+            st_nt(c + i * N + k, __builtin_fma(-P.h, F[i], next - x[i]));
+        }
+    }
 }
 
 // Boundary rows b < nb after the n N defect rows: row b is X_{b mod n} at
