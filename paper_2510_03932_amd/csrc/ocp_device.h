@@ -407,6 +407,19 @@ __device__ __forceinline__ void hess_node_euler(const KP &P, const double *__res
             if (k < P.N) yt[i] = y[i * N + k];
         }
     }
+    // the control and bilinear slots (no sines) are stored first, as in
+    // hess_node, then the diagonals
+    if (k < P.NU) {
+        const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
+        for (int l = 0; l < m; l++) st_out<NT>(hv + ub + (int64_t)l * P.NU, 2.0 * sigma * w * P.r[l]);
+    }
+    if (n >= 3) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < n) st_out<NT>(hv + (n + i) * N1 + k, -h * yt[i] * P.gam[i]);
+    } else if (n == 2) {
+        st_out<NT>(hv + 2 * N1 + k, -h * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
+    }
 #pragma unroll
     for (int j = 0; j < NB; j++) {
         if (j < n) {
@@ -419,17 +432,6 @@ __device__ __forceinline__ void hess_node_euler(const KP &P, const double *__res
             if (n == 1) v -= 2.0 * h * yt[0] * P.gam[0];
             st_out<NT>(hv + j * N1 + k, v);
         }
-    }
-    if (n >= 3) {
-#pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < n) st_out<NT>(hv + (n + i) * N1 + k, -h * yt[i] * P.gam[i]);
-    } else if (n == 2) {
-        st_out<NT>(hv + 2 * N1 + k, -h * (yt[0] * P.gam[0] + yt[1] * P.gam[1]));
-    }
-    if (k < P.NU) {
-        const int64_t ub = (int64_t)(n + P.npair) * N1 + k;
-        for (int l = 0; l < m; l++) st_out<NT>(hv + ub + (int64_t)l * P.NU, 2.0 * sigma * w * P.r[l]);
     }
 }
 
