@@ -616,6 +616,35 @@ def test_coef_adjoint_leaves_the_handle_alone(ocp):
     prob.close()
 
 
+def test_coef_adjoint_overlaps_coefficient_uploads(ocp):
+    """The adjoint reads no coefficient of the handle, so it may overlap any
+    other call on it: adjoints issued on one stream while another stream
+    keeps uploading different coefficients into the same handle equal, bit
+    for bit, the adjoint computed alone."""
+    _say("[coef adjoint] overlapping uploads on another stream")
+    dev = torch.device("cuda", 0)
+    inst = synth.make_instance(20_000, 6, 3, seed=12)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y = torch.from_numpy(inst.z).to(dev), torch.from_numpy(inst.y).to(dev)
+    _, dt = _cotangents(6, 3, 9, dev)
+    want = prob.coef_adjoint(z, y, *dt)
+    coefs = [tuple(torch.from_numpy(np.array(a) * s).to(dev) for a in (inst.A, inst.B, inst.gamma))
+             for s in (1.0, -3.0)]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(dev), torch.cuda.Stream(dev)  # default priority
+    got = []
+    for r in range(20):
+        with torch.cuda.stream(s2):
+            prob.set_coefficients(*coefs[r % 2])
+        with torch.cuda.stream(s1):
+            got.append(prob.coef_adjoint(z, y, *dt))
+    torch.cuda.synchronize()
+    for gz, gy in got:
+        assert torch.equal(gz.view(torch.int64), want[0].view(torch.int64))
+        assert torch.equal(gy.view(torch.int64), want[1].view(torch.int64))
+    prob.close()
+
+
 def test_coef_adjoint_rejects_quadrotor_null_and_no_output(ocp):
     q = synth.make_quadrotor(8, seed=0, bnd=1)
     dev = torch.device("cuda", 0)
