@@ -56,9 +56,13 @@
  * synchronization.  No C++ exception crosses this interface.
  *
  * Reentrancy: evaluations on one handle may run concurrently on different
- * streams, except ocp_eval_obj, which uses the handle's workspace (concurrent
- * ocp_eval_obj calls on one handle race).  Create and destroy are not
- * thread-safe for the same handle.
+ * streams, except calls that share one of the handle's two workspaces:
+ * ocp_eval_obj and ocp_eval_lagrangian (the reduction workspace), and
+ * ocp_eval_coef_grad, ocp_eval_coef_mixed and ocp_eval_lagrangian_backward
+ * with coefficient outputs (the coefficient-gradient workspace); two
+ * overlapping calls on one workspace race.  ocp_set_coefficients changes what
+ * the other calls read, so the caller orders it against them.  Create and
+ * destroy are not thread-safe for the same handle.
  */
 #ifndef OCP_EVAL_H
 #define OCP_EVAL_H
