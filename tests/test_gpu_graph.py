@@ -112,6 +112,36 @@ def test_calls_go_to_the_current_stream(ocp):
     prob.close()
 
 
+def test_evaluations_on_one_handle_overlap(ocp):
+    """Evaluations that use no handle workspace may run concurrently on
+    different streams: the Jacobian and the defects on one stream,
+    overlapping the Hessian, grad_z L, H v and J v on another, give the bits
+    of the same calls run one after another."""
+    _say("[streams] overlapping evaluations on one handle")
+    dev = torch.device("cuda", 0)
+    inst = synth.make_instance(50_000, 8, 4, seed=21, scheme=0, bnd=1)
+    prob = ocp.Problem.from_instance(inst, dev)
+    z, y = _t(inst.z), _t(inst.y)
+    v = _t(np.random.default_rng(2).normal(size=prob.sizes["nvar"]))
+    first = lambda: (prob.jac(z), prob.cons(z))
+    second = lambda: (prob.hess(z, y, 0.6), prob.lag_grad(z, y, 0.6), prob.hvp(z, y, v, 0.6), prob.jvp(z, v))
+    want = first() + second()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(dev), torch.cuda.Stream(dev)  # default priority
+    got = []
+    for _ in range(5):
+        with torch.cuda.stream(s1):
+            a = first()
+        with torch.cuda.stream(s2):
+            b = second()
+        got.append(a + b)
+    torch.cuda.synchronize()
+    for outs in got:
+        for g, w in zip(outs, want):
+            assert torch.equal(g.view(torch.int64), w.view(torch.int64))
+    prob.close()
+
+
 @pytest.mark.parametrize("N,n,m,scheme,bnd", [(3000, 6, 3, 0, 0), (1001, 16, 8, 0, 1), (777, 5, 2, 1, 2)])
 def test_graph_replays_equal_eager_synthetic(ocp, N, n, m, scheme, bnd):
     _say(f"[graph] synthetic N={N} n={n} m={m} scheme={scheme} bnd={bnd}")
